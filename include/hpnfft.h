@@ -1,0 +1,195 @@
+/*
+ * hpnfft — nonequispaced fast Fourier transform on AMD MI355X (gfx950).
+ *
+ * C-ABI of the library.  Plain pointers and sizes only; nothing throws across
+ * this boundary.  Every call returns HPNFFT_OK (0) or a negative status code.
+ *
+ * What is computed (Yang & Wang, arXiv 2001.01583, Section 1):
+ *   frequency box  I_N = { k in Z^d : -N_t/2 <= k_t < N_t/2 },
+ *   points x_j in [-1/2, 1/2)^d, j = 0 .. M-1,
+ *   adjoint  (the paper's NDFT, Eq. (5)):     fhat(k) = sum_j f_j e^{-2 pi i k.x_j}
+ *   forward  (the paper's "inverse", Eq. (6)): f_j = sum_{k in I_N} fhat(k) e^{+2 pi i k.x_j}
+ * Eq. (6) is the conjugate transpose A^H of the matrix A of Eq. (5), not an
+ * inverse (Section 1, the matrix form).  Both are evaluated approximately by
+ * the gridding scheme of Section 2: window spreading onto an oversampled grid
+ * of n_t = sigma * N_t cells, an FFT, and a division by the window's Fourier
+ * coefficients restricted to I_N ("scaling"); the transpose runs the same
+ * steps in reverse with interpolation in place of spreading.
+ *
+ * Layouts (all device memory, owned by the caller):
+ *   x      M x d float64 (or float32 for *_f32), row-major, each in [-1/2, 1/2)
+ *   f      M complex, interleaved (re, im); double for HPNFFT_F64 plans,
+ *          float for HPNFFT_F32 plans
+ *   fhat   prod(N) complex, C order (last dimension fastest), frequency k_t
+ *          stored at index k_t + N_t/2
+ * Streams: all transform calls are asynchronous on the plan's HIP stream.
+ * The library never allocates device memory: the caller provides one
+ * workspace buffer of hpnfft_workspace_size() bytes.
+ */
+#ifndef HPNFFT_H
+#define HPNFFT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+#define HPNFFT_OK        0
+#define HPNFFT_EINVAL   (-1)  /* invalid argument (sizes, null pointer, unsupported) */
+#define HPNFFT_EDOMAIN  (-2)  /* a point lies outside [-1/2,1/2)^d or is not finite */
+#define HPNFFT_ENOMEM   (-3)  /* host allocation failed or workspace too small       */
+#define HPNFFT_EHIP     (-4)  /* a HIP runtime call failed                           */
+#define HPNFFT_ESTATE   (-5)  /* call out of order (e.g. transform before set_points)*/
+
+/* ---- window (Section 2: a window well localised in space and frequency) */
+#define HPNFFT_KAISER_BESSEL 0
+
+/* ---- arithmetic precision of the transform -------------------------- */
+#define HPNFFT_F64 0          /* complex128 values, FP64 grid, FFT and sums     */
+#define HPNFFT_F32 1          /* complex64 values, FP32 grid, FFT and sums      */
+
+/* ---- plan flags ------------------------------------------------------ */
+#define HPNFFT_WITH_GRADIENT 1u  /* also tabulate window derivatives at set_points,
+                                    enabling hpnfft_adjoint_backward            */
+
+typedef struct hpnfft_plan_s *hpnfft_plan;
+typedef struct hpnfft_plan_s *hpnfft_batch;   /* a batch is a plan over B transforms */
+
+/* Human-readable text for a status code.  Never NULL. */
+const char *hpnfft_strerror(int status);
+
+/* Create a plan for one transform (Section 1 defines d, N, M; Section 4 uses
+ * sigma = 2 and the cut-off m).
+ *   d          must be 3
+ *   N[d]       bandwidth, each N_t even and >= 2 (Section 1)
+ *   M          number of points, >= 1
+ *   sigma      oversampling factor; n_t = sigma * N_t must be an even integer
+ *              of the form 2^a 3^b with 2m <= n_t <= 1024
+ *   m          window cut-off: 2m grid cells per dimension, 1 <= m <= 8
+ *   window     HPNFFT_KAISER_BESSEL
+ *   precision  HPNFFT_F64 or HPNFFT_F32
+ *   flags      0 or HPNFFT_WITH_GRADIENT
+ * The plan starts without a workspace and without points.
+ * Errors: EINVAL on any invalid argument, ENOMEM. */
+int hpnfft_plan_create(hpnfft_plan *out, int d, const int64_t *N, int64_t M,
+                       double sigma, int m, int window, int precision,
+                       unsigned flags);
+
+/* Destroy a plan.  Does not free the caller's workspace.  NULL is a no-op. */
+int hpnfft_plan_destroy(hpnfft_plan plan);
+
+/* HIP stream (a hipStream_t cast to void*) for all later calls; NULL is the
+ * default stream.  Must not be changed while a graph captured by
+ * hpnfft_batch_capture is in use. */
+int hpnfft_set_stream(hpnfft_plan plan, void *hip_stream);
+
+/* Spread/interpolation tiling: tile edge in the two fastest grid dimensions
+ * (cells), slab depth along the slowest dimension (cells) and threads per
+ * workgroup (multiple of 64, <= 1024).  Pass 0 to keep a value.  Must be
+ * called before hpnfft_set_workspace.  EINVAL if the tile does not fit the
+ * 160 KiB local data share. */
+int hpnfft_set_tiles(hpnfft_plan plan, int tile, int slab, int threads);
+int hpnfft_get_tiles(hpnfft_plan plan, int *tile, int *slab, int *threads);
+
+/* Bytes of device workspace this plan needs (depends on the tiling). */
+int hpnfft_workspace_size(hpnfft_plan plan, size_t *bytes);
+
+/* Attach the caller's device workspace (>= hpnfft_workspace_size bytes,
+ * 256-byte aligned).  Uploads the roll-off and twiddle tables.  The buffer
+ * must stay alive and untouched by the caller until the plan is destroyed or
+ * another workspace is set.  ENOMEM if too small. */
+int hpnfft_set_workspace(hpnfft_plan plan, void *dev_ptr, size_t bytes);
+
+/* Set the points x (device, M x d row-major, float64).  Bins and sorts them
+ * and tabulates the window values (the paper's CUNFFT evaluates the window on
+ * the fly, Section 1; here it is tabulated once per point set because the
+ * same points serve adjoint, forward and gradient).  The caller may free x
+ * afterwards.  Synchronises the plan's stream once, to check the domain:
+ * returns EDOMAIN if any coordinate is outside [-1/2,1/2) or not finite, and
+ * the plan then has no points.  ESTATE if no workspace is attached. */
+int hpnfft_set_points(hpnfft_plan plan, const double *x);
+/* Same, for float32 coordinates (promoted exactly to float64). */
+int hpnfft_set_points_f32(hpnfft_plan plan, const float *x);
+
+/* Adjoint transform, Eq. (5) (sign -): fhat = A f.
+ * f: M complex (input), fhat: prod(N) complex (output, overwritten).
+ * Steps: spread f onto the grid (Section 2, "Spreading"), FFT, divide by the
+ * window's Fourier coefficients on I_N ("Scaling").  ESTATE without points. */
+int hpnfft_adjoint(hpnfft_plan plan, const void *f, void *fhat);
+
+/* Forward transform, Eq. (6) (sign +, unnormalised): f = A^H fhat.
+ * Steps: divide by the window's Fourier coefficients and zero-pad to the
+ * oversampled grid ("Subdividing"), inverse FFT, interpolate at the points
+ * ("Interpolating").  ESTATE without points. */
+int hpnfft_forward(hpnfft_plan plan, const void *fhat, void *f);
+
+/* Backward of the adjoint for a real loss L(fhat), differentiating Eq. (5):
+ *   grad_fhat = dL/dRe fhat + i dL/dIm fhat       (input, prod(N) complex)
+ *   grad_f    = A^H grad_fhat                      (output, M complex)
+ *   grad_x    [j*d+t] = Re( f_j * conj( d/dx_{j,t} (A^H grad_fhat)(x_j) ) )
+ *                                                  (output, M x d reals of the
+ *                                                   plan precision)
+ * f is the adjoint's input.  Needs a plan created with HPNFFT_WITH_GRADIENT
+ * (else EINVAL).  grad_f or grad_x may be NULL to skip that output. */
+int hpnfft_adjoint_backward(hpnfft_plan plan, const void *f, const void *grad_fhat,
+                            void *grad_f, void *grad_x);
+
+/* Reciprocal-space Ewald sum of Eq. (12) (Section 5) from the structure
+ * factor S = A q computed by hpnfft_adjoint with f = q and x = r / L:
+ *   energy = 1/(2 pi L) sum_{k in I_N, k != 0} exp(-pi^2 |k|^2/(alpha L)^2)/|k|^2 |S(k)|^2
+ * (self term not included), accumulated in float64 on the device, written to
+ * *energy_dev (one double, device memory).  If gbar is not NULL it receives
+ * dE/dRe S + i dE/dIm S (prod(N) complex, plan precision), the input of
+ * hpnfft_adjoint_backward that yields forces F = -(1/L) grad_x. */
+int hpnfft_ewald_recip(hpnfft_plan plan, const void *S, double L, double alpha,
+                       double *energy_dev, void *gbar);
+
+/* Tiling autotuner: times the adjoint and forward for each candidate tiling
+ * on the current points and keeps the fastest.  Needs points and a workspace
+ * at least as large as the largest candidate needs (query with
+ * hpnfft_workspace_size after hpnfft_set_tiles).  Writes the chosen tiling
+ * to tile/slab/threads (may be NULL).  Synchronises the stream. */
+int hpnfft_autotune(hpnfft_plan plan, void *scratch_f, void *scratch_fhat,
+                    int *tile, int *slab, int *threads);
+
+/* Oversampled grid size n (d values) and points count. */
+int hpnfft_plan_info(hpnfft_plan plan, int64_t *n_out, int64_t *M_out);
+
+/* ---- batches of independent transforms ------------------------------ */
+/* B transforms sharing precision, sigma, m and window; transform b has
+ * bandwidth N[3b .. 3b+2] and M[b] points.  Packed buffers concatenate the
+ * per-transform arrays in order: x (sum M x 3), f (sum M complex),
+ * fhat (sum prod(N_b) complex). */
+int hpnfft_batch_create(hpnfft_batch *out, int B, const int64_t *N, const int64_t *M,
+                        double sigma, int m, int window, int precision, unsigned flags);
+/* Packed set_points / adjoint / forward for a batch: each phase of every
+ * transform runs as one launch over a cross-transform work list. */
+int hpnfft_batch_set_points(hpnfft_batch batch, const double *x_packed);
+int hpnfft_batch_adjoint(hpnfft_batch batch, const void *f_packed, void *fhat_packed);
+int hpnfft_batch_forward(hpnfft_batch batch, const void *fhat_packed, void *f_packed);
+/* Record the batch adjoint on the plan's (non-default) stream into a HIP
+ * graph, with the given buffers; hpnfft_batch_launch replays it. */
+int hpnfft_batch_capture(hpnfft_batch batch, const void *f_packed, void *fhat_packed);
+int hpnfft_batch_launch(hpnfft_batch batch);
+/* Element offsets of transform b in the packed point and frequency arrays. */
+int hpnfft_batch_offsets(hpnfft_batch batch, int b, int64_t *point_offset,
+                         int64_t *freq_offset);
+
+/* ---- host-only helpers (no GPU needed) ------------------------------ */
+/* Kaiser-Bessel window in grid units t = n x - l, normalised to phi(0) = 1:
+ *   phi(t) = sinh(b r) / (r sinh(b m) / m), r = sqrt(m^2 - t^2), b = pi(2 - 1/sigma),
+ * and its derivative dphi/dt, for |t| <= m (0 beyond).  dphi may be NULL. */
+int hpnfft_window_eval(int m, double sigma, int64_t count, const double *t,
+                       double *phi, double *dphi);
+/* Roll-off factors 1/c_k for k = -N/2 .. N/2-1 (N values) of one dimension
+ * with grid size n: c_k = n * phihat(k), the Fourier coefficient of the
+ * periodised window scaled as above (Section 2, "Scaling"). */
+int hpnfft_window_rolloff(int m, double sigma, int64_t n, int64_t N, double *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HPNFFT_H */

@@ -1,0 +1,275 @@
+// FFT passes over the oversampled grid (Section 2: the FFT step of the
+// gridding scheme; Algorithm 2 runs a forward FFT, Algorithm 5 an inverse one)
+// with the crop to I_N and the division by the window's Fourier coefficients
+// ("Scaling"; "Subdividing" on the way back) fused into the first / last pass.
+//
+// One pass transforms all pencils along one dimension.  A workgroup loads
+// `count` pencils (coalesced: a run of contiguous elements per pencil row),
+// runs a mixed-radix (8, 4, 2, 3) Stockham autosort FFT in LDS with FP64
+// twiddles (rounded once for the float path), and stores only the outputs the
+// next step needs.  The passes are HBM-bound; pruning keeps the traffic at
+// about 2.6 grid volumes per transform instead of 6.
+//
+// Adjoint (sign -):  grid[n0][n1][n2] --dim2--> A[n0][n1][N2] --dim1--> B[n0][N1][N2]
+//                    --dim0, x 1/c_k--> fhat[N0][N1][N2]
+// Forward (sign +):  fhat --x 1/c_k, pad, dim0--> B --dim1--> A --dim2--> grid
+// Frequency k of a length-n transform sits at bin k mod n; the cropped
+// (centred) arrays store k at k + N/2.
+#include "internal.h"
+
+namespace hpnfft {
+
+constexpr int kFftThreads = 256;
+constexpr int kFftCap = 2112;  // complex elements per LDS buffer
+
+template <typename R> struct C2 { R x, y; };
+
+template <typename R> __device__ inline C2<R> cmul(C2<R> a, C2<R> b)
+{
+    return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename R> __device__ inline C2<R> cadd(C2<R> a, C2<R> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename R> __device__ inline C2<R> csub(C2<R> a, C2<R> b) { return {a.x - b.x, a.y - b.y}; }
+// multiply by i*S (S = +1 or -1)
+template <int S, typename R> __device__ inline C2<R> mul_is(C2<R> a) { return {-S * a.y, S * a.x}; }
+
+// In-register DFT of length RAD with kernel exp(S 2 pi i n k / RAD).
+template <int S, typename R> __device__ inline void dft2(C2<R> *v)
+{
+    C2<R> a = v[0], b = v[1];
+    v[0] = cadd(a, b);
+    v[1] = csub(a, b);
+}
+template <int S, typename R> __device__ inline void dft4(C2<R> *v)
+{
+    C2<R> a0 = v[0], a1 = v[1], a2 = v[2], a3 = v[3];
+    C2<R> s02 = cadd(a0, a2), d02 = csub(a0, a2);
+    C2<R> s13 = cadd(a1, a3), d13 = mul_is<S>(csub(a1, a3));
+    v[0] = cadd(s02, s13);
+    v[2] = csub(s02, s13);
+    v[1] = cadd(d02, d13);
+    v[3] = csub(d02, d13);
+}
+template <int S, typename R> __device__ inline void dft8(C2<R> *v)
+{
+    C2<R> e[4] = {v[0], v[2], v[4], v[6]};
+    C2<R> o[4] = {v[1], v[3], v[5], v[7]};
+    dft4<S>(e);
+    dft4<S>(o);
+    const R h = (R)0.70710678118654752440;
+    // w^k = exp(S 2 pi i k / 8)
+    C2<R> w1 = {h, S * h}, w3 = {-h, S * h};
+    C2<R> t0 = o[0], t1 = cmul(o[1], w1), t2 = mul_is<S>(o[2]), t3 = cmul(o[3], w3);
+    v[0] = cadd(e[0], t0);
+    v[4] = csub(e[0], t0);
+    v[1] = cadd(e[1], t1);
+    v[5] = csub(e[1], t1);
+    v[2] = cadd(e[2], t2);
+    v[6] = csub(e[2], t2);
+    v[3] = cadd(e[3], t3);
+    v[7] = csub(e[3], t3);
+}
+template <int S, typename R> __device__ inline void dft3(C2<R> *v)
+{
+    const R c = (R)0.86602540378443864676;  // sqrt(3)/2
+    C2<R> t1 = cadd(v[1], v[2]), t2 = csub(v[1], v[2]);
+    C2<R> a = {v[0].x - (R)0.5 * t1.x, v[0].y - (R)0.5 * t1.y};
+    C2<R> b = {-S * c * t2.y, S * c * t2.x};  // i S (sqrt3/2) t2
+    v[0] = cadd(v[0], t1);
+    v[1] = cadd(a, b);
+    v[2] = csub(a, b);
+}
+
+// One Stockham stage of radix RAD for `count` pencils of length n.
+template <int RAD, int S, typename R>
+__device__ inline void stage(const C2<R> *__restrict__ src, C2<R> *__restrict__ dst, const C2<R> *tw,
+                             int n, int ld, int count, int Ns)
+{
+    const int nb = n / RAD;
+    const int tstep = n / (Ns * RAD);
+    for (int t = threadIdx.x; t < count * nb; t += blockDim.x) {
+        int pen = t / nb, j = t - pen * nb;
+        const C2<R> *sp = src + pen * ld;
+        C2<R> *dp = dst + pen * ld;
+        int k = j % Ns;
+        C2<R> v[RAD];
+#pragma unroll
+        for (int r = 0; r < RAD; ++r) v[r] = sp[j + r * nb];
+        if (Ns > 1) {
+#pragma unroll
+            for (int r = 1; r < RAD; ++r) v[r] = cmul(v[r], tw[k * r * tstep]);
+        }
+        if (RAD == 2) dft2<S>(v);
+        if (RAD == 3) dft3<S>(v);
+        if (RAD == 4) dft4<S>(v);
+        if (RAD == 8) dft8<S>(v);
+        int idx = (j / Ns) * Ns * RAD + k;
+#pragma unroll
+        for (int r = 0; r < RAD; ++r) dp[idx + r * Ns] = v[r];
+    }
+}
+
+struct PassGeom {
+    int dim, n, N, Lin, Lout, inner;
+    long long outer_len;  // number of outer indices
+    bool crop;            // adjoint: keep N of n outputs
+    bool roll_out, roll_in;
+};
+
+__device__ inline PassGeom pass_geom(int pass, const Xform &X)
+{
+    PassGeom g;
+    switch (pass) {
+    case P_ADJ0: g.dim = 2; g.inner = 1; g.outer_len = (long long)X.n[0] * X.n[1]; break;
+    case P_ADJ1: g.dim = 1; g.inner = X.N[2]; g.outer_len = X.n[0]; break;
+    case P_ADJ2: g.dim = 0; g.inner = X.N[1] * X.N[2]; g.outer_len = 1; break;
+    case P_FWD0: g.dim = 0; g.inner = X.N[1] * X.N[2]; g.outer_len = 1; break;
+    case P_FWD1: g.dim = 1; g.inner = X.N[2]; g.outer_len = X.n[0]; break;
+    default:     g.dim = 2; g.inner = 1; g.outer_len = (long long)X.n[0] * X.n[1]; break;
+    }
+    g.n = X.n[g.dim];
+    g.N = X.N[g.dim];
+    g.crop = pass <= P_ADJ2;
+    g.Lin = g.crop ? g.n : g.N;
+    g.Lout = g.crop ? g.N : g.n;
+    g.roll_out = pass == P_ADJ2;
+    g.roll_in = pass == P_FWD0;
+    return g;
+}
+
+template <typename R, int S>
+__global__ __launch_bounds__(kFftThreads) void k_fft(int pass, const Xform *__restrict__ xfs,
+                                                     const FItem *__restrict__ items, void *fhat_base)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    C2<R> *bufA = reinterpret_cast<C2<R> *>(smem);
+    C2<R> *bufB = bufA + kFftCap;
+    C2<R> *tw = bufB + kFftCap;
+
+    const FItem W = items[blockIdx.x];
+    const Xform &X = xfs[W.xf];
+    const PassGeom g = pass_geom(pass, X);
+    const int n = g.n, ld = n + 1, cnt = W.count;
+    const int tid = threadIdx.x, nthr = blockDim.x;
+
+    const C2<R> *src;
+    C2<R> *dst;
+    C2<R> *fh = reinterpret_cast<C2<R> *>(fhat_base) + X.foff;
+    switch (pass) {
+    case P_ADJ0: src = (const C2<R> *)X.grid; dst = (C2<R> *)X.tmpA; break;
+    case P_ADJ1: src = (const C2<R> *)X.tmpA; dst = (C2<R> *)X.tmpB; break;
+    case P_ADJ2: src = (const C2<R> *)X.tmpB; dst = fh; break;
+    case P_FWD0: src = fh; dst = (C2<R> *)X.tmpB; break;
+    case P_FWD1: src = (const C2<R> *)X.tmpB; dst = (C2<R> *)X.tmpA; break;
+    default:     src = (const C2<R> *)X.tmpA; dst = (C2<R> *)X.grid; break;
+    }
+
+    // twiddles exp(S 2 pi i j / n), table holds exp(-2 pi i j / n)
+    const C2<R> *twg = reinterpret_cast<const C2<R> *>(X.tw[g.dim]);
+    for (int j = tid; j < n; j += nthr) {
+        C2<R> w = twg[j];
+        if (S > 0) w.y = -w.y;
+        tw[j] = w;
+    }
+
+    // element (pencil p, position j) of an array with L positions per pencil
+    const int inner = g.inner;
+    auto addr = [&](int p, int j, int L) -> long long {
+        if (inner == 1) return ((long long)W.outer + p) * L + j;
+        return ((long long)W.outer * L + j) * inner + W.inner0 + p;
+    };
+
+    // ---- load ----
+    if (g.crop) {
+        const int tot = cnt * n;
+        for (int e = tid; e < tot; e += nthr) {
+            int p, j;
+            if (inner == 1) { p = e / n; j = e - p * n; }
+            else { j = e / cnt; p = e - j * cnt; }
+            bufA[p * ld + j] = src[addr(p, j, n)];
+        }
+    } else {
+        for (int e = tid; e < cnt * n; e += nthr) {
+            int p = e / n, j = e - p * n;
+            bufA[p * ld + j] = C2<R>{R(0), R(0)};
+        }
+        __syncthreads();
+        const int N = g.N, tot = cnt * N;
+        for (int e = tid; e < tot; e += nthr) {
+            int p, i;
+            if (inner == 1) { p = e / N; i = e - p * N; }
+            else { i = e / cnt; p = e - i * cnt; }
+            C2<R> v = src[addr(p, i, N)];
+            if (g.roll_in) {
+                int ii = W.inner0 + p;
+                double f = X.roll[0][i] * X.roll[1][ii / X.N[2]] * X.roll[2][ii % X.N[2]];
+                v.x = (R)(v.x * f);
+                v.y = (R)(v.y * f);
+            }
+            int bin = i - N / 2;
+            if (bin < 0) bin += n;
+            bufA[p * ld + bin] = v;
+        }
+    }
+    __syncthreads();
+
+    // ---- Stockham stages: radix 8 first, then 4, 2, 3 ----
+    C2<R> *cur = bufA, *nxt = bufB;
+    int rem = n, Ns = 1;
+    while (rem > 1) {
+        int rad = (rem % 8 == 0) ? 8 : (rem % 4 == 0) ? 4 : (rem % 2 == 0) ? 2 : 3;
+        switch (rad) {
+        case 8: stage<8, S, R>(cur, nxt, tw, n, ld, cnt, Ns); break;
+        case 4: stage<4, S, R>(cur, nxt, tw, n, ld, cnt, Ns); break;
+        case 2: stage<2, S, R>(cur, nxt, tw, n, ld, cnt, Ns); break;
+        default: stage<3, S, R>(cur, nxt, tw, n, ld, cnt, Ns); break;
+        }
+        __syncthreads();
+        C2<R> *t = cur;
+        cur = nxt;
+        nxt = t;
+        Ns *= rad;
+        rem /= rad;
+    }
+
+    // ---- store ----
+    const int Lout = g.Lout, tot = cnt * Lout;
+    for (int e = tid; e < tot; e += nthr) {
+        int p, o;
+        if (inner == 1) { p = e / Lout; o = e - p * Lout; }
+        else { o = e / cnt; p = e - o * cnt; }
+        int bin = o;
+        if (g.crop) {
+            bin = o - g.N / 2;
+            if (bin < 0) bin += n;
+        }
+        C2<R> v = cur[p * ld + bin];
+        if (g.roll_out) {
+            int ii = W.inner0 + p;
+            double f = X.roll[0][o] * X.roll[1][ii / X.N[2]] * X.roll[2][ii % X.N[2]];
+            v.x = (R)(v.x * f);
+            v.y = (R)(v.y * f);
+        }
+        dst[addr(p, o, Lout)] = v;
+    }
+}
+
+template <typename R>
+hipError_t launch_fft(int pass, const Xform *dxf, const FItem *items, int nitems, int max_n,
+                      void *fhat_base, hipStream_t s)
+{
+    if (nitems <= 0) return hipSuccess;
+    size_t lds = (size_t)(2 * kFftCap + max_n) * 2 * sizeof(R);
+    bool adj = pass <= P_ADJ2;
+    auto kern = adj ? k_fft<R, -1> : k_fft<R, 1>;
+    hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kern, dim3(nitems), dim3(kFftThreads), lds, s, pass, dxf, items, fhat_base);
+    return hipGetLastError();
+}
+
+template hipError_t launch_fft<double>(int, const Xform *, const FItem *, int, int, void *, hipStream_t);
+template hipError_t launch_fft<float>(int, const Xform *, const FItem *, int, int, void *, hipStream_t);
+
+}  // namespace hpnfft

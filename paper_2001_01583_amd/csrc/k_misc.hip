@@ -1,0 +1,174 @@
+// Small elementwise kernels: zero fill (used instead of memset so the
+// sequences can be captured in a HIP graph), value gather into sorted point
+// order, result scatter back to the caller's order, the gradient epilogue,
+// and the reciprocal-space Ewald sum of Eq. (12) with a float64 reduction.
+#include "internal.h"
+
+namespace hpnfft {
+
+__global__ void k_zero(uint4 *__restrict__ p, size_t n16, unsigned char *__restrict__ tail,
+                       size_t ntail)
+{
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (; i < n16; i += stride) p[i] = make_uint4(0, 0, 0, 0);
+    if (blockIdx.x == 0 && threadIdx.x < ntail) tail[threadIdx.x] = 0;
+}
+
+hipError_t launch_zero(void *p, size_t bytes, hipStream_t s)
+{
+    if (bytes == 0) return hipSuccess;
+    size_t n16 = bytes / 16, ntail = bytes % 16;
+    size_t blocks = (n16 + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_zero, dim3((unsigned)blocks), dim3(256), 0, s, (uint4 *)p, n16,
+                       (unsigned char *)p + n16 * 16, ntail);
+    return hipGetLastError();
+}
+
+template <typename R>
+__global__ void k_gather(const R *__restrict__ f, const int *__restrict__ perm, long long total,
+                         R *__restrict__ fs)
+{
+    long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= total) return;
+    long long j = perm[p];
+    fs[2 * p] = f[2 * j];
+    fs[2 * p + 1] = f[2 * j + 1];
+}
+
+template <typename R>
+__global__ void k_scatter(const R *__restrict__ outs, const int *__restrict__ perm, long long total,
+                          R *__restrict__ f)
+{
+    long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= total) return;
+    long long j = perm[p];
+    f[2 * j] = outs[2 * p];
+    f[2 * j + 1] = outs[2 * p + 1];
+}
+
+// outs4 per sorted point: p, d0 p, d1 p, d2 p (complex).  grad_x = Re(f conj(d p)).
+template <typename R>
+__global__ void k_grad_finish(const R *__restrict__ outs4, const R *__restrict__ f,
+                              const int *__restrict__ perm, long long total, R *__restrict__ grad_f,
+                              R *__restrict__ grad_x)
+{
+    long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= total) return;
+    long long j = perm[p];
+    const R *o = outs4 + p * 8;
+    if (grad_f) {
+        grad_f[2 * j] = o[0];
+        grad_f[2 * j + 1] = o[1];
+    }
+    if (grad_x) {
+        R fr = f[2 * j], fi = f[2 * j + 1];
+        for (int t = 0; t < 3; ++t) grad_x[3 * j + t] = fr * o[2 + 2 * t] + fi * o[3 + 2 * t];
+    }
+}
+
+template <typename R>
+hipError_t launch_gather(const void *f, const int *perm, long long total, R *fs, hipStream_t s)
+{
+    if (total <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gather<R>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s,
+                       (const R *)f, perm, total, fs);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_scatter(const R *outs, const int *perm, long long total, void *f, hipStream_t s)
+{
+    if (total <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_scatter<R>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, outs, perm,
+                       total, (R *)f);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_grad_finish(const R *outs4, const void *f, const int *perm, long long total,
+                              void *grad_f, void *grad_x, hipStream_t s)
+{
+    if (total <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_grad_finish<R>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, outs4,
+                       (const R *)f, perm, total, (R *)grad_f, (R *)grad_x);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Eq. (12) reciprocal sum.  One thread per k in I_N; k = 0 excluded.
+constexpr int kEwThreads = 256;
+
+template <typename R>
+__global__ __launch_bounds__(kEwThreads) void k_ewald(const R *__restrict__ S, int N0, int N1, int N2,
+                                                      double L, double alpha, double *__restrict__ part,
+                                                      R *__restrict__ gbar)
+{
+    __shared__ double sh[kEwThreads];
+    long long tot = (long long)N0 * N1 * N2;
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    double e = 0.0;
+    if (i < tot) {
+        long long k0 = i / ((long long)N1 * N2) - N0 / 2;
+        long long k1 = (i / N2) % N1 - N1 / 2;
+        long long k2 = i % N2 - N2 / 2;
+        double k2s = (double)(k0 * k0 + k1 * k1 + k2 * k2);
+        double w = 0.0;
+        if (k2s > 0.0) w = exp(-M_PI * M_PI * k2s / (alpha * L * alpha * L)) / k2s;
+        double sr = (double)S[2 * i], si = (double)S[2 * i + 1];
+        e = w * (sr * sr + si * si) / (2.0 * M_PI * L);
+        if (gbar) {
+            // d/dRe S + i d/dIm S of w |S|^2 / (2 pi L)
+            gbar[2 * i] = (R)(w * sr / (M_PI * L));
+            gbar[2 * i + 1] = (R)(w * si / (M_PI * L));
+        }
+    }
+    sh[threadIdx.x] = e;
+    __syncthreads();
+    for (int off = kEwThreads / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+// Fixed-order final sum of the block partials (deterministic).
+__global__ __launch_bounds__(kEwThreads) void k_sum_partials(const double *__restrict__ part, int n,
+                                                             double *__restrict__ out)
+{
+    __shared__ double sh[kEwThreads];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) s += part[i];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = kEwThreads / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = sh[0];
+}
+
+template <typename R>
+hipError_t launch_ewald(const void *S, const Xform &X, double L, double alpha, double *partials,
+                        int nblocks, double *energy, void *gbar, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_ewald<R>, dim3(nblocks), dim3(kEwThreads), 0, s, (const R *)S, X.N[0], X.N[1],
+                       X.N[2], L, alpha, partials, (R *)gbar);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kEwThreads), 0, s, partials, nblocks, energy);
+    return hipGetLastError();
+}
+
+#define HPNFFT_INST(R)                                                                             \
+    template hipError_t launch_gather<R>(const void *, const int *, long long, R *, hipStream_t);  \
+    template hipError_t launch_scatter<R>(const R *, const int *, long long, void *, hipStream_t); \
+    template hipError_t launch_grad_finish<R>(const R *, const void *, const int *, long long,     \
+                                              void *, void *, hipStream_t);                        \
+    template hipError_t launch_ewald<R>(const void *, const Xform &, double, double, double *, int, \
+                                        double *, void *, hipStream_t);
+HPNFFT_INST(double)
+HPNFFT_INST(float)
+#undef HPNFFT_INST
+
+}  // namespace hpnfft

@@ -1,0 +1,771 @@
+// Host side of the C-ABI: validation, window tables, workspace layout, and
+// the kernel sequences of set_points / adjoint / forward / backward.
+//
+// Section 3 of the paper runs one CUNFFT per subcell (Algorithm 2:
+// copy in, spread, FFT, scale, copy out; Algorithm 5: copy in, subdivide,
+// inverse FFT, interpolate, copy out).  Here the data stays in HBM: the
+// caller passes device pointers and every step is a kernel on the plan's
+// stream.  A plan over B transforms runs each step of all B transforms as
+// one launch over a combined work list (Section 3 decomposes one transform
+// into subcell transforms whose results add up, Eq. (8); independent
+// transforms batch the same way).
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <new>
+#include <vector>
+
+#include "../../include/hpnfft.h"
+#include "internal.h"
+#include "window.h"
+
+namespace hpnfft {
+hipError_t launch_tile_cost(const int *cell_start, const Xform &X, int T, int Zs, int m, int *tcost,
+                            unsigned long long *total, hipStream_t s);
+hipError_t launch_make_items(const int *cell_start, int xf, const Xform &X, int T, int Zs, int m,
+                             const int *tcost, const unsigned long long *total, int cap_div, int min_cap,
+                             int max_items, SItem *items, int *nitems, int *overflow, hipStream_t s);
+}  // namespace hpnfft
+
+using namespace hpnfft;
+
+namespace {
+
+constexpr int kFftCap = 2112;
+constexpr int kMinCap = 2048;
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+bool is_2a3b(long v)
+{
+    if (v < 1) return false;
+    while (v % 2 == 0) v /= 2;
+    while (v % 3 == 0) v /= 3;
+    return v == 1;
+}
+
+int fft_count(int n)
+{
+    int c = 1;
+    while ((c * 2) * (n + 1) <= kFftCap) c *= 2;
+    return c;
+}
+
+struct Layout {
+    size_t counters, setp, grids, tmpA, tmpB, cell_start, scan_tmp, rank, perm, pz, us, xs, psi, dpsi,
+        fs, outs, tcost, items, fit[3], ewald, roll, tw, xf, total;
+    std::vector<size_t> grid_off, tmpA_off, tmpB_off, key_off, tcost_off, roll_off;
+    std::map<int, size_t> tw_off;
+    int max_items = 0, nfit[3] = {0, 0, 0}, ew_blocks = 0;
+    size_t grids_bytes = 0, outs_bytes = 0;
+};
+
+}  // namespace
+
+struct hpnfft_plan_s {
+    int B = 0, m = 0, prec = 0, window = 0;
+    double sigma = 2.0, b = 0.0, inv_peak = 0.0;
+    unsigned flags = 0;
+    std::vector<Xform> hx;
+    std::vector<long long> keys;
+    long long Mtot = 0, Ftot = 0;
+    Tiling til{16, 16, 1024};
+    hipStream_t stream = nullptr;
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+    Layout L;
+    bool have_ws = false, have_points = false;
+    int nitems = 0;
+    int cus = 256;
+    int maxn = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+
+    size_t rbytes() const { return prec == HPNFFT_F32 ? 4 : 8; }
+    int M2() const { return 2 * m; }
+    bool grad() const { return (flags & HPNFFT_WITH_GRADIENT) != 0; }
+    template <typename T> T *at(size_t off) const { return reinterpret_cast<T *>(ws + off); }
+};
+
+namespace {
+
+int hip_status(hipError_t e) { return e == hipSuccess ? HPNFFT_OK : HPNFFT_EHIP; }
+#define HCHECK(x)                                                                                  \
+    do {                                                                                           \
+        hipError_t e_ = (x);                                                                       \
+        if (e_ != hipSuccess) return HPNFFT_EHIP;                                                  \
+    } while (0)
+
+bool tiling_fits(const hpnfft_plan_s *p, Tiling t)
+{
+    if (t.T < 4 || t.T > 32 || t.Zs < 2 || t.Zs > 64) return false;
+    if (t.threads < 64 || t.threads > 1024 || t.threads % 64) return false;
+    bool comp = p->prec == HPNFFT_F32;
+    size_t a = spread_lds_bytes(t.T, t.Zs, p->M2(), p->rbytes(), comp);
+    size_t b = interp_lds_bytes(t.T, t.Zs, p->M2(), p->rbytes(), t.threads, p->grad());
+    return a + 64 <= (size_t)kLdsBytes && b + 64 <= (size_t)kLdsBytes;
+}
+
+Tiling default_tiling(const hpnfft_plan_s *p)
+{
+    // largest power-of-two tile edge whose spread tile fits ~150 KiB of LDS
+    for (int Zs : {16, 8, 4})
+        for (int T : {32, 16, 8, 4}) {
+            Tiling t{T, Zs, 1024};
+            size_t a = spread_lds_bytes(T, Zs, p->M2(), p->rbytes(), p->prec == HPNFFT_F32);
+            if (tiling_fits(p, t) && a <= 150 * 1024) return t;
+        }
+    return Tiling{4, 4, 256};
+}
+
+void build_layout(hpnfft_plan_s *p)
+{
+    Layout &L = p->L;
+    L = Layout();
+    const size_t C = 2 * p->rbytes();
+    const int T = p->til.T, Zs = p->til.Zs;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align256(off + bytes);
+        return o;
+    };
+    L.counters = take(256);
+    L.setp = take(256);
+    size_t gbytes = 0;
+    long long maxkeys = 0, maxM = 0, pairs = 0, maxF = 0;
+    for (int b = 0; b < p->B; ++b) {
+        Xform &X = p->hx[b];
+        X.ntx = (X.n[2] + T - 1) / T;
+        X.nty = (X.n[1] + T - 1) / T;
+        X.nslab = (X.n[0] + Zs - 1) / Zs;
+        p->keys[b] = (long long)X.ntx * X.nty * T * T * X.n[0] + 1;
+        maxkeys = std::max(maxkeys, p->keys[b]);
+        maxM = std::max(maxM, X.M);
+        pairs += (long long)X.ntx * X.nty * X.nslab;
+        maxF = std::max(maxF, (long long)X.N[0] * X.N[1] * X.N[2]);
+    }
+    // grids (contiguous, zeroed by one launch)
+    L.grids = off;
+    for (int b = 0; b < p->B; ++b) {
+        const Xform &X = p->hx[b];
+        L.grid_off.push_back(off);
+        gbytes += align256((size_t)X.n[0] * X.n[1] * X.n[2] * C);
+        off = align256(off + (size_t)X.n[0] * X.n[1] * X.n[2] * C);
+    }
+    L.grids_bytes = off - L.grids;
+    L.tmpA = off;
+    for (int b = 0; b < p->B; ++b) {
+        const Xform &X = p->hx[b];
+        L.tmpA_off.push_back(take((size_t)X.n[0] * X.n[1] * X.N[2] * C));
+    }
+    L.tmpB = off;
+    for (int b = 0; b < p->B; ++b) {
+        const Xform &X = p->hx[b];
+        L.tmpB_off.push_back(take((size_t)X.n[0] * X.N[1] * X.N[2] * C));
+    }
+    L.cell_start = off;
+    for (int b = 0; b < p->B; ++b) L.key_off.push_back(take((size_t)p->keys[b] * 4));
+    long long nb = (maxkeys + 4095) / 4096;
+    L.scan_tmp = take((size_t)(nb + nb / 2048 + 64) * 4);
+    L.rank = take((size_t)maxM * 4);
+    L.perm = take((size_t)p->Mtot * 4);
+    L.pz = take((size_t)p->Mtot * 4);
+    L.us = take((size_t)p->Mtot * 24);
+    L.xs = take((size_t)p->Mtot * 24);
+    size_t psi_b = (size_t)p->Mtot * 3 * p->M2() * p->rbytes();
+    L.psi = take(psi_b);
+    L.dpsi = p->grad() ? take(psi_b) : 0;
+    L.fs = take((size_t)p->Mtot * C);
+    L.outs_bytes = (size_t)p->Mtot * C * (p->grad() ? 4 : 1);
+    L.outs = take(L.outs_bytes);
+    L.tcost = off;
+    for (int b = 0; b < p->B; ++b) {
+        const Xform &X = p->hx[b];
+        L.tcost_off.push_back(take((size_t)X.ntx * X.nty * X.nslab * 4));
+    }
+    L.max_items = (int)std::min<long long>(pairs + (long long)p->cus * 4 + 64, 0x7fffffffLL / 64);
+    L.items = take((size_t)L.max_items * sizeof(SItem));
+    for (int d = 0; d < 3; ++d) {
+        long long cnt = 0;
+        for (int b = 0; b < p->B; ++b) {
+            const Xform &X = p->hx[b];
+            int n = X.n[d], c = fft_count(n);
+            if (d == 2) cnt += ((long long)X.n[0] * X.n[1] + c - 1) / c;
+            if (d == 1) cnt += (long long)X.n[0] * ((X.N[2] + c - 1) / c);
+            if (d == 0) cnt += ((long long)X.N[1] * X.N[2] + c - 1) / c;
+        }
+        L.nfit[d] = (int)cnt;
+        L.fit[d] = take((size_t)cnt * sizeof(FItem));
+    }
+    L.ew_blocks = (int)((maxF + 255) / 256);
+    L.ewald = take((size_t)L.ew_blocks * 8 + 64);
+    L.roll = off;
+    for (int b = 0; b < p->B; ++b) {
+        const Xform &X = p->hx[b];
+        L.roll_off.push_back(take((size_t)(X.N[0] + X.N[1] + X.N[2]) * 8));
+    }
+    L.tw = off;
+    for (int b = 0; b < p->B; ++b)
+        for (int d = 0; d < 3; ++d) {
+            int n = p->hx[b].n[d];
+            if (!L.tw_off.count(n)) L.tw_off[n] = take((size_t)n * C);
+        }
+    L.xf = take((size_t)p->B * sizeof(Xform));
+    L.total = off + 256;
+    (void)gbytes;
+}
+
+int upload_tables(hpnfft_plan_s *p)
+{
+    const Layout &L = p->L;
+    // descriptors
+    for (int b = 0; b < p->B; ++b) {
+        Xform &X = p->hx[b];
+        X.grid = p->ws + L.grid_off[b];
+        X.tmpA = p->ws + L.tmpA_off[b];
+        X.tmpB = p->ws + L.tmpB_off[b];
+        double *r = p->at<double>(L.roll_off[b]);
+        X.roll[0] = r;
+        X.roll[1] = r + X.N[0];
+        X.roll[2] = r + X.N[0] + X.N[1];
+        for (int d = 0; d < 3; ++d) X.tw[d] = p->ws + L.tw_off.at(X.n[d]);
+        X.key_off = (long long)((L.key_off[b] - L.cell_start) / 4);
+    }
+    // roll-off factors 1/c_k (FP64)
+    for (int b = 0; b < p->B; ++b) {
+        const Xform &X = p->hx[b];
+        std::vector<double> h;
+        for (int d = 0; d < 3; ++d)
+            for (int k = -X.N[d] / 2; k < X.N[d] / 2; ++k)
+                h.push_back(1.0 / kb_phihat(k, X.n[d], p->m, p->b, p->inv_peak));
+        HCHECK(hipMemcpyAsync(p->ws + L.roll_off[b], h.data(), h.size() * 8, hipMemcpyHostToDevice,
+                              p->stream));
+        HCHECK(hipStreamSynchronize(p->stream));
+    }
+    // twiddles exp(-2 pi i j / n), computed in FP64 (long double angle), rounded once for float
+    for (auto &kv : L.tw_off) {
+        int n = kv.first;
+        std::vector<double> w64(2 * (size_t)n);
+        for (int j = 0; j < n; ++j) {
+            long double a = -2.0L * 3.141592653589793238462643383279502884L * j / n;
+            w64[2 * j] = (double)cosl(a);
+            w64[2 * j + 1] = (double)sinl(a);
+        }
+        if (p->prec == HPNFFT_F32) {
+            std::vector<float> w32(w64.begin(), w64.end());
+            HCHECK(hipMemcpyAsync(p->ws + kv.second, w32.data(), w32.size() * 4, hipMemcpyHostToDevice,
+                                  p->stream));
+        } else {
+            HCHECK(hipMemcpyAsync(p->ws + kv.second, w64.data(), w64.size() * 8, hipMemcpyHostToDevice,
+                                  p->stream));
+        }
+        HCHECK(hipStreamSynchronize(p->stream));
+    }
+    // FFT items
+    for (int d = 0; d < 3; ++d) {
+        std::vector<FItem> it;
+        it.reserve(L.nfit[d]);
+        for (int b = 0; b < p->B; ++b) {
+            const Xform &X = p->hx[b];
+            int c = fft_count(X.n[d]);
+            if (d == 2) {
+                long long rows = (long long)X.n[0] * X.n[1];
+                for (long long r = 0; r < rows; r += c)
+                    it.push_back(FItem{b, (int)r, 0, (int)std::min<long long>(c, rows - r)});
+            } else if (d == 1) {
+                for (int o = 0; o < X.n[0]; ++o)
+                    for (int i = 0; i < X.N[2]; i += c) it.push_back(FItem{b, o, i, std::min(c, X.N[2] - i)});
+            } else {
+                int inner = X.N[1] * X.N[2];
+                for (int i = 0; i < inner; i += c) it.push_back(FItem{b, 0, i, std::min(c, inner - i)});
+            }
+        }
+        if ((int)it.size() != L.nfit[d]) return HPNFFT_EINVAL;
+        HCHECK(hipMemcpyAsync(p->ws + L.fit[d], it.data(), it.size() * sizeof(FItem),
+                              hipMemcpyHostToDevice, p->stream));
+        HCHECK(hipStreamSynchronize(p->stream));
+    }
+    HCHECK(hipMemcpyAsync(p->ws + L.xf, p->hx.data(), p->hx.size() * sizeof(Xform), hipMemcpyHostToDevice,
+                          p->stream));
+    HCHECK(hipStreamSynchronize(p->stream));
+    return HPNFFT_OK;
+}
+
+int check_plan(hpnfft_plan_s *p) { return p ? HPNFFT_OK : HPNFFT_EINVAL; }
+
+// Bin, sort and tabulate the stored points (p->ws + L.xs); then build the
+// spread / interpolation work list.  Synchronises once.
+int bin_points(hpnfft_plan_s *p)
+{
+    const Layout &L = p->L;
+    hipStream_t s = p->stream;
+    int *setp = p->at<int>(L.setp);  // [0] err, [1] nitems, [2] overflow, [4..5] total (u64)
+    HCHECK(launch_zero(setp, 256, s));
+    const double *xs = p->at<double>(L.xs);
+    unsigned long long *total = reinterpret_cast<unsigned long long *>(setp + 4);
+    for (int b = 0; b < p->B; ++b) {
+        const Xform &X = p->hx[b];
+        int *cs = p->at<int>(L.key_off[b]);
+        HCHECK(launch_zero(cs, (size_t)p->keys[b] * 4, s));
+        const double *xb = xs + X.poff * 3;
+        HCHECK(launch_bin_count(xb, nullptr, X.M, X, p->til.T, p->m, cs, p->at<int>(L.rank), setp, s));
+        HCHECK(launch_scan(cs, p->keys[b], p->at<int>(L.scan_tmp), s));
+        HCHECK(launch_bin_scatter(xb, nullptr, X.M, X, p->til.T, p->m, cs, p->at<int>(L.rank),
+                                  p->at<int>(L.perm), p->at<int>(L.pz), p->at<double>(L.us), s));
+        if (p->prec == HPNFFT_F32)
+            HCHECK(launch_psi<float>(p->at<double>(L.us), p->at<int>(L.pz), X.M, X.poff, X, p->m, p->b,
+                                     p->inv_peak, p->at<float>(L.psi),
+                                     p->grad() ? p->at<float>(L.dpsi) : nullptr, s));
+        else
+            HCHECK(launch_psi<double>(p->at<double>(L.us), p->at<int>(L.pz), X.M, X.poff, X, p->m, p->b,
+                                      p->inv_peak, p->at<double>(L.psi),
+                                      p->grad() ? p->at<double>(L.dpsi) : nullptr, s));
+        HCHECK(launch_tile_cost(cs, X, p->til.T, p->til.Zs, p->m, p->at<int>(L.tcost_off[b]), total, s));
+    }
+    const int cap_div = p->cus * 4;
+    for (int b = 0; b < p->B; ++b) {
+        const Xform &X = p->hx[b];
+        HCHECK(launch_make_items(p->at<int>(L.key_off[b]), b, X, p->til.T, p->til.Zs, p->m,
+                                 p->at<int>(L.tcost_off[b]), total, cap_div, kMinCap, L.max_items,
+                                 p->at<SItem>(L.items), setp + 1, setp + 2, s));
+    }
+    int host[4] = {0, 0, 0, 0};
+    HCHECK(hipMemcpyAsync(host, setp, sizeof(host), hipMemcpyDeviceToHost, s));
+    HCHECK(hipStreamSynchronize(s));
+    if (host[0]) return HPNFFT_EDOMAIN;
+    if (host[2]) return HPNFFT_ENOMEM;
+    p->nitems = std::min(host[1], L.max_items);
+    return HPNFFT_OK;
+}
+
+template <typename R> int run_adjoint(hpnfft_plan_s *p, const void *f, void *fhat)
+{
+    const Layout &L = p->L;
+    hipStream_t s = p->stream;
+    const Xform *dxf = p->at<Xform>(L.xf);
+    // queue counters and grids form one contiguous zeroed range
+    HCHECK(launch_zero(p->ws + L.counters, 256, s));
+    HCHECK(launch_zero(p->ws + L.grids, L.grids_bytes, s));
+    HCHECK(launch_gather<R>(f, p->at<int>(L.perm), p->Mtot, p->at<R>(L.fs), s));
+    HCHECK(launch_spread<R>(p->m, dxf, p->at<SItem>(L.items), p->nitems, p->at<int>(L.counters), p->til,
+                            p->at<R>(L.psi), p->at<R>(L.fs), p->at<int>(L.pz), p->at<int>(L.cell_start),
+                            nullptr, s));
+    for (int pass = P_ADJ0; pass <= P_ADJ2; ++pass) {
+        int d = pass == P_ADJ0 ? 2 : (pass == P_ADJ1 ? 1 : 0);
+        HCHECK(launch_fft<R>(pass, dxf, p->at<FItem>(L.fit[d]), L.nfit[d], p->maxn, fhat, s));
+    }
+    return HPNFFT_OK;
+}
+
+template <typename R> int run_to_grid(hpnfft_plan_s *p, const void *fhat)
+{
+    const Layout &L = p->L;
+    hipStream_t s = p->stream;
+    const Xform *dxf = p->at<Xform>(L.xf);
+    for (int pass = P_FWD0; pass <= P_FWD2; ++pass) {
+        int d = pass == P_FWD0 ? 0 : (pass == P_FWD1 ? 1 : 2);
+        HCHECK(launch_fft<R>(pass, dxf, p->at<FItem>(L.fit[d]), L.nfit[d], p->maxn,
+                             const_cast<void *>(fhat), s));
+    }
+    return HPNFFT_OK;
+}
+
+template <typename R> int run_forward(hpnfft_plan_s *p, const void *fhat, void *f)
+{
+    const Layout &L = p->L;
+    hipStream_t s = p->stream;
+    const Xform *dxf = p->at<Xform>(L.xf);
+    HCHECK(launch_zero(p->ws + L.counters, 256, s));
+    HCHECK(launch_zero(p->ws + L.outs, (size_t)p->Mtot * 2 * sizeof(R), s));
+    int rc = run_to_grid<R>(p, fhat);
+    if (rc) return rc;
+    HCHECK(launch_interp<R>(p->m, false, dxf, p->at<SItem>(L.items), p->nitems, p->at<int>(L.counters) + 1,
+                            p->til, p->at<R>(L.psi), nullptr, p->at<int>(L.pz), p->at<int>(L.cell_start),
+                            p->at<R>(L.outs), s));
+    HCHECK(launch_scatter<R>(p->at<R>(L.outs), p->at<int>(L.perm), p->Mtot, f, s));
+    return HPNFFT_OK;
+}
+
+template <typename R>
+int run_backward(hpnfft_plan_s *p, const void *f, const void *gfhat, void *grad_f, void *grad_x)
+{
+    const Layout &L = p->L;
+    hipStream_t s = p->stream;
+    const Xform *dxf = p->at<Xform>(L.xf);
+    HCHECK(launch_zero(p->ws + L.counters, 256, s));
+    HCHECK(launch_zero(p->ws + L.outs, L.outs_bytes, s));
+    int rc = run_to_grid<R>(p, gfhat);
+    if (rc) return rc;
+    HCHECK(launch_interp<R>(p->m, true, dxf, p->at<SItem>(L.items), p->nitems, p->at<int>(L.counters) + 1,
+                            p->til, p->at<R>(L.psi), p->at<R>(L.dpsi), p->at<int>(L.pz),
+                            p->at<int>(L.cell_start), p->at<R>(L.outs), s));
+    HCHECK(launch_grad_finish<R>(p->at<R>(L.outs), f, p->at<int>(L.perm), p->Mtot, grad_f, grad_x, s));
+    return HPNFFT_OK;
+}
+
+int create_common(hpnfft_plan_s **out, int B, const int64_t *N, const int64_t *M, double sigma, int m,
+                  int window, int precision, unsigned flags)
+{
+    if (!out || B < 1 || !N || !M) return HPNFFT_EINVAL;
+    *out = nullptr;
+    if (window != HPNFFT_KAISER_BESSEL) return HPNFFT_EINVAL;
+    if (precision != HPNFFT_F64 && precision != HPNFFT_F32) return HPNFFT_EINVAL;
+    if (m < 1 || m > 8) return HPNFFT_EINVAL;
+    if (flags & ~HPNFFT_WITH_GRADIENT) return HPNFFT_EINVAL;
+    if (!(sigma >= 1.0) || !std::isfinite(sigma)) return HPNFFT_EINVAL;
+    hpnfft_plan_s *p = new (std::nothrow) hpnfft_plan_s();
+    if (!p) return HPNFFT_ENOMEM;
+    p->B = B;
+    p->m = m;
+    p->prec = precision;
+    p->window = window;
+    p->sigma = sigma;
+    p->flags = flags;
+    p->b = kb_shape(sigma);
+    p->inv_peak = 1.0 / kb_peak(m, p->b);
+    p->hx.resize(B);
+    p->keys.resize(B);
+    long long Mtot = 0, Ftot = 0;
+    for (int b = 0; b < B; ++b) {
+        Xform &X = p->hx[b];
+        std::memset(&X, 0, sizeof(X));
+        if (M[b] < 1) { delete p; return HPNFFT_EINVAL; }
+        for (int d = 0; d < 3; ++d) {
+            int64_t Nt = N[3 * b + d];
+            if (Nt < 2 || Nt % 2 != 0 || Nt > kMaxN) { delete p; return HPNFFT_EINVAL; }
+            double nv = sigma * (double)Nt;
+            long nt = std::lround(nv);
+            if (std::fabs(nv - (double)nt) > 1e-9 * nv || nt % 2 != 0 || !is_2a3b(nt) || nt < 2 * m ||
+                nt > kMaxN || nt < Nt) {
+                delete p;
+                return HPNFFT_EINVAL;
+            }
+            X.N[d] = (int)Nt;
+            X.n[d] = (int)nt;
+            p->maxn = std::max(p->maxn, (int)nt);
+        }
+        X.M = M[b];
+        X.poff = Mtot;
+        X.foff = Ftot;
+        Mtot += M[b];
+        Ftot += (long long)X.N[0] * X.N[1] * X.N[2];
+    }
+    if (Mtot >= (1LL << 31)) { delete p; return HPNFFT_EINVAL; }
+    p->Mtot = Mtot;
+    p->Ftot = Ftot;
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+        p->cus = cus;
+    p->til = default_tiling(p);
+    build_layout(p);
+    *out = p;
+    return HPNFFT_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+extern "C" {
+
+const char *hpnfft_strerror(int status)
+{
+    switch (status) {
+    case HPNFFT_OK: return "success";
+    case HPNFFT_EINVAL: return "invalid argument";
+    case HPNFFT_EDOMAIN: return "point outside [-1/2,1/2)^d or not finite";
+    case HPNFFT_ENOMEM: return "out of memory or workspace too small";
+    case HPNFFT_EHIP: return "HIP runtime error";
+    case HPNFFT_ESTATE: return "call out of order";
+    default: return "unknown status";
+    }
+}
+
+int hpnfft_plan_create(hpnfft_plan *out, int d, const int64_t *N, int64_t M, double sigma, int m, int window,
+                       int precision, unsigned flags)
+{
+    if (d != 3) return HPNFFT_EINVAL;
+    return create_common(out, 1, N, &M, sigma, m, window, precision, flags);
+}
+
+int hpnfft_batch_create(hpnfft_batch *out, int B, const int64_t *N, const int64_t *M, double sigma, int m,
+                        int window, int precision, unsigned flags)
+{
+    return create_common(out, B, N, M, sigma, m, window, precision, flags);
+}
+
+int hpnfft_plan_destroy(hpnfft_plan p)
+{
+    if (!p) return HPNFFT_OK;
+    if (p->gexec) hipGraphExecDestroy(p->gexec);
+    if (p->graph) hipGraphDestroy(p->graph);
+    delete p;
+    return HPNFFT_OK;
+}
+
+int hpnfft_set_stream(hpnfft_plan p, void *stream)
+{
+    if (!p) return HPNFFT_EINVAL;
+    p->stream = (hipStream_t)stream;
+    return HPNFFT_OK;
+}
+
+int hpnfft_set_tiles(hpnfft_plan p, int tile, int slab, int threads)
+{
+    if (!p) return HPNFFT_EINVAL;
+    Tiling t = p->til;
+    if (tile) t.T = tile;
+    if (slab) t.Zs = slab;
+    if (threads) t.threads = threads;
+    if (!tiling_fits(p, t)) return HPNFFT_EINVAL;
+    p->til = t;
+    build_layout(p);
+    p->have_ws = false;
+    p->have_points = false;
+    return HPNFFT_OK;
+}
+
+int hpnfft_get_tiles(hpnfft_plan p, int *tile, int *slab, int *threads)
+{
+    if (!p) return HPNFFT_EINVAL;
+    if (tile) *tile = p->til.T;
+    if (slab) *slab = p->til.Zs;
+    if (threads) *threads = p->til.threads;
+    return HPNFFT_OK;
+}
+
+int hpnfft_workspace_size(hpnfft_plan p, size_t *bytes)
+{
+    if (!p || !bytes) return HPNFFT_EINVAL;
+    *bytes = p->L.total;
+    return HPNFFT_OK;
+}
+
+int hpnfft_set_workspace(hpnfft_plan p, void *dev_ptr, size_t bytes)
+{
+    if (!p || !dev_ptr) return HPNFFT_EINVAL;
+    if (((uintptr_t)dev_ptr) % 256) return HPNFFT_EINVAL;
+    if (bytes < p->L.total) return HPNFFT_ENOMEM;
+    p->ws = (char *)dev_ptr;
+    p->ws_bytes = bytes;
+    p->have_points = false;
+    int rc = upload_tables(p);
+    p->have_ws = rc == HPNFFT_OK;
+    return rc;
+}
+
+static int set_points_any(hpnfft_plan p, const double *x, const float *x32)
+{
+    if (!p || (!x && !x32)) return HPNFFT_EINVAL;
+    if (!p->have_ws) return HPNFFT_ESTATE;
+    p->have_points = false;
+    // keep a float64 copy of the points (used again by the autotuner)
+    double *xs = p->at<double>(p->L.xs);
+    if (x) {
+        HCHECK(hipMemcpyAsync(xs, x, (size_t)p->Mtot * 24, hipMemcpyDeviceToDevice, p->stream));
+    } else {
+        // promote float32 coordinates exactly: stage through the us buffer
+        std::vector<float> h((size_t)p->Mtot * 3);
+        HCHECK(hipMemcpyAsync(h.data(), x32, h.size() * 4, hipMemcpyDeviceToHost, p->stream));
+        HCHECK(hipStreamSynchronize(p->stream));
+        std::vector<double> hd(h.begin(), h.end());
+        HCHECK(hipMemcpyAsync(xs, hd.data(), hd.size() * 8, hipMemcpyHostToDevice, p->stream));
+        HCHECK(hipStreamSynchronize(p->stream));
+    }
+    int rc = bin_points(p);
+    p->have_points = rc == HPNFFT_OK;
+    return rc;
+}
+
+int hpnfft_set_points(hpnfft_plan p, const double *x) { return set_points_any(p, x, nullptr); }
+int hpnfft_set_points_f32(hpnfft_plan p, const float *x) { return set_points_any(p, nullptr, x); }
+int hpnfft_batch_set_points(hpnfft_batch p, const double *x) { return set_points_any(p, x, nullptr); }
+
+int hpnfft_adjoint(hpnfft_plan p, const void *f, void *fhat)
+{
+    if (!p || !f || !fhat) return HPNFFT_EINVAL;
+    if (!p->have_points) return HPNFFT_ESTATE;
+    return p->prec == HPNFFT_F32 ? run_adjoint<float>(p, f, fhat) : run_adjoint<double>(p, f, fhat);
+}
+
+int hpnfft_forward(hpnfft_plan p, const void *fhat, void *f)
+{
+    if (!p || !f || !fhat) return HPNFFT_EINVAL;
+    if (!p->have_points) return HPNFFT_ESTATE;
+    return p->prec == HPNFFT_F32 ? run_forward<float>(p, fhat, f) : run_forward<double>(p, fhat, f);
+}
+
+int hpnfft_batch_adjoint(hpnfft_batch p, const void *f, void *fhat) { return hpnfft_adjoint(p, f, fhat); }
+int hpnfft_batch_forward(hpnfft_batch p, const void *fhat, void *f) { return hpnfft_forward(p, fhat, f); }
+
+int hpnfft_adjoint_backward(hpnfft_plan p, const void *f, const void *gfhat, void *grad_f, void *grad_x)
+{
+    if (!p || !gfhat) return HPNFFT_EINVAL;
+    if (!p->grad()) return HPNFFT_EINVAL;
+    if (grad_x && !f) return HPNFFT_EINVAL;
+    if (!p->have_points) return HPNFFT_ESTATE;
+    if (!grad_f && !grad_x) return HPNFFT_OK;
+    return p->prec == HPNFFT_F32 ? run_backward<float>(p, f, gfhat, grad_f, grad_x)
+                                 : run_backward<double>(p, f, gfhat, grad_f, grad_x);
+}
+
+int hpnfft_ewald_recip(hpnfft_plan p, const void *S, double L, double alpha, double *energy_dev, void *gbar)
+{
+    if (!p || !S || !energy_dev || p->B != 1) return HPNFFT_EINVAL;
+    if (!(L > 0.0) || !(alpha > 0.0)) return HPNFFT_EINVAL;
+    if (!p->have_ws) return HPNFFT_ESTATE;
+    const Xform &X = p->hx[0];
+    double *part = p->at<double>(p->L.ewald);
+    int nb = (int)(((long long)X.N[0] * X.N[1] * X.N[2] + 255) / 256);
+    hipError_t e = p->prec == HPNFFT_F32
+                       ? launch_ewald<float>(S, X, L, alpha, part, nb, energy_dev, gbar, p->stream)
+                       : launch_ewald<double>(S, X, L, alpha, part, nb, energy_dev, gbar, p->stream);
+    return hip_status(e);
+}
+
+int hpnfft_plan_info(hpnfft_plan p, int64_t *n_out, int64_t *M_out)
+{
+    if (!p) return HPNFFT_EINVAL;
+    if (n_out)
+        for (int d = 0; d < 3; ++d) n_out[d] = p->hx[0].n[d];
+    if (M_out) *M_out = p->Mtot;
+    return HPNFFT_OK;
+}
+
+int hpnfft_batch_offsets(hpnfft_batch p, int b, int64_t *point_offset, int64_t *freq_offset)
+{
+    if (!p || b < 0 || b >= p->B) return HPNFFT_EINVAL;
+    if (point_offset) *point_offset = p->hx[b].poff;
+    if (freq_offset) *freq_offset = p->hx[b].foff;
+    return HPNFFT_OK;
+}
+
+int hpnfft_batch_capture(hpnfft_batch p, const void *f, void *fhat)
+{
+    if (!p || !f || !fhat) return HPNFFT_EINVAL;
+    if (!p->have_points) return HPNFFT_ESTATE;
+    if (!p->stream) return HPNFFT_EINVAL;  // capture needs a non-default stream
+    if (p->gexec) {
+        hipGraphExecDestroy(p->gexec);
+        p->gexec = nullptr;
+    }
+    if (p->graph) {
+        hipGraphDestroy(p->graph);
+        p->graph = nullptr;
+    }
+    // attribute setup outside the capture: one eager run
+    int rc = hpnfft_adjoint(p, f, fhat);
+    if (rc) return rc;
+    HCHECK(hipStreamSynchronize(p->stream));
+    HCHECK(hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal));
+    rc = hpnfft_adjoint(p, f, fhat);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(p->stream, &g);
+    if (rc) {
+        if (g) hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) return HPNFFT_EHIP;
+    p->graph = g;
+    HCHECK(hipGraphInstantiate(&p->gexec, g, nullptr, nullptr, 0));
+    return HPNFFT_OK;
+}
+
+int hpnfft_batch_launch(hpnfft_batch p)
+{
+    if (!p) return HPNFFT_EINVAL;
+    if (!p->gexec) return HPNFFT_ESTATE;
+    return hip_status(hipGraphLaunch(p->gexec, p->stream));
+}
+
+int hpnfft_autotune(hpnfft_plan p, void *scratch_f, void *scratch_fhat, int *tile, int *slab, int *threads)
+{
+    if (!p || !scratch_f || !scratch_fhat) return HPNFFT_EINVAL;
+    if (!p->have_points) return HPNFFT_ESTATE;
+    // candidates that fit the attached workspace
+    std::vector<Tiling> cand;
+    for (int T : {8, 12, 16, 24, 32})
+        for (int Zs : {8, 16, 32})
+            for (int th : {512, 1024}) {
+                Tiling t{T, Zs, th};
+                if (!tiling_fits(p, t)) continue;
+                Tiling keep = p->til;
+                p->til = t;
+                build_layout(p);
+                size_t need = p->L.total;
+                p->til = keep;
+                if (need <= p->ws_bytes) cand.push_back(t);
+            }
+    // the stored float64 points survive re-layouts only if their offset is
+    // unchanged; keep a host copy instead
+    std::vector<double> hx((size_t)p->Mtot * 3);
+    HCHECK(hipMemcpyAsync(hx.data(), p->at<double>(p->L.xs), hx.size() * 8, hipMemcpyDeviceToHost,
+                          p->stream));
+    HCHECK(hipStreamSynchronize(p->stream));
+    auto install = [&](Tiling t) -> int {
+        p->til = t;
+        build_layout(p);
+        int rc = upload_tables(p);
+        if (rc) return rc;
+        HCHECK(hipMemcpyAsync(p->at<double>(p->L.xs), hx.data(), hx.size() * 8, hipMemcpyHostToDevice,
+                              p->stream));
+        rc = bin_points(p);
+        p->have_points = rc == HPNFFT_OK;
+        return rc;
+    };
+    Tiling best = p->til;
+    double best_t = 1e30;
+    hipEvent_t e0, e1;
+    HCHECK(hipEventCreate(&e0));
+    HCHECK(hipEventCreate(&e1));
+    for (const Tiling &t : cand) {
+        if (install(t)) continue;
+        bool ok = true;
+        for (int w = 0; w < 2 && ok; ++w)
+            ok = hpnfft_adjoint(p, scratch_f, scratch_fhat) == 0 && hpnfft_forward(p, scratch_fhat, scratch_f) == 0;
+        if (!ok) continue;
+        hipEventRecord(e0, p->stream);
+        for (int r = 0; r < 3 && ok; ++r)
+            ok = hpnfft_adjoint(p, scratch_f, scratch_fhat) == 0 && hpnfft_forward(p, scratch_fhat, scratch_f) == 0;
+        hipEventRecord(e1, p->stream);
+        hipEventSynchronize(e1);
+        float ms = 0;
+        hipEventElapsedTime(&ms, e0, e1);
+        if (ok && ms < best_t) {
+            best_t = ms;
+            best = t;
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    int rc = install(best);
+    if (tile) *tile = best.T;
+    if (slab) *slab = best.Zs;
+    if (threads) *threads = best.threads;
+    return rc;
+}
+
+int hpnfft_window_eval(int m, double sigma, int64_t count, const double *t, double *phi, double *dphi)
+{
+    if (m < 1 || m > 8 || !(sigma >= 1.0) || count < 0 || (count && (!t || !phi))) return HPNFFT_EINVAL;
+    double b = kb_shape(sigma), ip = 1.0 / kb_peak(m, b);
+    for (int64_t i = 0; i < count; ++i) {
+        double a = std::fabs(t[i]);
+        phi[i] = a > m ? 0.0 : kb_phi(t[i], m, b, ip);
+        if (dphi) dphi[i] = a > m ? 0.0 : kb_dphi(t[i], m, b, ip);
+    }
+    return HPNFFT_OK;
+}
+
+int hpnfft_window_rolloff(int m, double sigma, int64_t n, int64_t N, double *out)
+{
+    if (m < 1 || m > 8 || !(sigma >= 1.0) || n < 2 || N < 2 || N > n || !out) return HPNFFT_EINVAL;
+    double b = kb_shape(sigma), ip = 1.0 / kb_peak(m, b);
+    for (int64_t k = -N / 2; k < N / 2; ++k) out[k + N / 2] = 1.0 / kb_phihat(k, n, m, b, ip);
+    return HPNFFT_OK;
+}
+
+}  // extern "C"

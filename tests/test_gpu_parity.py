@@ -1,0 +1,237 @@
+"""GPU parity: the HIP path against the FP64 oracle (direct Eq. (5) / Eq. (6)).
+
+Tolerances (relative l2, Eq. (9)):
+  * FP64 path: the Kaiser-Bessel aliasing/truncation bound
+    4 pi (sqrt(m) + m)(1 - 1/sigma)^(1/4) exp(-2 pi m sqrt(1 - 1/sigma))
+    (Potts-Steidl-Tasche), floored at 1e-13 for rounding; at m = 8,
+    sigma = 2 this is 4.2e-14, so the 1e-12 target holds with margin.
+  * FP32 path: the same bound floored at 2e-6 (float rounding of the grid
+    sums and the FFT), and never above the 1e-5 target at m >= 4.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def kb_bound(m, sigma=2.0):
+    a = math.sqrt(1 - 1 / sigma)
+    return 4 * math.pi * (math.sqrt(m) + m) * (1 - 1 / sigma) ** 0.25 * math.exp(-2 * math.pi * m * a)
+
+
+def tol(m, prec, sigma=2.0):
+    return max(kb_bound(m, sigma), 1e-13 if prec == "f64" else 2e-6)
+
+
+@pytest.fixture(scope="module")
+def H():
+    from paper_2001_01583_amd import hpnfft
+    assert torch.cuda.is_available()
+    hpnfft._load()
+    return hpnfft
+
+
+def _cd(prec):
+    return torch.complex128 if prec == "f64" else torch.complex64
+
+
+def run_adjoint(H, N, x, f, m, prec, sigma=2.0, tiles=None):
+    plan = H.Plan(N, x.shape[0], sigma=sigma, m=m, precision=prec, tiles=tiles)
+    xt = torch.from_numpy(x).cuda()
+    plan.set_points(xt)
+    ft = torch.from_numpy(f.astype(np.complex128 if prec == "f64" else np.complex64)).cuda()
+    out = plan.adjoint(ft)
+    torch.cuda.synchronize()
+    return out.cpu().numpy().astype(np.complex128), plan
+
+
+def run_forward(H, N, x, fh, m, prec, sigma=2.0, tiles=None):
+    plan = H.Plan(N, x.shape[0], sigma=sigma, m=m, precision=prec, tiles=tiles)
+    plan.set_points(torch.from_numpy(x).cuda())
+    ft = torch.from_numpy(fh.astype(np.complex128 if prec == "f64" else np.complex64)).cuda()
+    out = plan.forward(ft)
+    torch.cuda.synchronize()
+    return out.cpu().numpy().astype(np.complex128), plan
+
+
+def f_used(f, prec):
+    """The values the GPU received (FP32 runs: the same draws rounded)."""
+    return f.astype(np.complex64).astype(np.complex128) if prec == "f32" else f
+
+
+def test_c1_adjoint_fp64_m8(H, oracle_mod):
+    """16^3 bandwidth, 4096 uniform points, m = 8, sigma = 2 (the precision
+    experiment of Section 4): rel-l2 <= 1e-12 against the full direct NDFT."""
+    c = W.c1()
+    got, _ = run_adjoint(H, c["N"], c["x"], c["f"], 8, "f64")
+    ref = oracle_mod.ndft_adjoint(c["N"], c["x"], c["f"])
+    err = oracle_mod.rel_l2(got, ref)
+    print("C1 adjoint fp64 m=8 rel-l2 %.3e" % err)
+    assert err <= 1e-12
+
+
+def test_c1_forward_fp64_m8(H, oracle_mod):
+    c = W.c1()
+    g = W.rng(101)
+    fh = W.complex_normal(16 ** 3, g).reshape(16, 16, 16)
+    got, _ = run_forward(H, c["N"], c["x"], fh, 8, "f64")
+    ref = oracle_mod.ndft_forward(c["N"], c["x"], fh)
+    err = oracle_mod.rel_l2(got, ref)
+    print("C1 forward fp64 m=8 rel-l2 %.3e" % err)
+    assert err <= 1e-12
+
+
+@pytest.mark.parametrize("m", [4, 6])
+def test_c1_fp32(H, oracle_mod, m):
+    c = W.c1()
+    got, _ = run_adjoint(H, c["N"], c["x"], c["f"], m, "f32")
+    ref = oracle_mod.ndft_adjoint(c["N"], c["x"], f_used(c["f"], "f32"))
+    err = oracle_mod.rel_l2(got, ref)
+    print("C1 adjoint fp32 m=%d rel-l2 %.3e" % (m, err))
+    assert err <= min(1e-5, tol(m, "f32"))
+    g = W.rng(102)
+    fh = W.complex_normal(16 ** 3, g).reshape(16, 16, 16)
+    got, _ = run_forward(H, c["N"], c["x"], fh, m, "f32")
+    ref = oracle_mod.ndft_forward(c["N"], c["x"], f_used(fh, "f32"))
+    err = oracle_mod.rel_l2(got, ref)
+    print("C1 forward fp32 m=%d rel-l2 %.3e" % (m, err))
+    assert err <= min(1e-5, tol(m, "f32"))
+
+
+@pytest.mark.parametrize("N,M,m,prec", [
+    ((16, 12, 24), 1, 4, "f64"),
+    ((16, 12, 24), 7, 3, "f64"),
+    ((8, 16, 32), 1000, 2, "f64"),
+    ((16, 16, 16), 3000, 5, "f64"),
+    ((24, 16, 8), 2500, 7, "f64"),
+    ((32, 32, 32), 5000, 8, "f64"),
+    ((16, 12, 24), 777, 4, "f32"),
+    ((48, 16, 32), 4000, 4, "f32"),
+    ((16, 16, 16), 2000, 8, "f32"),
+])
+def test_shapes_ragged(H, oracle_mod, N, M, m, prec):
+    """Non-cubic bandwidths (incl. radix-3 grids), ragged point counts, every
+    window size, both directions."""
+    g = W.rng(200 + M)
+    x = W.uniform_points(M, 3, g)
+    f = W.complex_normal(M, g)
+    got, _ = run_adjoint(H, N, x, f, m, prec)
+    ref = oracle_mod.ndft_adjoint(N, x, f_used(f, prec))
+    e1 = oracle_mod.rel_l2(got, ref)
+    fh = W.complex_normal(int(np.prod(N)), g).reshape(N)
+    got2, _ = run_forward(H, N, x, fh, m, prec)
+    ref2 = oracle_mod.ndft_forward(N, x, f_used(fh, prec))
+    e2 = oracle_mod.rel_l2(got2, ref2)
+    print("N=%s M=%d m=%d %s adjoint %.3e forward %.3e (tol %.1e)" % (N, M, m, prec, e1, e2, tol(m, prec)))
+    assert e1 <= tol(m, prec) and e2 <= tol(m, prec)
+
+
+def test_points_on_cell_boundaries_and_domain_edges(H, oracle_mod):
+    """Points exactly on grid planes, at -1/2 and just below +1/2 (the tie of
+    the window cut-off and the periodic wrap)."""
+    N = (16, 16, 16)
+    n = 32
+    g = W.rng(301)
+    base = W.uniform_points(500, 3, g)
+    grid = (g.integers(-n // 2, n // 2, size=(300, 3)) / n).astype(np.float64)
+    edges = np.array([[-0.5, -0.5, -0.5], [np.nextafter(0.5, 0), -0.5, 0.0],
+                      [0.0, np.nextafter(0.5, 0), np.nextafter(-0.5, 0)], [0.0, 0.0, 0.0]])
+    x = np.concatenate([base, grid, edges])
+    f = W.complex_normal(x.shape[0], g)
+    got, _ = run_adjoint(H, N, x, f, 8, "f64")
+    ref = oracle_mod.ndft_adjoint(N, x, f)
+    err = oracle_mod.rel_l2(got, ref)
+    print("edges rel-l2 %.3e" % err)
+    # a cut-off tie drops a tap of relative weight b m / sinh(b m) = 3e-15
+    assert err <= 1e-12
+
+
+def test_dense_cluster(H, oracle_mod):
+    """Many points in a few cells (load imbalance, long register windows)."""
+    N = (16, 16, 16)
+    g = W.rng(302)
+    x = W.wrap_unit(0.21 + 0.004 * g.standard_normal((6000, 3)))
+    x = np.concatenate([x, W.uniform_points(200, 3, g)])
+    f = W.complex_normal(x.shape[0], g)
+    for prec, m in (("f64", 8), ("f32", 4)):
+        got, _ = run_adjoint(H, N, x, f, m, prec)
+        ref = oracle_mod.ndft_adjoint(N, x, f_used(f, prec))
+        err = oracle_mod.rel_l2(got, ref)
+        print("cluster %s rel-l2 %.3e" % (prec, err))
+        assert err <= tol(m, prec)
+
+
+def test_adjoint_identity_on_gpu(H):
+    """<A f, g> = <f, A^H g> with both sides from the GPU (Section 1)."""
+    N = (16, 24, 16)
+    g = W.rng(303)
+    x = W.uniform_points(3000, 3, g)
+    plan = H.Plan(N, 3000, m=8, precision="f64")
+    plan.set_points(torch.from_numpy(x).cuda())
+    f = torch.from_numpy(W.complex_normal(3000, g)).cuda()
+    h = torch.from_numpy(W.complex_normal(int(np.prod(N)), g).reshape(N)).cuda()
+    Af = plan.adjoint(f)
+    AHh = plan.forward(h)
+    lhs = torch.vdot(h.reshape(-1), Af.reshape(-1)).item()
+    rhs = torch.vdot(AHh, f).item()
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+
+
+def test_subcell_sum_eq8_on_gpu(H):
+    """Eq. (8): transforms of the points of 4 spatial subcells sum to the
+    transform of all points (one GPU standing in for 4 nodes)."""
+    N = (16, 16, 16)
+    g = W.rng(304)
+    x = W.uniform_points(4000, 3, g)
+    f = W.complex_normal(4000, g)
+    whole, _ = run_adjoint(H, N, x, f, 8, "f64")
+    cell = np.floor((x[:, 0] + 0.5) * 4).astype(int)
+    parts = 0
+    for i in range(4):
+        sel = cell == i
+        p, _ = run_adjoint(H, N, x[sel], f[sel], 8, "f64")
+        parts = parts + p
+    assert np.linalg.norm(parts - whole) <= 1e-13 * np.linalg.norm(whole)
+
+
+def test_out_of_domain_points_rejected(H):
+    plan = H.Plan((16, 16, 16), 10, m=4, precision="f64")
+    g = W.rng(305)
+    for bad in (0.5, -0.5000001, float("nan"), float("inf")):
+        x = W.uniform_points(10, 3, g)
+        x[3, 1] = bad
+        with pytest.raises(H.HpnfftError) as ei:
+            plan.set_points(torch.from_numpy(x).cuda())
+        assert ei.value.code == H.EDOMAIN
+        with pytest.raises(H.HpnfftError) as ei:
+            plan.adjoint(torch.zeros(10, dtype=torch.complex128, device="cuda"))
+        assert ei.value.code == H.ESTATE
+    x = W.uniform_points(10, 3, g)
+    plan.set_points(torch.from_numpy(x).cuda())   # recovers after a good call
+
+
+@pytest.mark.parametrize("prec,m", [("f64", 8), ("f32", 4)])
+def test_c2_full_size_sampled(H, oracle_mod, prec, m):
+    """N = 64^3, M = 2^20 (the benchmark workload) in the benchmark's launch
+    configuration: 96 sampled frequencies and 96 sampled points against the
+    oracle evaluated one by one."""
+    c = W.c2()
+    g = W.rng(306)
+    x, f, fh = c["x"], c["f"], c["fhat"]
+    got, plan = run_adjoint(H, c["N"], x, f, m, prec)
+    kidx = W.sample_indices(64 ** 3, 96, g)
+    ref = oracle_mod.ndft_adjoint(c["N"], x, f_used(f, prec), kidx=kidx)
+    e1 = oracle_mod.rel_l2(got.reshape(-1)[kidx], ref)
+    ft = torch.from_numpy(fh.astype(np.complex128 if prec == "f64" else np.complex64)).cuda()
+    got2 = plan.forward(ft).cpu().numpy().astype(np.complex128)
+    jidx = W.sample_indices(x.shape[0], 96, g)
+    ref2 = oracle_mod.ndft_forward(c["N"], x, f_used(fh, prec), jidx=jidx)
+    e2 = oracle_mod.rel_l2(got2[jidx], ref2)
+    print("C2 %s m=%d adjoint %.3e forward %.3e" % (prec, m, e1, e2))
+    target = 1e-12 if prec == "f64" else 1e-5
+    assert e1 <= target and e2 <= target
