@@ -1,0 +1,362 @@
+#!/usr/bin/env python
+"""Benchmark of the NFFT hot path on one MI355X.
+
+Workload: bandwidth N = 64^3 (grid n = 128^3, sigma = 2), M = 2^20 points
+i.i.d. uniform in [-1/2, 1/2)^3, complex values with re, im ~ N(0, 1).
+One step = the whole path once: set_points (bin, sort, window tables),
+adjoint (Eq. (5): spread, FFT, roll-off/crop) and forward (Eq. (6):
+roll-off/pad, inverse FFT, interpolate).
+
+Headline: the float32 path at m = 4 (relative l2 error <= 1e-5 against the
+FP64 oracle).  Reported beside it: the float64 path at m = 8 (<= 1e-12).
+value = M / (seconds per step).
+
+Prints one JSON line on stdout.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "NFFT points/s at rel-err 1e-5 FP32 vs FP64 plain (1e-12); spread HBM GB/s"
+PEAK_HBM_GBS = 8000.0
+PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}
+N = (64, 64, 64)
+M = 1 << 20
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def phase_work(prec: str, m: int, n: int, Nb: int, Mp: int):
+    """Algorithmic work per launch of each phase: (kind, amount).
+    alu phases count 2 FMA = 4 flops per window tap ((2m)^3 taps per point);
+    hbm phases count bytes each launch must read plus write once."""
+    r = 8 if prec == "f64" else 4
+    C = 2 * r
+    n3, N3 = n ** 3, Nb ** 3
+    taps = Mp * (2 * m) ** 3
+    return {
+        "spread": ("alu", taps * 4.0),
+        "interp": ("alu", taps * 4.0),
+        "fft_a0": ("hbm", (n3 + n * n * Nb) * C),
+        "fft_a1": ("hbm", (n * n * Nb + n * Nb * Nb) * C),
+        "fft_a2": ("hbm", (n * Nb * Nb + N3) * C),
+        "fft_f0": ("hbm", (N3 + n * Nb * Nb) * C),
+        "fft_f1": ("hbm", (n * Nb * Nb + n * n * Nb) * C),
+        "fft_f2": ("hbm", (n * n * Nb + n3) * C),
+        "gather": ("hbm", Mp * (4 + 2 * C)),
+        "scatter": ("hbm", Mp * (4 + 2 * C)),
+    }
+
+
+def spread_bytes(prec: str, m: int, n: int, Mp: int) -> float:
+    """Spread algorithmic HBM bytes: per point its value, plane index and
+    3 x 2m window weights in; the grid written once."""
+    r = 8 if prec == "f64" else 4
+    return Mp * (2 * r + 4 + 3 * 2 * m * r) + n ** 3 * 2 * r
+
+
+def src_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("k_spread.hip", "k_fft.hip", "k_misc.hip"):
+        with open(os.path.join(ROOT, "paper_2001_01583_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str, prec: str):
+    """Bytes per launch from the committed rocprofv3 counter summary, if it was
+    taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic_c2.json")
+    try:
+        with open(path) as fh:
+            d = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if d.get("src_hash") != src_hash():
+        return None
+    return d.get("kernels", {}).get("%s_%s" % (kernel, prec))
+
+
+COPY_BYTES = 1 << 30
+
+
+def copy_calibration(torch):
+    """A plain device copy of known size (1 GiB read + 1 GiB written) for
+    calibrating the FETCH_SIZE / WRITE_SIZE counters."""
+    a = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
+
+
+def summarize_counters(fetch_dir: str, write_dir: str, out_json: str, command: str):
+    """Per-kernel average FETCH_SIZE and WRITE_SIZE (KiB per dispatch) from two
+    rocprofv3 --pmc runs, each scaled by the copy kernel's measured/known ratio."""
+    import csv
+    import glob
+
+    def load(d, counter):
+        rows = []
+        for fn in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            with open(fn) as fh:
+                rows += [r for r in csv.DictReader(fh) if r.get("Counter_Name") == counter]
+        agg = {}
+        for r in rows:
+            name = r["Kernel_Name"]
+            agg.setdefault(name, []).append(float(r["Counter_Value"]))
+        return {k: sum(v) / len(v) for k, v in agg.items()}
+
+    fetch = load(fetch_dir, "FETCH_SIZE")
+    write = load(write_dir, "WRITE_SIZE")
+
+    def copy_kib(d):
+        cands = [(k, v) for k, v in d.items() if "copy" in k.lower() or "elementwise" in k.lower()]
+        return max(cands, key=lambda kv: kv[1]) if cands else (None, None)
+
+    ck, cf = copy_kib(fetch)
+    wk, cw = copy_kib(write)
+    known_kib = COPY_BYTES / 1024.0
+    f_scale = known_kib / cf if cf else None
+    w_scale = known_kib / cw if cw else None
+    kern = {}
+    names = {"k_spread": "spread", "k_interp": "interp", "k_fft": "fft"}
+    for full in set(fetch) | set(write):
+        short = None
+        for key, label in names.items():
+            if key in full:
+                short = label
+        if short is None:
+            continue
+        prec = "f32" if "<float" in full else "f64"
+        if short == "fft":
+            continue
+        fb = fetch.get(full, 0.0) * 1024.0 * (f_scale or 1.0)
+        wb = write.get(full, 0.0) * 1024.0 * (w_scale or 1.0)
+        kern["%s_%s" % (short, prec)] = round(fb + wb)
+    out = {"src_hash": src_hash(), "command": command, "copy_kernel_fetch": ck, "copy_kernel_write": wk,
+           "fetch_scale": f_scale, "write_scale": w_scale, "kernels": kern,
+           "raw_kib": {"fetch": fetch, "write": write}}
+    with open(out_json, "w") as fh:
+        json.dump(out, fh, indent=1, sort_keys=True)
+    print(json.dumps({k: v for k, v in out.items() if k != "raw_kib"}, indent=1))
+
+
+def run_path(H, torch, W, data, prec: str, m: int, steps: int, warmup: int):
+    dev = torch.device("cuda", 0)
+    cd = torch.complex128 if prec == "f64" else torch.complex64
+    plan = H.Plan(N, M, m=m, precision=prec, device=dev)
+    x = torch.from_numpy(data["x"]).to(dev)
+    f = torch.from_numpy(data["f"]).to(dev).to(cd)
+    fh_in = torch.from_numpy(data["fhat"]).to(dev).to(cd)
+    fh_out = torch.empty(N, dtype=cd, device=dev)
+    f_out = torch.empty(M, dtype=cd, device=dev)
+
+    def step():
+        plan.set_points(x)
+        plan.adjoint(f, out=fh_out)
+        plan.forward(fh_in, out=f_out)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    plan.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    phases = plan.profile_read()
+    plan.profile(False)
+    ms_step = (t1 - t0) * 1e3 / steps
+    return dict(plan=plan, ms_per_step=ms_step, phases=phases, fhat=fh_out.cpu().numpy(),
+                fout=f_out.cpu().numpy(), tiles=plan.tiles)
+
+
+def summarize(res, prec, m):
+    n = 2 * N[0]
+    work = phase_work(prec, m, n, N[0], M)
+    table = {}
+    for name, (ms, cnt) in res["phases"].items():
+        per = ms / max(cnt, 1)
+        row = {"ms_per_launch": round(per, 5), "launches": cnt}
+        if name in work:
+            kind, amount = work[name]
+            if kind == "alu":
+                row["tflops"] = round(amount / (per * 1e-3) / 1e12, 3)
+            else:
+                row["gbs"] = round(amount / (per * 1e-3) / 1e9, 1)
+        table[name] = row
+    kernel_ms = {k: v[0] for k, v in res["phases"].items() if k in work}
+    dom = max(kernel_ms, key=kernel_ms.get)
+    kind, amount = work[dom]
+    ms, cnt = res["phases"][dom]
+    per_s = ms / cnt * 1e-3
+    if kind == "alu":
+        ach, peak, unit = amount / per_s / 1e12, PEAK_TFLOPS[prec], "TFLOP/s"
+    else:
+        ach, peak, unit = amount / per_s / 1e9, PEAK_HBM_GBS, "GB/s"
+    traffic = measured_traffic(dom, prec)
+    roof = {"bound": kind, "kernel": dom, "achieved": round(ach, 3), "peak": peak, "unit": unit,
+            "frac": round(ach / peak, 4), "traffic": traffic}
+    sp_ms, sp_cnt = res["phases"].get("spread", (0.0, 0))
+    spread_gbs = spread_bytes(prec, m, n, M) / (sp_ms / max(sp_cnt, 1) * 1e-3) / 1e9 if sp_cnt else None
+    return table, roof, spread_gbs
+
+
+def cpu_baseline(data, gpu):
+    """The FP64 oracle (direct Eq. (5) and Eq. (6)) on a bounded sample of the
+    same workload, timed on the host cores; the same samples give the GPU
+    results' relative l2 errors."""
+    import numpy as np
+
+    import oracle
+    import workloads as W
+    oracle.build()
+    g = W.rng(99)
+    x, f, fhat = data["x"], data["f"], data["fhat"]
+    nall = N[0] * N[1] * N[2]
+    # calibrate: a few outputs, then size the sample to ~12 s (adjoint) + ~6 s (forward)
+    k8 = W.sample_indices(nall, 8, g)
+    t0 = time.perf_counter()
+    oracle.ndft_adjoint(N, x, f, kidx=k8)
+    t_k = (time.perf_counter() - t0) / 8
+    nk = int(max(16, min(4096, 12.0 / max(t_k, 1e-6))))
+    kidx = W.sample_indices(nall, nk, g)
+    j8 = W.sample_indices(M, 8, g)
+    t0 = time.perf_counter()
+    oracle.ndft_forward(N, x, fhat, jidx=j8)
+    t_j = (time.perf_counter() - t0) / 8
+    nj = int(max(16, min(8192, 6.0 / max(t_j, 1e-6))))
+    jidx = W.sample_indices(M, nj, g)
+
+    errs = {}
+    t0 = time.perf_counter()
+    ref_a = oracle.ndft_adjoint(N, x, f, kidx=kidx)
+    ta = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    ref_f = oracle.ndft_forward(N, x, fhat, jidx=jidx)
+    tf = time.perf_counter() - t0
+    for key, res in gpu.items():
+        prec = key.split("_")[0]
+        if prec == "f32":
+            fa = f.astype(np.complex64).astype(np.complex128)
+            fb = fhat.astype(np.complex64).astype(np.complex128)
+            ra = oracle.ndft_adjoint(N, x, fa, kidx=kidx[:64])
+            rf = oracle.ndft_forward(N, x, fb, jidx=jidx[:64])
+            ea = oracle.rel_l2(res["fhat"].reshape(-1)[kidx[:64]].astype(np.complex128), ra)
+            ef = oracle.rel_l2(res["fout"][jidx[:64]].astype(np.complex128), rf)
+        else:
+            ea = oracle.rel_l2(res["fhat"].reshape(-1)[kidx], ref_a)
+            ef = oracle.rel_l2(res["fout"][jidx], ref_f)
+        errs[key] = {"adjoint": float("%.3e" % ea), "forward": float("%.3e" % ef)}
+    t_adj_full = ta * nall / nk
+    t_fwd_full = tf * M / nj
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    base = {"value": round(M / (t_adj_full + t_fwd_full), 1), "unit": "points/s", "cores": cores,
+            "kind": "oracle",
+            "sample": "FP64 direct NDFT: %d sampled frequencies of the adjoint (Eq. 5, %.1f s) and %d "
+                      "sampled points of the forward (Eq. 6, %.1f s) over all %d points; full-transform "
+                      "time extrapolated linearly (cost is exactly proportional to outputs)"
+                      % (nk, ta, nj, tf, M)}
+    return base, errs
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="run a 1 GiB device copy first (counter calibration for rocprofv3 --pmc runs)")
+    ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write profiles/traffic_c2.json from two rocprofv3 --pmc output folders")
+    ap.add_argument("--counters-command", default="", help="command line recorded with the summary")
+    args = ap.parse_args()
+    if args.summarize_counters:
+        summarize_counters(args.summarize_counters[0], args.summarize_counters[1],
+                           os.path.join(ROOT, "profiles", "traffic_c2.json"), args.counters_command)
+        return
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU's share only: this build has no multi-GPU path "
+              "(the paper's subcell decomposition across GPUs is described, not run); use --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import workloads as W
+    from paper_2001_01583_amd import hpnfft as H
+
+    if not torch.cuda.is_available():
+        log("no GPU visible")
+        sys.exit(1)
+    data = W.c2()
+    log("workload ready: N=%s M=%d" % (N, M))
+    if args.copy_calib:
+        copy_calibration(torch)
+    gpu = {}
+    gpu["f32_m4"] = run_path(H, torch, W, data, "f32", 4, args.steps, args.warmup)
+    log("f32 m=4: %.3f ms/step" % gpu["f32_m4"]["ms_per_step"])
+    if not args.no_fp64:
+        gpu["f64_m8"] = run_path(H, torch, W, data, "f64", 8, max(3, args.steps // 2), args.warmup)
+        log("f64 m=8: %.3f ms/step" % gpu["f64_m8"]["ms_per_step"])
+
+    main_res = gpu["f32_m4"]
+    table, roof, spread_gbs = summarize(main_res, "f32", 4)
+    out = {
+        "metric": METRIC,
+        "value": round(M / (main_res["ms_per_step"] * 1e-3), 1),
+        "unit": "points/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(main_res["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "NFFT N=64^3 (n=128^3, sigma=2), M=2^20 uniform points, complex64, "
+                               "Kaiser-Bessel m=4; step = set_points + adjoint (Eq. 5) + forward (Eq. 6)",
+                   "N": list(N), "M": M, "m": 4, "sigma": 2.0, "tiles": list(main_res["tiles"])},
+        "roofline": roof,
+        "spread_gbs_algorithmic": None if spread_gbs is None else round(spread_gbs, 1),
+        "phases": table,
+    }
+    if "f64_m8" in gpu:
+        r64 = gpu["f64_m8"]
+        t64, roof64, sp64 = summarize(r64, "f64", 8)
+        out["fp64_m8"] = {"value": round(M / (r64["ms_per_step"] * 1e-3), 1), "unit": "points/s",
+                          "ms_per_step": round(r64["ms_per_step"], 4), "dtype": "f64",
+                          "tiles": list(r64["tiles"]), "roofline": roof64,
+                          "spread_gbs_algorithmic": None if sp64 is None else round(sp64, 1),
+                          "phases": t64}
+        out["fp32_speedup_over_fp64"] = round(r64["ms_per_step"] / main_res["ms_per_step"], 3)
+    if not args.no_cpu_baseline:
+        base, errs = cpu_baseline(data, gpu)
+        out["cpu_baseline"] = base
+        out["rel_l2_sampled"] = errs
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

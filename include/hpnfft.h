@@ -147,6 +147,18 @@ int hpnfft_adjoint_backward(hpnfft_plan plan, const void *f, const void *grad_fh
 int hpnfft_ewald_recip(hpnfft_plan plan, const void *S, double L, double alpha,
                        double *energy_dev, void *gbar);
 
+/* Real-space Ewald sum of Eq. (11) (Section 5) by direct pairs under the
+ * minimum-image convention, for ions r (device, M x 3 float64, coordinates in
+ * a cubic box of side L) with charges q (device, M float64):
+ *   energy = 1/2 sum_{i != j, r_ij < rcut} q_i q_j erfc(alpha r_ij) / r_ij
+ * written to *energy_dev (device double); forces_dev (M x 3, may be NULL)
+ * receives F_i = -dE/dr_i.  Requires rcut <= L/2 (one image per pair), so
+ * alpha must make erfc(alpha rcut) negligible.  scratch_dev: ceil(M/256)
+ * doubles of device memory.  Asynchronous on `stream` (a hipStream_t). */
+int hpnfft_ewald_real(const double *r, const double *q, int64_t M, double L, double alpha,
+                      double rcut, double *energy_dev, double *forces_dev,
+                      double *scratch_dev, void *stream);
+
 /* Tiling autotuner: times the adjoint and forward for each candidate tiling
  * on the current points and keeps the fastest.  Needs points and a workspace
  * at least as large as the largest candidate needs (query with
@@ -177,6 +189,34 @@ int hpnfft_batch_launch(hpnfft_batch batch);
 /* Element offsets of transform b in the packed point and frequency arrays. */
 int hpnfft_batch_offsets(hpnfft_batch batch, int b, int64_t *point_offset,
                          int64_t *freq_offset);
+
+/* ---- live kernel timing ------------------------------------------------ */
+/* Phases timed with HIP events recorded on the plan's stream around each
+ * kernel group (the FFT phases cover one pass each). */
+#define HPNFFT_PH_SET_POINTS 0   /* whole set_points: bin, sort, window tables, work list */
+#define HPNFFT_PH_ZERO       1   /* clearing of grids / outputs                          */
+#define HPNFFT_PH_GATHER     2   /* values into sorted point order                       */
+#define HPNFFT_PH_SPREAD     3   /* Spreading (adjoint)                                  */
+#define HPNFFT_PH_FFT_A0     4   /* adjoint FFT pass along dim 2 (+ crop)                */
+#define HPNFFT_PH_FFT_A1     5   /* adjoint FFT pass along dim 1 (+ crop)                */
+#define HPNFFT_PH_FFT_A2     6   /* adjoint FFT pass along dim 0 (+ crop, Scaling)       */
+#define HPNFFT_PH_FFT_F0     7   /* forward FFT pass along dim 0 (Subdividing + pad)     */
+#define HPNFFT_PH_FFT_F1     8   /* forward FFT pass along dim 1 (+ pad)                 */
+#define HPNFFT_PH_FFT_F2     9   /* forward FFT pass along dim 2 (+ pad)                 */
+#define HPNFFT_PH_INTERP    10   /* Interpolating (forward)                              */
+#define HPNFFT_PH_SCATTER   11   /* results back to the caller's point order             */
+#define HPNFFT_PH_GRAD      12   /* gradient interpolation (backward)                    */
+#define HPNFFT_PH_GRAD_FIN  13   /* gradient epilogue                                    */
+#define HPNFFT_NPHASES      14
+/* Enable (1) or disable (0) timing; either way previous records are dropped.
+ * While enabled every transform call records two events per phase. */
+int hpnfft_profile(hpnfft_plan plan, int enable);
+/* Wait for the recorded events, add their elapsed milliseconds per phase to
+ * ms[HPNFFT_NPHASES] and the number of launches to counts[HPNFFT_NPHASES]
+ * (either may be NULL), then drop the records. */
+int hpnfft_profile_read(hpnfft_plan plan, double *ms, int64_t *counts);
+/* Short name of a phase ("spread", "fft_a0", ...); "" when out of range. */
+const char *hpnfft_phase_name(int phase);
 
 /* ---- host-only helpers (no GPU needed) ------------------------------ */
 /* Kaiser-Bessel window in grid units t = n x - l, normalised to phi(0) = 1:

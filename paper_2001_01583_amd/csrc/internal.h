@@ -49,24 +49,65 @@ struct Tiling {
     int threads;  // threads per workgroup of spread / interp
 };
 
-// LDS bytes of the spread (comp = compensated float path) and interpolation.
-inline size_t spread_lds_bytes(int T, int Zs, int M2, size_t real_bytes, bool comp)
+__host__ __device__ constexpr size_t align16(size_t v) { return (v + 15) & ~(size_t)15; }
+
+// Record of one sorted point (16-byte aligned, contiguous per z-line run):
+//   [psi: 3 x 2m window values (dim 0 rotated, dims 1, 2 natural)]
+//   [f: the point's value, complex]  [plane index c0 (int)]  [pad]
+//   [dpsi: 3 x 2m window derivatives, gradient plans only]
+__host__ __device__ constexpr size_t rec_prefix(int M2, size_t R) { return align16(3 * M2 * R + 2 * R + 4); }
+__host__ __device__ constexpr size_t rec_size(int M2, size_t R, bool grad)
 {
-    size_t P = (size_t)(T + M2 - 1);
-    return (size_t)Zs * P * P * 2 * real_bytes * (comp ? 2 : 1) + 64;
+    return rec_prefix(M2, R) + (grad ? align16(3 * M2 * R) : 0);
 }
-inline size_t interp_lds_bytes(int T, int Zs, int M2, size_t real_bytes, int threads, bool grad)
+__host__ __device__ constexpr size_t rec_off_f(int M2, size_t R) { return 3 * M2 * R; }
+__host__ __device__ constexpr size_t rec_off_pz(int M2, size_t R) { return 3 * M2 * R + 2 * R; }
+
+// LDS layout of the spread / interpolation kernels (bytes from the start of
+// the dynamic LDS block).  kind: 0 spread, 1 interpolation, 2 gradient.
+//   [tile][stage: cap records][slot_p: cap ints][run_p0: 3T^2][run_soff: 3T^2+1]
+//   [scan scratch: 32 ints][interpolation outputs: cap x 2 NO reals]
+constexpr size_t kLdsLimit = 160 * 1024 - 512;
+struct LdsLayout {
+    size_t tile, stage, slot_p, run_p0, run_soff, sh, out, total;
+    int cap;
+};
+__host__ __device__ inline LdsLayout lds_layout(int T, int Zs, int M2, size_t R, int kind, bool comp, int cap)
 {
-    (void)threads;
-    (void)grad;
+    LdsLayout L{};
     size_t P = (size_t)(T + M2 - 1);
-    return (size_t)Zs * P * P * 2 * real_bytes + 64;
+    size_t st = kind == 2 ? rec_size(M2, R, true) : rec_prefix(M2, R);
+    size_t nr = (size_t)3 * T * T;
+    int NO = kind == 2 ? 4 : 1;
+    L.tile = 0;
+    L.stage = align16((size_t)Zs * P * P * 2 * R * ((kind == 0 && comp) ? 2 : 1));
+    L.slot_p = L.stage + (size_t)cap * st;
+    L.run_p0 = L.slot_p + (size_t)cap * 4;
+    L.run_soff = L.run_p0 + nr * 4;
+    L.sh = align16(L.run_soff + (nr + 1) * 4);
+    L.out = L.sh + 32 * 4;
+    L.total = align16(L.out + (kind ? (size_t)cap * 2 * NO * R : 0));
+    L.cap = cap;
+    return L;
+}
+// Largest chunk capacity (points) that fits the LDS; 0 if the tile alone does not.
+inline LdsLayout lds_fit(int T, int Zs, int M2, size_t R, int kind, bool comp)
+{
+    LdsLayout lo = lds_layout(T, Zs, M2, R, kind, comp, 0);
+    if (lo.total > kLdsLimit) return LdsLayout{};
+    size_t st = kind == 2 ? rec_size(M2, R, true) : rec_prefix(M2, R);
+    size_t per = st + 4 + (kind ? 2 * (kind == 2 ? 4 : 1) * R : 0);
+    int cap = (int)((kLdsLimit - lo.total) / per);
+    if (cap > 2048) cap = 2048;
+    while (cap > 0 && lds_layout(T, Zs, M2, R, kind, comp, cap).total > kLdsLimit) --cap;
+    if (cap < 16) return LdsLayout{};
+    return lds_layout(T, Zs, M2, R, kind, comp, cap);
 }
 
 // Threads per workgroup the interpolation kernel is compiled for: float64
 // windows of 2m >= 12 (and the gradient variant from 2m >= 6) need more than
 // the 128 registers a 1024-thread workgroup leaves per lane.
-constexpr int interp_max_threads(int real_bytes, int M2, bool grad)
+__host__ __device__ constexpr int interp_max_threads(int real_bytes, int M2, bool grad)
 {
     return (real_bytes == 8 && (M2 >= 12 || (grad && M2 >= 6))) || (grad && M2 >= 14) ? 512 : 1024;
 }
@@ -84,15 +125,15 @@ hipError_t launch_bin_count(const double *x, const float *xf32, long long M, con
 hipError_t launch_scan(int *data, long long n, int *tmp, hipStream_t s);
 hipError_t launch_bin_scatter(const double *x, const float *xf32, long long M, const Xform &X,
                               int T, int m, const int *cell_start, const int *rank,
-                              int *perm, int *pz, double *us, hipStream_t s);
-hipError_t launch_line_cost(const Xform &X, int T, int Zs, int m, const int *cell_start,
-                            int *cost, hipStream_t s);
+                              int *perm, unsigned char *rec, size_t rec_bytes, size_t off_pz,
+                              double *us, hipStream_t s);
 
 template <typename R>
-hipError_t launch_psi(const double *us, const int *pz, long long M, long long poff, const Xform &X,
-                      int m, double b, double inv_peak, R *psi, R *dpsi, hipStream_t s);
+hipError_t launch_psi(const double *us, long long M, long long poff, const Xform &X, int m, double b,
+                      double inv_peak, unsigned char *rec, size_t rec_bytes, bool grad, hipStream_t s);
 template <typename R>
-hipError_t launch_gather(const void *f, const int *perm, long long total, R *fs, hipStream_t s);
+hipError_t launch_gather(const void *f, const int *perm, long long total, unsigned char *rec,
+                         size_t rec_bytes, size_t off_f, hipStream_t s);
 template <typename R>
 hipError_t launch_scatter(const R *outs, const int *perm, long long total, void *f, hipStream_t s);
 template <typename R>
@@ -100,15 +141,17 @@ hipError_t launch_grad_finish(const R *outs4, const void *f, const int *perm, lo
                               void *grad_f, void *grad_x, hipStream_t s);
 template <typename R>
 hipError_t launch_spread(int m, const Xform *dxf, const SItem *items, int nitems, int *queue,
-                         Tiling t, const R *psi, const R *fs, const int *pz, const int *cell_start,
-                         const Xform *hxf0, hipStream_t s);
+                         Tiling t, const unsigned char *rec, size_t rec_bytes, const int *cell_start,
+                         hipStream_t s);
 template <typename R>
 hipError_t launch_interp(int m, bool grad, const Xform *dxf, const SItem *items, int nitems, int *queue,
-                         Tiling t, const R *psi, const R *dpsi, const int *pz, const int *cell_start,
+                         Tiling t, const unsigned char *rec, size_t rec_bytes, const int *cell_start,
                          R *outs, hipStream_t s);
 template <typename R>
 hipError_t launch_fft(int pass, const Xform *dxf, const FItem *items, int nitems, int max_n,
                       void *fhat_base, hipStream_t s);
+hipError_t launch_ewald_real(const double *r, const double *q, long long M, double L, double alpha,
+                             double rcut, double *partials, double *energy, double *forces, hipStream_t s);
 template <typename R>
 hipError_t launch_ewald(const void *S, const Xform &X, double L, double alpha, double *partials,
                         int nblocks, double *energy, void *gbar, hipStream_t s);

@@ -65,7 +65,8 @@ template <typename XT>
 __global__ void k_bin_scatter(const XT *__restrict__ x, long long M, long long poff, int n0, int n1,
                               int n2, int T, int ntx, const int *__restrict__ cell_start,
                               const int *__restrict__ rank, int *__restrict__ perm,
-                              int *__restrict__ pz, double *__restrict__ us)
+                              unsigned char *__restrict__ rec, size_t rec_bytes, size_t off_pz,
+                              double *__restrict__ us)
 {
     long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= M) return;
@@ -76,78 +77,47 @@ __global__ void k_bin_scatter(const XT *__restrict__ x, long long M, long long p
     for (int t = 0; t < 3; ++t) c[t] = cell_of((double)x[j * 3 + t], n[t], &u[t], &bad);
     long long pos = poff + cell_start[sort_key(c, T, ntx, n0)] + rank[j];
     perm[pos] = (int)(poff + j);
-    pz[pos] = c[0];
+    *reinterpret_cast<int *>(rec + pos * rec_bytes + off_pz) = c[0];
     us[pos * 3 + 0] = u[0];
     us[pos * 3 + 1] = u[1];
     us[pos * 3 + 2] = u[2];
 }
 
-// Window values of one sorted point along one dimension.  Tap t (0..2m-1) of
-// a point in cell c with offset u sits on grid cell c - m + 1 + t, at
-// grid-unit distance u + m - 1 - t.  Along dim 0 the taps are stored rotated:
-// slot s = (c0 - m + 1 + t) mod 2m, so that a register window indexed by
-// plane mod 2m needs no per-point shuffling.
+// Window values of the sorted points, one thread per (point, dimension, tap),
+// written into the point records (consecutive threads write consecutive
+// words).  Tap t (0..2m-1) of a point in cell c with offset u sits on grid
+// cell c - m + 1 + t, at grid-unit distance u + m - 1 - t.  Along dim 0 the
+// taps are stored rotated: slot s = (c0 - m + 1 + t) mod 2m, so that a
+// register window indexed by plane mod 2m needs no per-point shuffling.
 template <typename R>
-__global__ void k_psi(const double *__restrict__ us, const int *__restrict__ pz, long long M,
-                      long long poff, int m, double b, double inv_peak, int n0, int n1, int n2,
-                      R *__restrict__ psi, R *__restrict__ dpsi)
+__global__ void k_psi(const double *__restrict__ us, long long M, long long poff, int m, double b,
+                      double inv_peak, int n0, int n1, int n2, unsigned char *__restrict__ rec,
+                      size_t rec_bytes, int grad)
 {
-    long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= M * 3) return;
-    long long p = poff + g / 3;
-    int dim = (int)(g % 3);
     const int M2 = 2 * m;
+    long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= M * 3 * M2) return;
+    long long p = poff + g / (3 * M2);
+    int rem = (int)(g % (3 * M2));
+    int dim = rem / M2, t = rem - dim * M2;
+    unsigned char *rp = rec + p * rec_bytes;
     double u = us[p * 3 + dim];
-    int rot = 0;
+    int s = t;
     if (dim == 0) {
-        int r = (pz[p] - m + 1) % M2;
-        rot = r < 0 ? r + M2 : r;
+        int c0 = *reinterpret_cast<const int *>(rp + rec_off_pz(M2, sizeof(R)));
+        int r = (c0 - m + 1) % M2;
+        s = t + (r < 0 ? r + M2 : r);
+        if (s >= M2) s -= M2;
     }
     double nd = dim == 0 ? n0 : (dim == 1 ? n1 : n2);
-    R *dst = psi + p * 3 * M2 + dim * M2;
-    R *ddst = dpsi ? dpsi + p * 3 * M2 + dim * M2 : nullptr;
-    for (int t = 0; t < M2; ++t) {
-        double dist = u + (double)(m - 1 - t);
-        int s = t + rot;
-        if (s >= M2) s -= M2;
-        dst[s] = (R)kb_phi(dist, m, b, inv_peak);
-        if (ddst) ddst[s] = (R)(nd * kb_dphi(dist, m, b, inv_peak));
-    }
-}
-
-// Range of cells c0 of a z-line whose taps, shifted by U (U in {-n0, 0, n0}),
-// reach the slab [z0, z0 + zs): taps of cell c0 cover c0 + U - m + 1 .. c0 + U + m.
-__device__ inline void segment_range(int U, int z0, int zs, int m, int n0, int *a, int *b)
-{
-    int lo = z0 - m - U;
-    int hi = z0 + zs + m - 2 - U;
-    *a = lo < 0 ? 0 : lo;
-    *b = hi > n0 - 1 ? n0 - 1 : hi;
-}
-
-// Number of points each line of each (tile, slab) pair processes; used on
-// the host to cut the work into balanced items.
-__global__ void k_line_cost(const int *__restrict__ cell_start, int T, int Zs, int m, int n0,
-                            int ntiles, int nslab, int *__restrict__ cost)
-{
-    long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    long long total = (long long)ntiles * nslab * T * T;
-    if (g >= total) return;
-    int li = (int)(g % (T * T));
-    long long ts = g / (T * T);
-    int slab = (int)(ts % nslab);
-    int tile = (int)(ts / nslab);
-    int z0 = slab * Zs;
-    int zs = min(Zs, n0 - z0);
-    long long lk = (long long)tile * T * T + li;
-    int c = 0;
-    for (int s = -1; s <= 1; ++s) {
-        int a, b;
-        segment_range(s * n0, z0, zs, m, n0, &a, &b);
-        if (a > b) continue;
-        c += cell_start[lk * n0 + b + 1] - cell_start[lk * n0 + a];
-    }
-    cost[g] = c;
+    double dist = u + (double)(m - 1 - t);
+    // evaluated in float64 for both paths (the float path stores the values
+    // rounded once)
+    R *dst = reinterpret_cast<R *>(rp) + dim * M2 + s;
+    *dst = (R)kb_phi(dist, m, b, inv_peak);
+    if (grad)
+        *(reinterpret_cast<R *>(rp + rec_prefix(M2, sizeof(R))) + dim * M2 + s) =
+            (R)(nd * kb_dphi(dist, m, b, inv_peak));
 }
 
 // ---------------------------------------------------------------------------
@@ -235,43 +205,33 @@ hipError_t launch_bin_count(const double *x, const float *xf32, long long M, con
 }
 
 hipError_t launch_bin_scatter(const double *x, const float *xf32, long long M, const Xform &X, int T,
-                              int m, const int *cell_start, const int *rank, int *perm, int *pz,
-                              double *us, hipStream_t s)
+                              int m, const int *cell_start, const int *rank, int *perm, unsigned char *rec,
+                              size_t rec_bytes, size_t off_pz, double *us, hipStream_t s)
 {
     (void)m;
     unsigned nb = (unsigned)((M + 255) / 256);
     if (x)
         hipLaunchKernelGGL(k_bin_scatter<double>, dim3(nb), dim3(256), 0, s, x, M, X.poff, X.n[0],
-                           X.n[1], X.n[2], T, X.ntx, cell_start, rank, perm, pz, us);
+                           X.n[1], X.n[2], T, X.ntx, cell_start, rank, perm, rec, rec_bytes, off_pz, us);
     else
         hipLaunchKernelGGL(k_bin_scatter<float>, dim3(nb), dim3(256), 0, s, xf32, M, X.poff, X.n[0],
-                           X.n[1], X.n[2], T, X.ntx, cell_start, rank, perm, pz, us);
-    return hipGetLastError();
-}
-
-hipError_t launch_line_cost(const Xform &X, int T, int Zs, int m, const int *cell_start, int *cost,
-                            hipStream_t s)
-{
-    long long total = (long long)X.ntx * X.nty * X.nslab * T * T;
-    unsigned nb = (unsigned)((total + 255) / 256);
-    hipLaunchKernelGGL(k_line_cost, dim3(nb), dim3(256), 0, s, cell_start, T, Zs, m, X.n[0],
-                       X.ntx * X.nty, X.nslab, cost);
+                           X.n[1], X.n[2], T, X.ntx, cell_start, rank, perm, rec, rec_bytes, off_pz, us);
     return hipGetLastError();
 }
 
 template <typename R>
-hipError_t launch_psi(const double *us, const int *pz, long long M, long long poff, const Xform &X,
-                      int m, double b, double inv_peak, R *psi, R *dpsi, hipStream_t s)
+hipError_t launch_psi(const double *us, long long M, long long poff, const Xform &X, int m, double b,
+                      double inv_peak, unsigned char *rec, size_t rec_bytes, bool grad, hipStream_t s)
 {
-    unsigned nb = (unsigned)((M * 3 + 255) / 256);
-    hipLaunchKernelGGL(k_psi<R>, dim3(nb), dim3(256), 0, s, us, pz, M, poff, m, b, inv_peak, X.n[0],
-                       X.n[1], X.n[2], psi, dpsi);
+    unsigned nb = (unsigned)((M * 3 * 2 * m + 255) / 256);
+    hipLaunchKernelGGL(k_psi<R>, dim3(nb), dim3(256), 0, s, us, M, poff, m, b, inv_peak, X.n[0], X.n[1],
+                       X.n[2], rec, rec_bytes, grad ? 1 : 0);
     return hipGetLastError();
 }
 
-template hipError_t launch_psi<double>(const double *, const int *, long long, long long, const Xform &,
-                                       int, double, double, double *, double *, hipStream_t);
-template hipError_t launch_psi<float>(const double *, const int *, long long, long long, const Xform &,
-                                      int, double, double, float *, float *, hipStream_t);
+template hipError_t launch_psi<double>(const double *, long long, long long, const Xform &, int, double,
+                                       double, unsigned char *, size_t, bool, hipStream_t);
+template hipError_t launch_psi<float>(const double *, long long, long long, const Xform &, int, double,
+                                      double, unsigned char *, size_t, bool, hipStream_t);
 
 }  // namespace hpnfft

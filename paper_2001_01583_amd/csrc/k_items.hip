@@ -28,73 +28,101 @@ __device__ inline int line_cost(const int *cs_line, int n0, int z0, int zs, int 
     return c;
 }
 
+// One thread per (tile, slab, line); tcost must be zeroed beforehand.
 __global__ void k_tile_cost(const int *__restrict__ cell_start, int n0, int T, int Zs, int m,
                             int ntiles, int nslab, int *__restrict__ tcost,
                             unsigned long long *__restrict__ total)
 {
-    int g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= ntiles * nslab) return;
-    int tile = g / nslab, slab = g % nslab;
-    int z0 = slab * Zs, zs = min(Zs, n0 - z0);
-    int c = 0;
-    for (int li = 0; li < T * T; ++li)
-        c += line_cost(cell_start + ((long long)tile * T * T + li) * n0, n0, z0, zs, m);
-    tcost[g] = c;
-    atomicAdd(total, (unsigned long long)c);
+    __shared__ unsigned long long blk;
+    if (threadIdx.x == 0) blk = 0;
+    __syncthreads();
+    long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    long long n = (long long)ntiles * nslab * T * T;
+    if (g < n) {
+        int li = (int)(g % (T * T));
+        long long ts = g / (T * T);
+        int slab = (int)(ts % nslab), tile = (int)(ts / nslab);
+        int z0 = slab * Zs, zs = min(Zs, n0 - z0);
+        int c = line_cost(cell_start + ((long long)tile * T * T + li) * n0, n0, z0, zs, m);
+        atomicAdd(&tcost[ts], c);
+        atomicAdd(&blk, (unsigned long long)c);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) atomicAdd(total, blk);
 }
 
+// One wavefront per (tile, slab): the T*T line costs are prefix-summed across
+// the lanes and the pair is cut wherever the running cost crosses a multiple of
+// the cap (a pair within the cap becomes one item).
 __global__ void k_make_items(const int *__restrict__ cell_start, int xf, int n0, int T, int Zs, int m,
                              int ntiles, int nslab, const int *__restrict__ tcost,
                              const unsigned long long *__restrict__ total, int cap_div, int min_cap,
                              int max_items, SItem *__restrict__ items, int *__restrict__ nitems,
                              int *__restrict__ overflow)
 {
-    int g = blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int g = (int)(((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
     if (g >= ntiles * nslab) return;
-    int tile = g / nslab, slab = g % nslab;
-    int z0 = slab * Zs, zs = min(Zs, n0 - z0);
+    const int tile = g / nslab, slab = g % nslab;
+    const int z0 = slab * Zs, zs = min(Zs, n0 - z0);
     long long capl = (long long)(*total / (unsigned long long)cap_div);
-    int cap = capl < min_cap ? min_cap : (int)capl;
-    int c = tcost[g];
-    // a pair whose lines hold no points is skipped entirely
-    if (c <= T * T) return;
+    const int cap = capl < min_cap ? min_cap : (int)capl;
+    const int c = tcost[g];
+    const int nl = T * T;
     auto emit = [&](int lb, int le) {
         int idx = atomicAdd(nitems, 1);
         if (idx >= max_items) {
             atomicOr(overflow, 1);
             return;
         }
-        SItem it;
-        it.xf = xf;
-        it.tile = tile;
-        it.slab = slab;
-        it.lb = lb;
-        it.le = le;
-        it.pad0 = it.pad1 = it.pad2 = 0;
-        items[idx] = it;
+        SItem itm;
+        itm.xf = xf;
+        itm.tile = tile;
+        itm.slab = slab;
+        itm.lb = lb;
+        itm.le = le;
+        itm.pad0 = itm.pad1 = itm.pad2 = 0;
+        items[idx] = itm;
     };
+    if (c <= nl) return;  // no points in any line of this pair
     if (c <= cap) {
-        emit(0, T * T);
+        if (lane == 0) emit(0, nl);
         return;
     }
-    int lb = 0, acc = 0;
-    for (int li = 0; li < T * T; ++li) {
-        acc += line_cost(cell_start + ((long long)tile * T * T + li) * n0, n0, z0, zs, m);
-        if (acc >= cap) {
-            emit(lb, li + 1);
-            lb = li + 1;
-            acc = 0;
+    // lines in consecutive blocks of 64: lane k of block handles line base + k
+    int carry = 0;       // cost before this block
+    int lb = 0;          // start of the open item
+    for (int base = 0; base < nl; base += 64) {
+        int li = base + lane;
+        int lc = li < nl ? line_cost(cell_start + ((long long)tile * nl + li) * n0, n0, z0, zs, m) : 0;
+        int incl = lc;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            int y = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += y;
         }
+        int before = carry + incl - lc, after = carry + incl;
+        // a cut after line li when the running cost crosses a multiple of cap
+        bool cut = li < nl && (after / cap) != (before / cap) && li + 1 < nl;
+        unsigned long long mask = __ballot(cut);
+        while (mask) {
+            int k = __ffsll((long long)mask) - 1;
+            mask &= mask - 1;
+            int le = base + k + 1;
+            if (lane == 0) emit(lb, le);
+            lb = le;
+        }
+        carry += __shfl(incl, 63, 64);
     }
-    if (lb < T * T && acc > 0) emit(lb, T * T);
+    if (lane == 0 && lb < nl) emit(lb, nl);
 }
 
 hipError_t launch_tile_cost(const int *cell_start, const Xform &X, int T, int Zs, int m, int *tcost,
                             unsigned long long *total, hipStream_t s)
 {
-    int n = X.ntx * X.nty * X.nslab;
-    hipLaunchKernelGGL(k_tile_cost, dim3((n + 127) / 128), dim3(128), 0, s, cell_start, X.n[0], T, Zs, m,
-                       X.ntx * X.nty, X.nslab, tcost, total);
+    long long n = (long long)X.ntx * X.nty * X.nslab * T * T;
+    hipLaunchKernelGGL(k_tile_cost, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, cell_start, X.n[0], T,
+                       Zs, m, X.ntx * X.nty, X.nslab, tcost, total);
     return hipGetLastError();
 }
 
@@ -102,9 +130,9 @@ hipError_t launch_make_items(const int *cell_start, int xf, const Xform &X, int 
                              const int *tcost, const unsigned long long *total, int cap_div, int min_cap,
                              int max_items, SItem *items, int *nitems, int *overflow, hipStream_t s)
 {
-    int n = X.ntx * X.nty * X.nslab;
-    hipLaunchKernelGGL(k_make_items, dim3((n + 127) / 128), dim3(128), 0, s, cell_start, xf, X.n[0], T, Zs,
-                       m, X.ntx * X.nty, X.nslab, tcost, total, cap_div, min_cap, max_items, items,
+    long long n = (long long)X.ntx * X.nty * X.nslab * 64;  // one wavefront per pair
+    hipLaunchKernelGGL(k_make_items, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, cell_start, xf, X.n[0],
+                       T, Zs, m, X.ntx * X.nty, X.nslab, tcost, total, cap_div, min_cap, max_items, items,
                        nitems, overflow);
     return hipGetLastError();
 }

@@ -29,13 +29,14 @@ hipError_t launch_zero(void *p, size_t bytes, hipStream_t s)
 
 template <typename R>
 __global__ void k_gather(const R *__restrict__ f, const int *__restrict__ perm, long long total,
-                         R *__restrict__ fs)
+                         unsigned char *__restrict__ rec, size_t rec_bytes, size_t off_f)
 {
     long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= total) return;
     long long j = perm[p];
-    fs[2 * p] = f[2 * j];
-    fs[2 * p + 1] = f[2 * j + 1];
+    R *d = reinterpret_cast<R *>(rec + p * rec_bytes + off_f);
+    d[0] = f[2 * j];
+    d[1] = f[2 * j + 1];
 }
 
 template <typename R>
@@ -70,11 +71,12 @@ __global__ void k_grad_finish(const R *__restrict__ outs4, const R *__restrict__
 }
 
 template <typename R>
-hipError_t launch_gather(const void *f, const int *perm, long long total, R *fs, hipStream_t s)
+hipError_t launch_gather(const void *f, const int *perm, long long total, unsigned char *rec,
+                         size_t rec_bytes, size_t off_f, hipStream_t s)
 {
     if (total <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_gather<R>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s,
-                       (const R *)f, perm, total, fs);
+                       (const R *)f, perm, total, rec, rec_bytes, off_f);
     return hipGetLastError();
 }
 
@@ -160,8 +162,82 @@ hipError_t launch_ewald(const void *S, const Xform &X, double L, double alpha, d
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Eq. (11) real-space Ewald sum by direct pairs under the minimum-image
+// convention (valid when erfc(alpha r) is negligible beyond half the box):
+//   U = 1/2 sum_i sum_{j != i} q_i q_j erfc(alpha r_ij) / r_ij   (r_ij < rcut)
+//   F_i = sum_j q_i q_j [erfc(alpha r)/r + 2 alpha/sqrt(pi) exp(-alpha^2 r^2)] d_ij / r^2
+// One thread per ion i; the j loop streams through LDS tiles of 256 ions.
+constexpr int kRealTile = 256;
+
+__global__ __launch_bounds__(kRealTile) void k_ewald_real(const double *__restrict__ r,
+                                                          const double *__restrict__ q, long long M,
+                                                          double L, double alpha, double rcut2,
+                                                          double *__restrict__ part,
+                                                          double *__restrict__ forces)
+{
+    __shared__ double sx[kRealTile], sy[kRealTile], sz[kRealTile], sq[kRealTile];
+    __shared__ double red[kRealTile];
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool valid = i < M;
+    const double xi = valid ? r[3 * i] : 0.0, yi = valid ? r[3 * i + 1] : 0.0, zi = valid ? r[3 * i + 2] : 0.0;
+    const double qi = valid ? q[i] : 0.0;
+    const double c2 = 2.0 * alpha / sqrt(M_PI), invL = 1.0 / L;
+    double e = 0.0, fx = 0.0, fy = 0.0, fz = 0.0;
+    for (long long j0 = 0; j0 < M; j0 += kRealTile) {
+        long long j = j0 + threadIdx.x;
+        __syncthreads();
+        sx[threadIdx.x] = j < M ? r[3 * j] : 0.0;
+        sy[threadIdx.x] = j < M ? r[3 * j + 1] : 0.0;
+        sz[threadIdx.x] = j < M ? r[3 * j + 2] : 0.0;
+        sq[threadIdx.x] = j < M ? q[j] : 0.0;
+        __syncthreads();
+        const int nj = (int)min((long long)kRealTile, M - j0);
+        for (int t = 0; t < nj; ++t) {
+            if (j0 + t == i) continue;
+            double dx = xi - sx[t], dy = yi - sy[t], dz = zi - sz[t];
+            dx -= L * rint(dx * invL);
+            dy -= L * rint(dy * invL);
+            dz -= L * rint(dz * invL);
+            double d2 = dx * dx + dy * dy + dz * dz;
+            if (d2 >= rcut2) continue;
+            double d = sqrt(d2);
+            double qq = qi * sq[t];
+            double ec = erfc(alpha * d) / d;
+            e += 0.5 * qq * ec;
+            double g = qq * (ec + c2 * exp(-alpha * alpha * d2)) / d2;
+            fx += g * dx;
+            fy += g * dy;
+            fz += g * dz;
+        }
+    }
+    if (valid && forces) {
+        forces[3 * i] = fx;
+        forces[3 * i + 1] = fy;
+        forces[3 * i + 2] = fz;
+    }
+    red[threadIdx.x] = e;
+    __syncthreads();
+    for (int off = kRealTile / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+hipError_t launch_ewald_real(const double *r, const double *q, long long M, double L, double alpha,
+                             double rcut, double *partials, double *energy, double *forces, hipStream_t s)
+{
+    int nb = (int)((M + kRealTile - 1) / kRealTile);
+    hipLaunchKernelGGL(k_ewald_real, dim3(nb), dim3(kRealTile), 0, s, r, q, M, L, alpha, rcut * rcut, partials,
+                       forces);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kEwThreads), 0, s, partials, nb, energy);
+    return hipGetLastError();
+}
+
 #define HPNFFT_INST(R)                                                                             \
-    template hipError_t launch_gather<R>(const void *, const int *, long long, R *, hipStream_t);  \
+    template hipError_t launch_gather<R>(const void *, const int *, long long, unsigned char *,      \
+                                         size_t, size_t, hipStream_t);                             \
     template hipError_t launch_scatter<R>(const R *, const int *, long long, void *, hipStream_t); \
     template hipError_t launch_grad_finish<R>(const R *, const void *, const int *, long long,     \
                                               void *, void *, hipStream_t);                        \

@@ -1,27 +1,33 @@
-// Spreading (Section 3, the Spreading step of Algorithm 2) and interpolation
+// Spreading (the Spreading step of Algorithm 2, Section 3) and interpolation
 // (the Interpolating step of Algorithm 5) on gfx950.
 //
 // The paper assigns one thread per point and adds every window tap to the
 // grid with an atomic operation.  Here points are sorted by z-line (fixed
-// cells in dims 1 and 2, increasing cell along dim 0), and a work item is
-// one tile of T x T lines restricted to a slab of Zs planes along dim 0.
+// cells in dims 1 and 2, increasing cell along dim 0), and a work item is a
+// tile of T x T lines restricted to a slab of Zs planes along dim 0.
 //
-//   * lane <-> one (dy, dx) tap row of the point's (2m)^2 rows; a wavefront
-//     holds 64 rows (a row group), the (2m)^2 rows need ceil((2m)^2/64);
-//   * along dim 0 every lane keeps a register window of 2m complex values,
-//     slot s holding grid plane q with q = s (mod 2m).  Consecutive points
-//     of a line share the lane's row, so their taps accumulate in registers;
-//     a plane leaves the window (spread: one LDS add) only when the sweep
-//     has passed it.  Window weights along dim 0 are stored pre-rotated per
-//     point, so slot indices are compile-time constants;
-//   * the LDS tile holds the slab's planes with a halo of 2m-1 cells in dims
-//     1 and 2 and is flushed to the grid with one atomic add per cell;
-//   * interpolation loads the tile from the grid, slides the same register
-//     window (loading a plane when it enters) and reduces the (2m)^2 row
-//     partials of each point across the wavefront.
+// Per work item a workgroup
+//   1. lists the item's runs: for every line up to three contiguous ranges of
+//      sorted points (the periodic images whose taps reach the slab), and
+//      numbers their points 0 .. S-1 in run order;
+//   2. for each chunk of `cap` of those points, copies the points' records
+//      (window weights, value, plane index) into LDS with all threads at once
+//      (coalesced 16-byte copies, many loads in flight);
+//   3. sweeps the chunk: one wavefront per (run piece, row group); lane <->
+//      one (dy, dx) tap row of the point's (2m)^2 rows, and along dim 0 a
+//      register window of 2m complex values, slot s holding plane q with
+//      q = s (mod 2m).  Consecutive points of a line share the lane's row, so
+//      their taps accumulate in registers; a plane leaves the window (spread:
+//      one LDS add per row) only when the sweep has passed it.  Weights along
+//      dim 0 are stored pre-rotated per point, so slot indices are constants;
+//   4. flushes the LDS tile (the slab's planes with a halo of 2m-1 cells in
+//      dims 1 and 2) to the grid with one atomic add per cell.
+// Interpolation loads the tile from the grid, slides the same register
+// window (loading a plane when it enters) and reduces the (2m)^2 row partials
+// of each point across the wavefront with DPP moves.
 //
-// Work items are taken from a device queue (one atomic per item) so heavy
-// tiles and uneven batches balance across the 256 compute units.
+// Work items come from a device queue (one atomic per item) so heavy tiles
+// and uneven batches balance across the compute units.
 #include <algorithm>
 
 #include "internal.h"
@@ -42,15 +48,98 @@ __device__ inline void seg_range(int U, int z0, int zs, int m, int n0, int *a, i
     *b = hi > n0 - 1 ? n0 - 1 : hi;
 }
 
+template <int CTRL>
+__device__ inline float dpp_mov(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
+}
+template <int CTRL>
+__device__ inline double dpp_mov(double v)
+{
+    long long b = __double_as_longlong(v);
+    int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), CTRL, 0xF, 0xF, true);
+    int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, true);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sum over the 64 lanes; every lane receives the same total.  Within a row of
+// 16 lanes: xor-1 and xor-2 quad permutations, then half-row and row mirrors;
+// across rows: two lane-xor shuffles.
 template <typename R>
 __device__ inline R wave_sum(R v)
 {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    v += dpp_mov<0xB1>(v);   // quad_perm [1,0,3,2]
+    v += dpp_mov<0x4E>(v);   // quad_perm [2,3,0,1]
+    v += dpp_mov<0x141>(v);  // row_half_mirror
+    v += dpp_mov<0x140>(v);  // row_mirror
+    v += __shfl_xor(v, 16, 64);
+    v += __shfl_xor(v, 32, 64);
     return v;
 }
 
-// Fetch the next work item index for the whole workgroup.
+// Compensated float add into an LDS cell holding (sum, compensation) as one
+// 64-bit word: TwoSum (Knuth) of the stored sum and v gives the new sum and
+// its exact rounding error, which joins the compensation; the pair is
+// published with a 64-bit compare-and-swap.  (gfx950's native LDS float32
+// atomic add is about 13x slower than this loop when uncontended.)
+__device__ inline void lds_add_comp(unsigned long long *cell, float v)
+{
+    unsigned long long old = *reinterpret_cast<volatile unsigned long long *>(cell);
+    for (;;) {
+        float sm = __uint_as_float((unsigned int)old);
+        float cp = __uint_as_float((unsigned int)(old >> 32));
+        float t = sm + v;
+        float bp = t - sm;
+        float e = (sm - (t - bp)) + (v - bp);
+        unsigned long long nw = (unsigned long long)__float_as_uint(t) |
+                                ((unsigned long long)__float_as_uint(cp + e) << 32);
+        unsigned long long prev = atomicCAS(cell, old, nw);
+        if (prev == old) return;
+        old = prev;
+    }
+}
+
+// Exclusive scan of one int per thread over the workgroup (<= 1024 threads);
+// sh: 32 ints of LDS.  Contains barriers: call from all threads.
+__device__ inline int block_excl_scan(int v, int *sh, int *total)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    int x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        int y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) sh[wave] = x;
+    __syncthreads();
+    if (wave == 0) {
+        int w = lane < nw ? sh[lane] : 0;
+#pragma unroll
+        for (int o = 1; o < 16; o <<= 1) {
+            int y = __shfl_up(w, o, 64);
+            if (lane >= o) w += y;
+        }
+        if (lane < nw) sh[16 + lane] = w;
+    }
+    __syncthreads();
+    int before = wave > 0 ? sh[16 + wave - 1] : 0;
+    *total = sh[16 + nw - 1];
+    __syncthreads();
+    return before + x - v;
+}
+
+// Largest r in [0, nr) with soff[r] <= v (soff non-decreasing, soff[nr] > v).
+__device__ inline int find_run(const int *soff, int nr, int v)
+{
+    int lo = 0, hi = nr;
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (soff[mid] <= v) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
 __device__ inline int next_item(int *queue, int *s_item)
 {
     __syncthreads();
@@ -59,74 +148,167 @@ __device__ inline int next_item(int *queue, int *s_item)
     return *s_item;
 }
 
+// Geometry of one work item.
+struct ItemGeom {
+    int n0, n1, n2, X0, Y0, z0, zs, ry0, nrows, lb, le, tile;
+    long long poff, key_off;
+};
+
+__device__ inline ItemGeom item_geom(const SItem &W, const Xform &X, int T, int Zs, int M2)
+{
+    ItemGeom g;
+    g.n0 = X.n[0];
+    g.n1 = X.n[1];
+    g.n2 = X.n[2];
+    g.X0 = (W.tile % X.ntx) * T;
+    g.Y0 = (W.tile / X.ntx) * T;
+    g.z0 = W.slab * Zs;
+    g.zs = min(Zs, g.n0 - g.z0);
+    g.ry0 = W.lb / T;
+    g.nrows = (W.le - 1) / T + M2 - g.ry0;
+    g.lb = W.lb;
+    g.le = W.le;
+    g.tile = W.tile;
+    g.poff = X.poff;
+    g.key_off = X.key_off;
+    return g;
+}
+
+// Step 1: run list of the item.  Run r = 3 * (line - lb) + (segment + 1);
+// run_p0[r] = first sorted point, run_soff = exclusive prefix of run sizes
+// (run_soff[nr] = S).  Returns S.  Contains barriers.
+template <int M2>
+__device__ inline int build_runs(const ItemGeom &g, int T, const int *__restrict__ cell_start, int *run_p0,
+                                 int *run_soff, int *sh)
+{
+    constexpr int m = M2 / 2;
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int nr = 3 * (g.le - g.lb);
+    const int k = (nr + nthr - 1) / nthr;
+    int local = 0;
+    for (int i = 0; i < k; ++i) {
+        int r = tid * k + i;
+        if (r >= nr) break;
+        int li = g.lb + r / 3, U = (r % 3 - 1) * g.n0;
+        int ly = li / T, lx = li % T;
+        int cnt = 0, p0 = 0;
+        if (g.Y0 + ly < g.n1 && g.X0 + lx < g.n2) {
+            int a, b;
+            seg_range(U, g.z0, g.zs, m, g.n0, &a, &b);
+            if (a <= b) {
+                const int *cs = cell_start + g.key_off + ((long long)g.tile * T * T + li) * g.n0;
+                p0 = cs[a];
+                cnt = cs[b + 1] - p0;
+            }
+        }
+        run_p0[r] = (int)(g.poff + p0);
+        run_soff[r] = cnt;
+        local += cnt;
+    }
+    int total;
+    int base = block_excl_scan(local, sh, &total);
+    for (int i = 0; i < k; ++i) {
+        int r = tid * k + i;
+        if (r >= nr) break;
+        int c = run_soff[r];
+        run_soff[r] = base;
+        base += c;
+    }
+    if (tid == 0) run_soff[nr] = total;
+    __syncthreads();
+    return total;
+}
+
+// Step 2: slot -> sorted point map of the chunk [cs, cs + cnt) and the copy of
+// the records (st16 16-byte units each) into LDS.  Contains barriers.
+__device__ inline void stage_chunk(int cs, int cnt, int nr, const int *run_p0, const int *run_soff, int *slot_p,
+                                   uint4 *stage, int st16, const uint4 *__restrict__ rec, int rs16)
+{
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    for (int s = tid; s < cnt; s += nthr) {
+        int v = cs + s;
+        int r = find_run(run_soff, nr, v);
+        slot_p[s] = run_p0[r] + (v - run_soff[r]);
+    }
+    __syncthreads();
+    const int tot = cnt * st16;
+    for (int e = tid; e < tot; e += nthr) {
+        int sl = e / st16, q = e - sl * st16;
+        stage[e] = rec[(size_t)slot_p[sl] * rs16 + q];
+    }
+    __syncthreads();
+}
+
 // ---------------------------------------------------------------------------
-// Spread.  COMP: float path with compensated LDS sums -- every LDS add
-// returns the old value, the exact rounding error of the add is recovered
-// with TwoSum and accumulated in a second array.
+// Spread.  COMP: float path with per-bin compensated sums: every LDS tile
+// cell is a (sum, compensation) pair updated by lds_add_comp.  The float64
+// path adds with the native LDS float64 atomic.
 template <typename R, int M2, bool COMP>
 __global__ __launch_bounds__(1024) void k_spread(const Xform *__restrict__ xfs,
                                                  const SItem *__restrict__ items, int nitems,
-                                                 int *__restrict__ queue, int T, int Zs,
-                                                 const R *__restrict__ psi, const R *__restrict__ fs,
-                                                 const int *__restrict__ pz,
+                                                 int *__restrict__ queue, int T, int Zs, int cap,
+                                                 const uint4 *__restrict__ rec, int rs16,
                                                  const int *__restrict__ cell_start)
 {
     constexpr int m = M2 / 2;
     constexpr int ROWS = M2 * M2;
     constexpr int NRG = (ROWS + 63) / 64;
-    extern __shared__ __align__(16) unsigned char smem[];
+    constexpr int ST16 = (int)(rec_prefix(M2, sizeof(R)) / 16);
+    constexpr int OFF_F = (int)(rec_off_f(M2, sizeof(R)) / sizeof(R));
+    constexpr int OFF_PZ = (int)(rec_off_pz(M2, sizeof(R)) / 4);
+    extern __shared__ uint4 smem16[];
+    unsigned char *smem = reinterpret_cast<unsigned char *>(smem16);
     __shared__ int s_item;
+    const LdsLayout LL = lds_layout(T, Zs, M2, sizeof(R), 0, COMP, cap);
     const int P = T + M2 - 1;
     const int plane = P * P;
-    R *acc = reinterpret_cast<R *>(smem);
-    R *cmp = acc + (size_t)Zs * plane * 2;
+    R *acc = reinterpret_cast<R *>(smem + LL.tile);
+    unsigned long long *pairs = reinterpret_cast<unsigned long long *>(smem + LL.tile);
+    uint4 *stage = reinterpret_cast<uint4 *>(smem + LL.stage);
+    int *slot_p = reinterpret_cast<int *>(smem + LL.slot_p);
+    int *run_p0 = reinterpret_cast<int *>(smem + LL.run_p0);
+    int *run_soff = reinterpret_cast<int *>(smem + LL.run_soff);
+    int *sh = reinterpret_cast<int *>(smem + LL.sh);
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int wave = tid >> 6, lane = tid & 63, nwaves = nthr >> 6;
 
     for (int it = next_item(queue, &s_item); it < nitems; it = next_item(queue, &s_item)) {
-        const SItem W = items[it];
-        const Xform &X = xfs[W.xf];
-        const int n0 = X.n[0], n1 = X.n[1], n2 = X.n[2];
-        const int X0 = (W.tile % X.ntx) * T, Y0 = (W.tile / X.ntx) * T;
-        const int z0 = W.slab * Zs;
-        const int zs = min(Zs, n0 - z0);
-        const int ry0 = W.lb / T;
-        const int nrows = (W.le - 1) / T + M2 - ry0;  // LDS rows ry0 .. ry0+nrows-1
-        const int nz = zs * nrows * P;
-
+        const ItemGeom g = item_geom(items[it], xfs[items[it].xf], T, Zs, M2);
+        const int nz = g.zs * g.nrows * P;
         for (int i = tid; i < nz; i += nthr) {
-            int z = i / (nrows * P), rem = i - z * nrows * P;
-            size_t o = ((size_t)z * plane + (size_t)(ry0 + rem / P) * P + rem % P) * 2;
-            acc[o] = R(0);
-            acc[o + 1] = R(0);
+            int z = i / (g.nrows * P), rem = i - z * g.nrows * P;
+            size_t o = ((size_t)z * plane + (size_t)(g.ry0 + rem / P) * P + rem % P) * 2;
             if (COMP) {
-                cmp[o] = R(0);
-                cmp[o + 1] = R(0);
+                pairs[o] = 0ull;
+                pairs[o + 1] = 0ull;
+            } else {
+                acc[o] = R(0);
+                acc[o + 1] = R(0);
             }
         }
-        __syncthreads();
+        const int nr = 3 * (g.le - g.lb);
+        const int S = build_runs<M2>(g, T, cell_start, run_p0, run_soff, sh);
 
-        const int nl = W.le - W.lb;
-        for (int task = wave; task < nl * NRG; task += nwaves) {
-            const int li = W.lb + task / NRG;
-            const int rg = task % NRG;
-            const int ly = li / T, lx = li % T;
-            if (Y0 + ly >= n1 || X0 + lx >= n2) continue;
-            const int row = rg * 64 + lane;
-            const bool active = row < ROWS;
-            const int dy = active ? row / M2 : 0, dx = active ? row % M2 : 0;
-            const size_t lrow = (size_t)(ly + dy) * P + (lx + dx);
-            const int *cs = cell_start + X.key_off + ((long long)W.tile * T * T + li) * n0;
-
-            for (int sg = -1; sg <= 1; ++sg) {
-                const int U = sg * n0;
-                int a, b;
-                seg_range(U, z0, zs, m, n0, &a, &b);
-                if (a > b) continue;
-                const long long p0 = X.poff + cs[a], p1 = X.poff + cs[b + 1];
-                if (p0 >= p1) continue;
-                // slab-relative plane of window plane q:  q - M2 + U - z0
-                const int qshift = U - z0 - M2;
+        for (int cs = 0; cs < S; cs += cap) {
+            const int cnt = min(cap, S - cs);
+            stage_chunk(cs, cnt, nr, run_p0, run_soff, slot_p, stage, ST16, rec, rs16);
+            const int r_lo = find_run(run_soff, nr, cs);
+            const int r_hi = find_run(run_soff, nr, cs + cnt - 1);
+            const int ntask = (r_hi - r_lo + 1) * NRG;
+            for (int task = wave; task < ntask; task += nwaves) {
+                const int r = r_lo + task / NRG;
+                const int rg = task % NRG;
+                const int a = max(run_soff[r], cs) - cs;
+                const int b = min(run_soff[r + 1], cs + cnt) - cs;
+                if (a >= b) continue;
+                const int li = g.lb + r / 3;
+                const int U = (r % 3 - 1) * g.n0;
+                const int ly = li / T, lx = li % T;
+                const int row = rg * 64 + lane;
+                const bool active = row < ROWS;
+                const int dy = active ? row / M2 : 0, dx = active ? row % M2 : 0;
+                const size_t lrow = (size_t)(ly + dy) * P + (lx + dx);
+                const int qshift = U - g.z0 - M2;  // slab-relative plane = q + qshift
 
                 R wr[M2], wi[M2];
 #pragma unroll
@@ -134,17 +316,11 @@ __global__ __launch_bounds__(1024) void k_spread(const Xform *__restrict__ xfs,
 
                 auto flush = [&](int s, int q) {
                     int qr = q + qshift;
-                    if (active && qr >= 0 && qr < zs) {
+                    if (active && qr >= 0 && qr < g.zs) {
                         size_t o = ((size_t)qr * plane + lrow) * 2;
                         if (COMP) {
-                            R vr = wr[s], vi = wi[s];
-                            R old = atomicAdd(&acc[o], vr);
-                            R sum = old + vr, bb = sum - old;
-                            atomicAdd(&cmp[o], (old - (sum - bb)) + (vr - bb));
-                            old = atomicAdd(&acc[o + 1], vi);
-                            sum = old + vi;
-                            bb = sum - old;
-                            atomicAdd(&cmp[o + 1], (old - (sum - bb)) + (vi - bb));
+                            lds_add_comp(&pairs[o], (float)wr[s]);
+                            lds_add_comp(&pairs[o + 1], (float)wi[s]);
                         } else {
                             atomicAdd(&acc[o], wr[s]);
                             atomicAdd(&acc[o + 1], wi[s]);
@@ -154,21 +330,21 @@ __global__ __launch_bounds__(1024) void k_spread(const Xform *__restrict__ xfs,
                     wi[s] = R(0);
                 };
 
-                int Bw = -1;  // window base plane (first tap plane + M2), uniform
-                for (long long p = p0; p < p1; ++p) {
-                    const int B = pz[p] - m + 1 + M2;
+                int Bw = -1;  // window base plane (first tap plane + 2m), uniform
+                for (int sl = a; sl < b; ++sl) {
+                    const R *ps = reinterpret_cast<const R *>(stage + sl * ST16);
+                    const int B = reinterpret_cast<const int *>(ps)[OFF_PZ] - m + 1 + M2;
                     if (Bw >= 0 && B != Bw) {
-                        const int r = Bw % M2;
+                        const int rr = Bw % M2;
 #pragma unroll
                         for (int s = 0; s < M2; ++s) {
-                            const int q = Bw + (s >= r ? s - r : s - r + M2);
+                            const int q = Bw + (s >= rr ? s - rr : s - rr + M2);
                             if (q < B) flush(s, q);
                         }
                     }
                     Bw = B;
-                    const R *ps = psi + p * (3 * M2);
                     const R w12 = active ? ps[M2 + dy] * ps[2 * M2 + dx] : R(0);
-                    const R sr = fs[2 * p] * w12, si = fs[2 * p + 1] * w12;
+                    const R sr = ps[OFF_F] * w12, si = ps[OFF_F + 1] * w12;
 #pragma unroll
                     for (int s = 0; s < M2; ++s) {
                         const R wz = ps[s];
@@ -176,259 +352,275 @@ __global__ __launch_bounds__(1024) void k_spread(const Xform *__restrict__ xfs,
                         wi[s] = fma(si, wz, wi[s]);
                     }
                 }
-                const int r = Bw % M2;
+                const int rr = Bw % M2;
 #pragma unroll
-                for (int s = 0; s < M2; ++s) flush(s, Bw + (s >= r ? s - r : s - r + M2));
+                for (int s = 0; s < M2; ++s) flush(s, Bw + (s >= rr ? s - rr : s - rr + M2));
             }
+            __syncthreads();
         }
-        __syncthreads();
 
-        R *grid = reinterpret_cast<R *>(X.grid);
+        R *grid = reinterpret_cast<R *>(xfs[items[it].xf].grid);
         for (int i = tid; i < nz; i += nthr) {
-            int z = i / (nrows * P), rem = i - z * nrows * P;
-            int y = ry0 + rem / P, xx = rem % P;
+            int z = i / (g.nrows * P), rem = i - z * g.nrows * P;
+            int y = g.ry0 + rem / P, xx = rem % P;
             size_t o = ((size_t)z * plane + (size_t)y * P + xx) * 2;
-            R vr = acc[o], vi = acc[o + 1];
+            R vr, vi;
             if (COMP) {
-                vr += cmp[o];
-                vi += cmp[o + 1];
+                unsigned long long a0 = pairs[o], a1 = pairs[o + 1];
+                vr = (R)(__uint_as_float((unsigned int)a0) + __uint_as_float((unsigned int)(a0 >> 32)));
+                vi = (R)(__uint_as_float((unsigned int)a1) + __uint_as_float((unsigned int)(a1 >> 32)));
+            } else {
+                vr = acc[o];
+                vi = acc[o + 1];
             }
-            int gy = wrapn(Y0 + y - m + 1, n1), gx = wrapn(X0 + xx - m + 1, n2);
-            size_t g = (((size_t)(z0 + z) * n1 + gy) * n2 + gx) * 2;
-            if (vr != R(0)) atomicAdd(&grid[g], vr);
-            if (vi != R(0)) atomicAdd(&grid[g + 1], vi);
+            int gy = wrapn(g.Y0 + y - m + 1, g.n1), gx = wrapn(g.X0 + xx - m + 1, g.n2);
+            size_t gi = (((size_t)(g.z0 + z) * g.n1 + gy) * g.n2 + gx) * 2;
+            if (vr != R(0)) atomicAdd(&grid[gi], vr);
+            if (vi != R(0)) atomicAdd(&grid[gi + 1], vi);
         }
     }
 }
 
 // ---------------------------------------------------------------------------
-// Interpolation.  Output per sorted point (atomically added, zero-initialised
-// by the caller):  NO = 1 complex value, or with GRAD four complex values
+// Interpolation.  Output per sorted point (atomically added to `outs`, which
+// the caller zeroes): one complex value, or with GRAD four complex values
 // (value, d/dx0, d/dx1, d/dx2).
 template <typename R, int M2, bool GRAD>
-__global__ __launch_bounds__(interp_max_threads(sizeof(R), M2, GRAD)) void k_interp(const Xform *__restrict__ xfs,
-                                                 const SItem *__restrict__ items, int nitems,
-                                                 int *__restrict__ queue, int T, int Zs,
-                                                 const R *__restrict__ psi, const R *__restrict__ dpsi,
-                                                 const int *__restrict__ pz,
-                                                 const int *__restrict__ cell_start,
-                                                 R *__restrict__ outs)
+__global__ __launch_bounds__(interp_max_threads(sizeof(R), M2, GRAD)) void k_interp(
+    const Xform *__restrict__ xfs, const SItem *__restrict__ items, int nitems, int *__restrict__ queue,
+    int T, int Zs, int cap, const uint4 *__restrict__ rec, int rs16, const int *__restrict__ cell_start,
+    R *__restrict__ outs)
 {
     constexpr int m = M2 / 2;
     constexpr int ROWS = M2 * M2;
     constexpr int NRG = (ROWS + 63) / 64;
     constexpr int NO = GRAD ? 4 : 1;
-    extern __shared__ __align__(16) unsigned char smem[];
+    constexpr int ST16 = (int)(rec_size(M2, sizeof(R), GRAD) / 16);
+    constexpr int OFF_PZ = (int)(rec_off_pz(M2, sizeof(R)) / 4);
+    constexpr int OFF_D = (int)(rec_prefix(M2, sizeof(R)) / sizeof(R));
+    extern __shared__ uint4 smem16[];
+    unsigned char *smem = reinterpret_cast<unsigned char *>(smem16);
     __shared__ int s_item;
+    const LdsLayout LL = lds_layout(T, Zs, M2, sizeof(R), GRAD ? 2 : 1, false, cap);
     const int P = T + M2 - 1;
     const int plane = P * P;
-    R *tile = reinterpret_cast<R *>(smem);
+    R *tile = reinterpret_cast<R *>(smem + LL.tile);
+    uint4 *stage = reinterpret_cast<uint4 *>(smem + LL.stage);
+    int *slot_p = reinterpret_cast<int *>(smem + LL.slot_p);
+    int *run_p0 = reinterpret_cast<int *>(smem + LL.run_p0);
+    int *run_soff = reinterpret_cast<int *>(smem + LL.run_soff);
+    int *sh = reinterpret_cast<int *>(smem + LL.sh);
+    R *oacc = reinterpret_cast<R *>(smem + LL.out);
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int wave = tid >> 6, lane = tid & 63, nwaves = nthr >> 6;
 
     for (int it = next_item(queue, &s_item); it < nitems; it = next_item(queue, &s_item)) {
-        const SItem W = items[it];
-        const Xform &X = xfs[W.xf];
-        const int n0 = X.n[0], n1 = X.n[1], n2 = X.n[2];
-        const int X0 = (W.tile % X.ntx) * T, Y0 = (W.tile / X.ntx) * T;
-        const int z0 = W.slab * Zs;
-        const int zs = min(Zs, n0 - z0);
-        const int ry0 = W.lb / T;
-        const int nrows = (W.le - 1) / T + M2 - ry0;
-        const int nz = zs * nrows * P;
-        const R *grid = reinterpret_cast<const R *>(X.grid);
-
+        const ItemGeom g = item_geom(items[it], xfs[items[it].xf], T, Zs, M2);
+        const int nz = g.zs * g.nrows * P;
+        const R *grid = reinterpret_cast<const R *>(xfs[items[it].xf].grid);
         for (int i = tid; i < nz; i += nthr) {
-            int z = i / (nrows * P), rem = i - z * nrows * P;
-            int y = ry0 + rem / P, xx = rem % P;
-            int gy = wrapn(Y0 + y - m + 1, n1), gx = wrapn(X0 + xx - m + 1, n2);
-            size_t g = (((size_t)(z0 + z) * n1 + gy) * n2 + gx) * 2;
+            int z = i / (g.nrows * P), rem = i - z * g.nrows * P;
+            int y = g.ry0 + rem / P, xx = rem % P;
+            int gy = wrapn(g.Y0 + y - m + 1, g.n1), gx = wrapn(g.X0 + xx - m + 1, g.n2);
+            size_t gi = (((size_t)(g.z0 + z) * g.n1 + gy) * g.n2 + gx) * 2;
             size_t o = ((size_t)z * plane + (size_t)y * P + xx) * 2;
-            tile[o] = grid[g];
-            tile[o + 1] = grid[g + 1];
+            tile[o] = grid[gi];
+            tile[o + 1] = grid[gi + 1];
         }
-        __syncthreads();
+        const int nr = 3 * (g.le - g.lb);
+        const int S = build_runs<M2>(g, T, cell_start, run_p0, run_soff, sh);
 
-        const int nl = W.le - W.lb;
-        for (int task = wave; task < nl; task += nwaves) {
-            const int li = W.lb + task;
-            const int ly = li / T, lx = li % T;
-            if (Y0 + ly >= n1 || X0 + lx >= n2) continue;
-            const int *cs = cell_start + X.key_off + ((long long)W.tile * T * T + li) * n0;
-
-            for (int sg = -1; sg <= 1; ++sg) {
-                const int U = sg * n0;
-                int a, b;
-                seg_range(U, z0, zs, m, n0, &a, &b);
-                if (a > b) continue;
-                const long long p0 = X.poff + cs[a], p1 = X.poff + cs[b + 1];
-                const int qshift = U - z0 - M2;
-
-                for (long long c = p0; c < p1; c += 64) {
-                    const long long ce = min(p1, c + 64);
+        for (int cs = 0; cs < S; cs += cap) {
+            const int cnt = min(cap, S - cs);
+            stage_chunk(cs, cnt, nr, run_p0, run_soff, slot_p, stage, ST16, rec, rs16);
+            const int r_lo = find_run(run_soff, nr, cs);
+            const int r_hi = find_run(run_soff, nr, cs + cnt - 1);
+            // task = one run piece (all row groups); the piece's points are
+            // taken 64 at a time, lane (slot - first) owning the outputs of
+            // its slot, so every slot has exactly one writer.
+            for (int task = wave; task <= r_hi - r_lo; task += nwaves) {
+                const int r = r_lo + task;
+                const int a = max(run_soff[r], cs) - cs;
+                const int b = min(run_soff[r + 1], cs + cnt) - cs;
+                if (a >= b) continue;
+                const int li = g.lb + r / 3;
+                const int U = (r % 3 - 1) * g.n0;
+                const int ly = li / T, lx = li % T;
+                const int qshift = U - g.z0 - M2;
+                for (int c0 = a; c0 < b; c0 += 64) {
+                    const int c1 = min(b, c0 + 64);
                     R ores[2 * NO];
 #pragma unroll
                     for (int i = 0; i < 2 * NO; ++i) ores[i] = R(0);
-
                     for (int rg = 0; rg < NRG; ++rg) {
-                        const int row = rg * 64 + lane;
-                        const bool active = row < ROWS;
-                        const int dy = active ? row / M2 : 0, dx = active ? row % M2 : 0;
-                        const size_t lrow = (size_t)(ly + dy) * P + (lx + dx);
-                        R gr[M2], gi[M2];
+                const int row = rg * 64 + lane;
+                const bool active = row < ROWS;
+                const int dy = active ? row / M2 : 0, dx = active ? row % M2 : 0;
+                const size_t lrow = (size_t)(ly + dy) * P + (lx + dx);
+
+                R gr[M2], gi[M2];
 #pragma unroll
-                        for (int s = 0; s < M2; ++s) gr[s] = gi[s] = R(0);
-                        int Bw = -1;
-                        for (long long p = c; p < ce; ++p) {
-                            const int B = pz[p] - m + 1 + M2;
-                            if (B != Bw) {
-                                const int rn = B % M2;
-                                const int ro = Bw >= 0 ? Bw % M2 : 0;
+                for (int s = 0; s < M2; ++s) gr[s] = gi[s] = R(0);
+                int Bw = -1;
+                for (int sl = c0; sl < c1; ++sl) {
+                    const R *ps = reinterpret_cast<const R *>(stage + sl * ST16);
+                    const int B = reinterpret_cast<const int *>(ps)[OFF_PZ] - m + 1 + M2;
+                    if (B != Bw) {
+                        const int rn = B % M2;
+                        const int ro = Bw >= 0 ? Bw % M2 : 0;
 #pragma unroll
-                                for (int s = 0; s < M2; ++s) {
-                                    const int qold = Bw + (s >= ro ? s - ro : s - ro + M2);
-                                    if (Bw < 0 || qold < B) {
-                                        const int qn = B + (s >= rn ? s - rn : s - rn + M2);
-                                        const int qr = qn + qshift;
-                                        if (active && qr >= 0 && qr < zs) {
-                                            size_t o = ((size_t)qr * plane + lrow) * 2;
-                                            gr[s] = tile[o];
-                                            gi[s] = tile[o + 1];
-                                        } else {
-                                            gr[s] = R(0);
-                                            gi[s] = R(0);
-                                        }
-                                    }
+                        for (int s = 0; s < M2; ++s) {
+                            const int qold = Bw + (s >= ro ? s - ro : s - ro + M2);
+                            if (Bw < 0 || qold < B) {
+                                const int qn = B + (s >= rn ? s - rn : s - rn + M2);
+                                const int qr = qn + qshift;
+                                if (active && qr >= 0 && qr < g.zs) {
+                                    size_t o = ((size_t)qr * plane + lrow) * 2;
+                                    gr[s] = tile[o];
+                                    gi[s] = tile[o + 1];
+                                } else {
+                                    gr[s] = R(0);
+                                    gi[s] = R(0);
                                 }
-                                Bw = B;
-                            }
-                            const R *ps = psi + p * (3 * M2);
-                            R sr = R(0), si = R(0);
-#pragma unroll
-                            for (int s = 0; s < M2; ++s) {
-                                sr = fma(gr[s], ps[s], sr);
-                                si = fma(gi[s], ps[s], si);
-                            }
-                            const R w1 = active ? ps[M2 + dy] : R(0);
-                            const R w2 = active ? ps[2 * M2 + dx] : R(0);
-                            const R w12 = w1 * w2;
-                            R v[2 * NO];
-                            v[0] = sr * w12;
-                            v[1] = si * w12;
-                            if (GRAD) {
-                                const R *dp = dpsi + p * (3 * M2);
-                                R dr = R(0), di = R(0);
-#pragma unroll
-                                for (int s = 0; s < M2; ++s) {
-                                    dr = fma(gr[s], dp[s], dr);
-                                    di = fma(gi[s], dp[s], di);
-                                }
-                                const R d1 = active ? dp[M2 + dy] * w2 : R(0);
-                                const R d2 = active ? w1 * dp[2 * M2 + dx] : R(0);
-                                v[2] = dr * w12;
-                                v[3] = di * w12;
-                                v[4] = sr * d1;
-                                v[5] = si * d1;
-                                v[6] = sr * d2;
-                                v[7] = si * d2;
-                            }
-                            const int slot = (int)(p - c);
-#pragma unroll
-                            for (int i = 0; i < 2 * NO; ++i) {
-                                R tsum = wave_sum(v[i]);
-                                if (lane == slot) ores[i] += tsum;
                             }
                         }
+                        Bw = B;
                     }
-                    if (lane < ce - c) {
-                        R *dst = outs + (c + lane) * (2 * NO);
+                    R sr = R(0), si = R(0);
 #pragma unroll
-                        for (int i = 0; i < 2 * NO; ++i) atomicAdd(&dst[i], ores[i]);
+                    for (int s = 0; s < M2; ++s) {
+                        sr = fma(gr[s], ps[s], sr);
+                        si = fma(gi[s], ps[s], si);
+                    }
+                    const R w1 = active ? ps[M2 + dy] : R(0);
+                    const R w2 = active ? ps[2 * M2 + dx] : R(0);
+                    const R w12 = w1 * w2;
+                    R v[2 * NO];
+                    v[0] = sr * w12;
+                    v[1] = si * w12;
+                    if (GRAD) {
+                        const R *dp = ps + OFF_D;
+                        R dr = R(0), di = R(0);
+#pragma unroll
+                        for (int s = 0; s < M2; ++s) {
+                            dr = fma(gr[s], dp[s], dr);
+                            di = fma(gi[s], dp[s], di);
+                        }
+                        const R d1 = active ? dp[M2 + dy] * w2 : R(0);
+                        const R d2 = active ? w1 * dp[2 * M2 + dx] : R(0);
+                        v[2] = dr * w12;
+                        v[3] = di * w12;
+                        v[4] = sr * d1;
+                        v[5] = si * d1;
+                        v[6] = sr * d2;
+                        v[7] = si * d2;
+                    }
+                    const bool mine = lane == sl - c0;
+#pragma unroll
+                    for (int i = 0; i < 2 * NO; ++i) {
+                        R tsum = wave_sum(v[i]);
+                        if (mine) ores[i] += tsum;
+                    }
+                }
+                    }
+                    if (lane < c1 - c0) {
+#pragma unroll
+                        for (int i = 0; i < 2 * NO; ++i) oacc[(c0 + lane) * 2 * NO + i] = ores[i];
                     }
                 }
             }
+            __syncthreads();
+            for (int e = tid; e < cnt * 2 * NO; e += nthr) {
+                R v = oacc[e];
+                if (v != R(0)) atomicAdd(&outs[(size_t)slot_p[e / (2 * NO)] * (2 * NO) + e % (2 * NO)], v);
+            }
+            __syncthreads();
         }
     }
 }
 
 // ---------------------------------------------------------------------------
+static int cu_count()
+{
+    static int cus = 0;
+    if (!cus) {
+        int dev = 0;
+        hipGetDevice(&dev);
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+            cus = 256;
+    }
+    return cus;
+}
+
 template <typename R, int M2>
 static hipError_t spread_m(const Xform *dxf, const SItem *items, int nitems, int *queue, Tiling t,
-                           const R *psi, const R *fs, const int *pz, const int *cs, hipStream_t s)
+                           const unsigned char *rec, size_t rec_bytes, const int *cs, hipStream_t s)
 {
     constexpr bool COMP = sizeof(R) == 4;
-    size_t lds = spread_lds_bytes(t.T, t.Zs, M2, sizeof(R), COMP);
+    LdsLayout LL = lds_fit(t.T, t.Zs, M2, sizeof(R), 0, COMP);
+    if (!LL.cap) return hipErrorInvalidValue;
     auto kern = k_spread<R, M2, COMP>;
     hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)lds);
+                                       (int)LL.total);
     if (e != hipSuccess) return e;
-    int dev = 0, cus = 256;
-    hipGetDevice(&dev);
-    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    int per_cu = (int)(kLdsBytes / lds);
+    int per_cu = (int)((160 * 1024) / (LL.total + 1024));
     if (per_cu < 1) per_cu = 1;
-    int grid = cus * per_cu;
-    if (grid > nitems) grid = nitems;
+    int grid = std::min(cu_count() * per_cu, nitems);
     if (grid < 1) return hipSuccess;
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(t.threads), lds, s, dxf, items, nitems, queue, t.T, t.Zs,
-                       psi, fs, pz, cs);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(t.threads), LL.total, s, dxf, items, nitems, queue, t.T, t.Zs,
+                       LL.cap, (const uint4 *)rec, (int)(rec_bytes / 16), cs);
     return hipGetLastError();
 }
 
 template <typename R, int M2, bool GRAD>
 static hipError_t interp_m(const Xform *dxf, const SItem *items, int nitems, int *queue, Tiling t,
-                           const R *psi, const R *dpsi, const int *pz, const int *cs, R *outs,
-                           hipStream_t s)
+                           const unsigned char *rec, size_t rec_bytes, const int *cs, R *outs, hipStream_t s)
 {
-    size_t lds = interp_lds_bytes(t.T, t.Zs, M2, sizeof(R), t.threads, GRAD);
+    LdsLayout LL = lds_fit(t.T, t.Zs, M2, sizeof(R), GRAD ? 2 : 1, false);
+    if (!LL.cap) return hipErrorInvalidValue;
     auto kern = k_interp<R, M2, GRAD>;
     hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)lds);
+                                       (int)LL.total);
     if (e != hipSuccess) return e;
-    int dev = 0, cus = 256;
-    hipGetDevice(&dev);
-    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    int per_cu = (int)(kLdsBytes / lds);
+    int per_cu = (int)((160 * 1024) / (LL.total + 1024));
     if (per_cu < 1) per_cu = 1;
-    int grid = cus * per_cu;
-    if (grid > nitems) grid = nitems;
+    int grid = std::min(cu_count() * per_cu, nitems);
     if (grid < 1) return hipSuccess;
     int threads = std::min(t.threads, interp_max_threads(sizeof(R), M2, GRAD));
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(threads), lds, s, dxf, items, nitems, queue, t.T, t.Zs,
-                       psi, dpsi, pz, cs, outs);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(threads), LL.total, s, dxf, items, nitems, queue, t.T, t.Zs,
+                       LL.cap, (const uint4 *)rec, (int)(rec_bytes / 16), cs, outs);
     return hipGetLastError();
 }
 
 template <typename R>
 hipError_t launch_spread(int m, const Xform *dxf, const SItem *items, int nitems, int *queue, Tiling t,
-                         const R *psi, const R *fs, const int *pz, const int *cell_start,
-                         const Xform *hxf0, hipStream_t s)
+                         const unsigned char *rec, size_t rec_bytes, const int *cell_start, hipStream_t s)
 {
-    (void)hxf0;
+#define HPNFFT_SPREAD_CASE(MM) \
+    case MM: return spread_m<R, 2 * MM>(dxf, items, nitems, queue, t, rec, rec_bytes, cell_start, s);
     switch (m) {
-    case 1: return spread_m<R, 2>(dxf, items, nitems, queue, t, psi, fs, pz, cell_start, s);
-    case 2: return spread_m<R, 4>(dxf, items, nitems, queue, t, psi, fs, pz, cell_start, s);
-    case 3: return spread_m<R, 6>(dxf, items, nitems, queue, t, psi, fs, pz, cell_start, s);
-    case 4: return spread_m<R, 8>(dxf, items, nitems, queue, t, psi, fs, pz, cell_start, s);
-    case 5: return spread_m<R, 10>(dxf, items, nitems, queue, t, psi, fs, pz, cell_start, s);
-    case 6: return spread_m<R, 12>(dxf, items, nitems, queue, t, psi, fs, pz, cell_start, s);
-    case 7: return spread_m<R, 14>(dxf, items, nitems, queue, t, psi, fs, pz, cell_start, s);
-    case 8: return spread_m<R, 16>(dxf, items, nitems, queue, t, psi, fs, pz, cell_start, s);
+        HPNFFT_SPREAD_CASE(1)
+        HPNFFT_SPREAD_CASE(2)
+        HPNFFT_SPREAD_CASE(3)
+        HPNFFT_SPREAD_CASE(4)
+        HPNFFT_SPREAD_CASE(5)
+        HPNFFT_SPREAD_CASE(6)
+        HPNFFT_SPREAD_CASE(7)
+        HPNFFT_SPREAD_CASE(8)
     default: return hipErrorInvalidValue;
     }
+#undef HPNFFT_SPREAD_CASE
 }
 
 template <typename R>
 hipError_t launch_interp(int m, bool grad, const Xform *dxf, const SItem *items, int nitems, int *queue,
-                         Tiling t, const R *psi, const R *dpsi, const int *pz, const int *cs, R *outs,
+                         Tiling t, const unsigned char *rec, size_t rec_bytes, const int *cs, R *outs,
                          hipStream_t s)
 {
-#define HPNFFT_INTERP_CASE(MM)                                                                     \
-    case MM:                                                                                       \
-        return grad ? interp_m<R, 2 * MM, true>(dxf, items, nitems, queue, t, psi, dpsi, pz, cs,  \
-                                                outs, s)                                           \
-                    : interp_m<R, 2 * MM, false>(dxf, items, nitems, queue, t, psi, dpsi, pz, cs, \
-                                                 outs, s);
+#define HPNFFT_INTERP_CASE(MM)                                                                        \
+    case MM:                                                                                          \
+        return grad ? interp_m<R, 2 * MM, true>(dxf, items, nitems, queue, t, rec, rec_bytes, cs, outs, s) \
+                    : interp_m<R, 2 * MM, false>(dxf, items, nitems, queue, t, rec, rec_bytes, cs, outs, s);
     switch (m) {
         HPNFFT_INTERP_CASE(1)
         HPNFFT_INTERP_CASE(2)
@@ -444,16 +636,12 @@ hipError_t launch_interp(int m, bool grad, const Xform *dxf, const SItem *items,
 }
 
 template hipError_t launch_spread<double>(int, const Xform *, const SItem *, int, int *, Tiling,
-                                          const double *, const double *, const int *, const int *,
-                                          const Xform *, hipStream_t);
+                                          const unsigned char *, size_t, const int *, hipStream_t);
 template hipError_t launch_spread<float>(int, const Xform *, const SItem *, int, int *, Tiling,
-                                         const float *, const float *, const int *, const int *,
-                                         const Xform *, hipStream_t);
+                                         const unsigned char *, size_t, const int *, hipStream_t);
 template hipError_t launch_interp<double>(int, bool, const Xform *, const SItem *, int, int *, Tiling,
-                                          const double *, const double *, const int *, const int *,
-                                          double *, hipStream_t);
+                                          const unsigned char *, size_t, const int *, double *, hipStream_t);
 template hipError_t launch_interp<float>(int, bool, const Xform *, const SItem *, int, int *, Tiling,
-                                         const float *, const float *, const int *, const int *,
-                                         float *, hipStream_t);
+                                         const unsigned char *, size_t, const int *, float *, hipStream_t);
 
 }  // namespace hpnfft

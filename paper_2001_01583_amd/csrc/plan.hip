@@ -17,7 +17,7 @@
 #include <new>
 #include <vector>
 
-#include "../../include/hpnfft.h"
+#include "hpnfft.h"
 #include "internal.h"
 #include "window.h"
 
@@ -54,8 +54,9 @@ int fft_count(int n)
 }
 
 struct Layout {
-    size_t counters, setp, grids, tmpA, tmpB, cell_start, scan_tmp, rank, perm, pz, us, xs, psi, dpsi,
-        fs, outs, tcost, items, fit[3], ewald, roll, tw, xf, total;
+    size_t counters, setp, grids, tmpA, tmpB, cell_start, scan_tmp, rank, perm, us, xs, rec, outs, tcost,
+        items, fit[3], ewald, roll, tw, xf, total;
+    size_t rec_bytes = 0;
     std::vector<size_t> grid_off, tmpA_off, tmpB_off, key_off, tcost_off, roll_off;
     std::map<int, size_t> tw_off;
     int max_items = 0, nfit[3] = {0, 0, 0}, ew_blocks = 0;
@@ -82,6 +83,14 @@ struct hpnfft_plan_s {
     int maxn = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
+    // live timing
+    struct Rec {
+        int phase;
+        hipEvent_t a, b;
+    };
+    bool prof = false;
+    std::vector<Rec> recs;
+    std::vector<hipEvent_t> pool;
 
     size_t rbytes() const { return prec == HPNFFT_F32 ? 4 : 8; }
     int M2() const { return 2 * m; }
@@ -103,19 +112,34 @@ bool tiling_fits(const hpnfft_plan_s *p, Tiling t)
     if (t.T < 4 || t.T > 32 || t.Zs < 2 || t.Zs > 64) return false;
     if (t.threads < 64 || t.threads > 1024 || t.threads % 64) return false;
     bool comp = p->prec == HPNFFT_F32;
-    size_t a = spread_lds_bytes(t.T, t.Zs, p->M2(), p->rbytes(), comp);
-    size_t b = interp_lds_bytes(t.T, t.Zs, p->M2(), p->rbytes(), t.threads, p->grad());
-    return a + 64 <= (size_t)kLdsBytes && b + 64 <= (size_t)kLdsBytes;
+    if (!lds_fit(t.T, t.Zs, p->M2(), p->rbytes(), 0, comp).cap) return false;
+    if (!lds_fit(t.T, t.Zs, p->M2(), p->rbytes(), 1, false).cap) return false;
+    if (p->grad() && !lds_fit(t.T, t.Zs, p->M2(), p->rbytes(), 2, false).cap) return false;
+    return true;
 }
 
+// Default tiling: the largest tile whose staging chunk still holds enough
+// lines to give every wavefront of a 1024-thread workgroup two tasks, given
+// the mean point density per cell.
 Tiling default_tiling(const hpnfft_plan_s *p)
 {
-    // largest power-of-two tile edge whose spread tile fits ~150 KiB of LDS
-    for (int Zs : {16, 8, 4})
-        for (int T : {32, 16, 8, 4}) {
+    double cells = 0.0;
+    for (const Xform &X : p->hx) cells += (double)X.n[0] * X.n[1] * X.n[2];
+    double rho = (double)p->Mtot / std::max(cells, 1.0);
+    int nrg = (p->M2() * p->M2() + 63) / 64;
+    for (int T : {16, 12, 8, 6, 4})
+        for (int Zs : {16, 12, 8}) {
             Tiling t{T, Zs, 1024};
-            size_t a = spread_lds_bytes(T, Zs, p->M2(), p->rbytes(), p->prec == HPNFFT_F32);
-            if (tiling_fits(p, t) && a <= 150 * 1024) return t;
+            if (!tiling_fits(p, t)) continue;
+            int cap = lds_fit(T, Zs, p->M2(), p->rbytes(), 0, p->prec == HPNFFT_F32).cap;
+            double per_line = std::max(1.0, rho * (Zs + p->M2() - 1));
+            double tasks = std::min((double)T * T, cap / per_line) * nrg;
+            if (tasks >= 32) return t;
+        }
+    for (int T : {8, 6, 4})
+        for (int Zs : {8, 6, 4}) {
+            Tiling t{T, Zs, 1024};
+            if (tiling_fits(p, t)) return t;
         }
     return Tiling{4, 4, 256};
 }
@@ -172,13 +196,10 @@ void build_layout(hpnfft_plan_s *p)
     L.scan_tmp = take((size_t)(nb + nb / 2048 + 64) * 4);
     L.rank = take((size_t)maxM * 4);
     L.perm = take((size_t)p->Mtot * 4);
-    L.pz = take((size_t)p->Mtot * 4);
     L.us = take((size_t)p->Mtot * 24);
     L.xs = take((size_t)p->Mtot * 24);
-    size_t psi_b = (size_t)p->Mtot * 3 * p->M2() * p->rbytes();
-    L.psi = take(psi_b);
-    L.dpsi = p->grad() ? take(psi_b) : 0;
-    L.fs = take((size_t)p->Mtot * C);
+    L.rec_bytes = rec_size(p->M2(), p->rbytes(), p->grad());
+    L.rec = take((size_t)p->Mtot * L.rec_bytes);
     L.outs_bytes = (size_t)p->Mtot * C * (p->grad() ? 4 : 1);
     L.outs = take(L.outs_bytes);
     L.tcost = off;
@@ -296,6 +317,48 @@ int upload_tables(hpnfft_plan_s *p)
 
 int check_plan(hpnfft_plan_s *p) { return p ? HPNFFT_OK : HPNFFT_EINVAL; }
 
+hipEvent_t take_event(hpnfft_plan_s *p)
+{
+    if (!p->pool.empty()) {
+        hipEvent_t e = p->pool.back();
+        p->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Records an event pair around a kernel group when timing is enabled.
+struct PhaseTimer {
+    hpnfft_plan_s *p;
+    int phase;
+    hipEvent_t a = nullptr;
+    PhaseTimer(hpnfft_plan_s *pl, int ph) : p(pl), phase(ph)
+    {
+        if (!p->prof) return;
+        a = take_event(p);
+        if (a) hipEventRecord(a, p->stream);
+    }
+    ~PhaseTimer()
+    {
+        if (!a) return;
+        hipEvent_t b = take_event(p);
+        if (!b) return;
+        hipEventRecord(b, p->stream);
+        p->recs.push_back({phase, a, b});
+    }
+};
+
+void drop_records(hpnfft_plan_s *p)
+{
+    for (auto &r : p->recs) {
+        p->pool.push_back(r.a);
+        p->pool.push_back(r.b);
+    }
+    p->recs.clear();
+}
+
 // Bin, sort and tabulate the stored points (p->ws + L.xs); then build the
 // spread / interpolation work list.  Synchronises once.
 int bin_points(hpnfft_plan_s *p)
@@ -314,16 +377,17 @@ int bin_points(hpnfft_plan_s *p)
         HCHECK(launch_bin_count(xb, nullptr, X.M, X, p->til.T, p->m, cs, p->at<int>(L.rank), setp, s));
         HCHECK(launch_scan(cs, p->keys[b], p->at<int>(L.scan_tmp), s));
         HCHECK(launch_bin_scatter(xb, nullptr, X.M, X, p->til.T, p->m, cs, p->at<int>(L.rank),
-                                  p->at<int>(L.perm), p->at<int>(L.pz), p->at<double>(L.us), s));
+                                  p->at<int>(L.perm), p->at<unsigned char>(L.rec), L.rec_bytes,
+                                  rec_off_pz(p->M2(), p->rbytes()), p->at<double>(L.us), s));
         if (p->prec == HPNFFT_F32)
-            HCHECK(launch_psi<float>(p->at<double>(L.us), p->at<int>(L.pz), X.M, X.poff, X, p->m, p->b,
-                                     p->inv_peak, p->at<float>(L.psi),
-                                     p->grad() ? p->at<float>(L.dpsi) : nullptr, s));
+            HCHECK(launch_psi<float>(p->at<double>(L.us), X.M, X.poff, X, p->m, p->b, p->inv_peak,
+                                     p->at<unsigned char>(L.rec), L.rec_bytes, p->grad(), s));
         else
-            HCHECK(launch_psi<double>(p->at<double>(L.us), p->at<int>(L.pz), X.M, X.poff, X, p->m, p->b,
-                                      p->inv_peak, p->at<double>(L.psi),
-                                      p->grad() ? p->at<double>(L.dpsi) : nullptr, s));
-        HCHECK(launch_tile_cost(cs, X, p->til.T, p->til.Zs, p->m, p->at<int>(L.tcost_off[b]), total, s));
+            HCHECK(launch_psi<double>(p->at<double>(L.us), X.M, X.poff, X, p->m, p->b, p->inv_peak,
+                                      p->at<unsigned char>(L.rec), L.rec_bytes, p->grad(), s));
+        int *tc = p->at<int>(L.tcost_off[b]);
+        HCHECK(launch_zero(tc, (size_t)X.ntx * X.nty * X.nslab * 4, s));
+        HCHECK(launch_tile_cost(cs, X, p->til.T, p->til.Zs, p->m, tc, total, s));
     }
     const int cap_div = p->cus * 4;
     for (int b = 0; b < p->B; ++b) {
@@ -346,15 +410,24 @@ template <typename R> int run_adjoint(hpnfft_plan_s *p, const void *f, void *fha
     const Layout &L = p->L;
     hipStream_t s = p->stream;
     const Xform *dxf = p->at<Xform>(L.xf);
-    // queue counters and grids form one contiguous zeroed range
-    HCHECK(launch_zero(p->ws + L.counters, 256, s));
-    HCHECK(launch_zero(p->ws + L.grids, L.grids_bytes, s));
-    HCHECK(launch_gather<R>(f, p->at<int>(L.perm), p->Mtot, p->at<R>(L.fs), s));
-    HCHECK(launch_spread<R>(p->m, dxf, p->at<SItem>(L.items), p->nitems, p->at<int>(L.counters), p->til,
-                            p->at<R>(L.psi), p->at<R>(L.fs), p->at<int>(L.pz), p->at<int>(L.cell_start),
-                            nullptr, s));
+    {
+        PhaseTimer t(p, HPNFFT_PH_ZERO);
+        HCHECK(launch_zero(p->ws + L.counters, 256, s));
+        HCHECK(launch_zero(p->ws + L.grids, L.grids_bytes, s));
+    }
+    {
+        PhaseTimer t(p, HPNFFT_PH_GATHER);
+        HCHECK(launch_gather<R>(f, p->at<int>(L.perm), p->Mtot, p->at<unsigned char>(L.rec), L.rec_bytes,
+                                rec_off_f(p->M2(), sizeof(R)), s));
+    }
+    {
+        PhaseTimer t(p, HPNFFT_PH_SPREAD);
+        HCHECK(launch_spread<R>(p->m, dxf, p->at<SItem>(L.items), p->nitems, p->at<int>(L.counters), p->til,
+                                p->at<unsigned char>(L.rec), L.rec_bytes, p->at<int>(L.cell_start), s));
+    }
     for (int pass = P_ADJ0; pass <= P_ADJ2; ++pass) {
         int d = pass == P_ADJ0 ? 2 : (pass == P_ADJ1 ? 1 : 0);
+        PhaseTimer t(p, HPNFFT_PH_FFT_A0 + pass - P_ADJ0);
         HCHECK(launch_fft<R>(pass, dxf, p->at<FItem>(L.fit[d]), L.nfit[d], p->maxn, fhat, s));
     }
     return HPNFFT_OK;
@@ -367,6 +440,7 @@ template <typename R> int run_to_grid(hpnfft_plan_s *p, const void *fhat)
     const Xform *dxf = p->at<Xform>(L.xf);
     for (int pass = P_FWD0; pass <= P_FWD2; ++pass) {
         int d = pass == P_FWD0 ? 0 : (pass == P_FWD1 ? 1 : 2);
+        PhaseTimer t(p, HPNFFT_PH_FFT_F0 + pass - P_FWD0);
         HCHECK(launch_fft<R>(pass, dxf, p->at<FItem>(L.fit[d]), L.nfit[d], p->maxn,
                              const_cast<void *>(fhat), s));
     }
@@ -378,14 +452,23 @@ template <typename R> int run_forward(hpnfft_plan_s *p, const void *fhat, void *
     const Layout &L = p->L;
     hipStream_t s = p->stream;
     const Xform *dxf = p->at<Xform>(L.xf);
-    HCHECK(launch_zero(p->ws + L.counters, 256, s));
-    HCHECK(launch_zero(p->ws + L.outs, (size_t)p->Mtot * 2 * sizeof(R), s));
+    {
+        PhaseTimer t(p, HPNFFT_PH_ZERO);
+        HCHECK(launch_zero(p->ws + L.counters, 256, s));
+        HCHECK(launch_zero(p->ws + L.outs, (size_t)p->Mtot * 2 * sizeof(R), s));
+    }
     int rc = run_to_grid<R>(p, fhat);
     if (rc) return rc;
-    HCHECK(launch_interp<R>(p->m, false, dxf, p->at<SItem>(L.items), p->nitems, p->at<int>(L.counters) + 1,
-                            p->til, p->at<R>(L.psi), nullptr, p->at<int>(L.pz), p->at<int>(L.cell_start),
-                            p->at<R>(L.outs), s));
-    HCHECK(launch_scatter<R>(p->at<R>(L.outs), p->at<int>(L.perm), p->Mtot, f, s));
+    {
+        PhaseTimer t(p, HPNFFT_PH_INTERP);
+        HCHECK(launch_interp<R>(p->m, false, dxf, p->at<SItem>(L.items), p->nitems,
+                                p->at<int>(L.counters) + 1, p->til, p->at<unsigned char>(L.rec), L.rec_bytes,
+                                p->at<int>(L.cell_start), p->at<R>(L.outs), s));
+    }
+    {
+        PhaseTimer t(p, HPNFFT_PH_SCATTER);
+        HCHECK(launch_scatter<R>(p->at<R>(L.outs), p->at<int>(L.perm), p->Mtot, f, s));
+    }
     return HPNFFT_OK;
 }
 
@@ -395,14 +478,23 @@ int run_backward(hpnfft_plan_s *p, const void *f, const void *gfhat, void *grad_
     const Layout &L = p->L;
     hipStream_t s = p->stream;
     const Xform *dxf = p->at<Xform>(L.xf);
-    HCHECK(launch_zero(p->ws + L.counters, 256, s));
-    HCHECK(launch_zero(p->ws + L.outs, L.outs_bytes, s));
+    {
+        PhaseTimer t(p, HPNFFT_PH_ZERO);
+        HCHECK(launch_zero(p->ws + L.counters, 256, s));
+        HCHECK(launch_zero(p->ws + L.outs, L.outs_bytes, s));
+    }
     int rc = run_to_grid<R>(p, gfhat);
     if (rc) return rc;
-    HCHECK(launch_interp<R>(p->m, true, dxf, p->at<SItem>(L.items), p->nitems, p->at<int>(L.counters) + 1,
-                            p->til, p->at<R>(L.psi), p->at<R>(L.dpsi), p->at<int>(L.pz),
-                            p->at<int>(L.cell_start), p->at<R>(L.outs), s));
-    HCHECK(launch_grad_finish<R>(p->at<R>(L.outs), f, p->at<int>(L.perm), p->Mtot, grad_f, grad_x, s));
+    {
+        PhaseTimer t(p, HPNFFT_PH_GRAD);
+        HCHECK(launch_interp<R>(p->m, true, dxf, p->at<SItem>(L.items), p->nitems,
+                                p->at<int>(L.counters) + 1, p->til, p->at<unsigned char>(L.rec), L.rec_bytes,
+                                p->at<int>(L.cell_start), p->at<R>(L.outs), s));
+    }
+    {
+        PhaseTimer t(p, HPNFFT_PH_GRAD_FIN);
+        HCHECK(launch_grad_finish<R>(p->at<R>(L.outs), f, p->at<int>(L.perm), p->Mtot, grad_f, grad_x, s));
+    }
     return HPNFFT_OK;
 }
 
@@ -500,6 +592,9 @@ int hpnfft_batch_create(hpnfft_batch *out, int B, const int64_t *N, const int64_
 int hpnfft_plan_destroy(hpnfft_plan p)
 {
     if (!p) return HPNFFT_OK;
+    if (!p->recs.empty()) hipStreamSynchronize(p->stream);
+    drop_records(p);
+    for (hipEvent_t e : p->pool) hipEventDestroy(e);
     if (p->gexec) hipGraphExecDestroy(p->gexec);
     if (p->graph) hipGraphDestroy(p->graph);
     delete p;
@@ -575,7 +670,11 @@ static int set_points_any(hpnfft_plan p, const double *x, const float *x32)
         HCHECK(hipMemcpyAsync(xs, hd.data(), hd.size() * 8, hipMemcpyHostToDevice, p->stream));
         HCHECK(hipStreamSynchronize(p->stream));
     }
-    int rc = bin_points(p);
+    int rc;
+    {
+        PhaseTimer t(p, HPNFFT_PH_SET_POINTS);
+        rc = bin_points(p);
+    }
     p->have_points = rc == HPNFFT_OK;
     return rc;
 }
@@ -626,6 +725,15 @@ int hpnfft_ewald_recip(hpnfft_plan p, const void *S, double L, double alpha, dou
     return hip_status(e);
 }
 
+int hpnfft_ewald_real(const double *r, const double *q, int64_t M, double L, double alpha, double rcut,
+                      double *energy_dev, double *forces_dev, double *scratch_dev, void *stream)
+{
+    if (!r || !q || !energy_dev || !scratch_dev || M < 1) return HPNFFT_EINVAL;
+    if (!(L > 0.0) || !(alpha > 0.0) || !(rcut > 0.0) || rcut > 0.5 * L) return HPNFFT_EINVAL;
+    return hip_status(launch_ewald_real(r, q, M, L, alpha, rcut, scratch_dev, energy_dev, forces_dev,
+                                        (hipStream_t)stream));
+}
+
 int hpnfft_plan_info(hpnfft_plan p, int64_t *n_out, int64_t *M_out)
 {
     if (!p) return HPNFFT_EINVAL;
@@ -656,12 +764,19 @@ int hpnfft_batch_capture(hpnfft_batch p, const void *f, void *fhat)
         hipGraphDestroy(p->graph);
         p->graph = nullptr;
     }
-    // attribute setup outside the capture: one eager run
+    // attribute setup outside the capture: one eager run; no timing events
+    // inside the graph
+    bool prof = p->prof;
+    p->prof = false;
     int rc = hpnfft_adjoint(p, f, fhat);
-    if (rc) return rc;
+    if (rc) {
+        p->prof = prof;
+        return rc;
+    }
     HCHECK(hipStreamSynchronize(p->stream));
     HCHECK(hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal));
     rc = hpnfft_adjoint(p, f, fhat);
+    p->prof = prof;
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(p->stream, &g);
     if (rc) {
@@ -746,6 +861,37 @@ int hpnfft_autotune(hpnfft_plan p, void *scratch_f, void *scratch_fhat, int *til
     if (slab) *slab = best.Zs;
     if (threads) *threads = best.threads;
     return rc;
+}
+
+int hpnfft_profile(hpnfft_plan p, int enable)
+{
+    if (!p) return HPNFFT_EINVAL;
+    if (!p->recs.empty()) HCHECK(hipStreamSynchronize(p->stream));
+    drop_records(p);
+    p->prof = enable != 0;
+    return HPNFFT_OK;
+}
+
+int hpnfft_profile_read(hpnfft_plan p, double *ms, int64_t *counts)
+{
+    if (!p) return HPNFFT_EINVAL;
+    if (!p->recs.empty()) HCHECK(hipEventSynchronize(p->recs.back().b));
+    for (auto &r : p->recs) {
+        float t = 0.f;
+        HCHECK(hipEventElapsedTime(&t, r.a, r.b));
+        if (ms) ms[r.phase] += t;
+        if (counts) counts[r.phase] += 1;
+    }
+    drop_records(p);
+    return HPNFFT_OK;
+}
+
+const char *hpnfft_phase_name(int phase)
+{
+    static const char *names[HPNFFT_NPHASES] = {"set_points", "zero",   "gather", "spread", "fft_a0",
+                                                "fft_a1",     "fft_a2", "fft_f0", "fft_f1", "fft_f2",
+                                                "interp",     "scatter", "grad_interp", "grad_finish"};
+    return (phase >= 0 && phase < HPNFFT_NPHASES) ? names[phase] : "";
 }
 
 int hpnfft_window_eval(int m, double sigma, int64_t count, const double *t, double *phi, double *dphi)

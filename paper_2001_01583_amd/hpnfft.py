@@ -67,10 +67,15 @@ def _load():
         "hpnfft_adjoint_backward": (ctypes.c_int, [P, P, P, P, P]),
         "hpnfft_ewald_recip": (ctypes.c_int, [P, P, ctypes.c_double, ctypes.c_double, P, P]),
         "hpnfft_autotune": (ctypes.c_int, [P, P, P, ip, ip, ip]),
+        "hpnfft_ewald_real": (ctypes.c_int, [P, P, ctypes.c_int64, ctypes.c_double, ctypes.c_double,
+                                             ctypes.c_double, P, P, P, P]),
         "hpnfft_plan_info": (ctypes.c_int, [P, i64p, i64p]),
         "hpnfft_batch_capture": (ctypes.c_int, [P, P, P]),
         "hpnfft_batch_launch": (ctypes.c_int, [P]),
         "hpnfft_batch_offsets": (ctypes.c_int, [P, ctypes.c_int, i64p, i64p]),
+        "hpnfft_profile": (ctypes.c_int, [P, ctypes.c_int]),
+        "hpnfft_profile_read": (ctypes.c_int, [P, P, P]),
+        "hpnfft_phase_name": (ctypes.c_char_p, [ctypes.c_int]),
         "hpnfft_window_eval": (ctypes.c_int, [ctypes.c_int, ctypes.c_double, ctypes.c_int64, P, P, P]),
         "hpnfft_window_rolloff": (ctypes.c_int, [ctypes.c_int, ctypes.c_double, ctypes.c_int64,
                                                  ctypes.c_int64, P]),
@@ -295,6 +300,25 @@ class Plan:
         _check(lib.hpnfft_autotune(self._h, _ptr(f), _ptr(fh), ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)),
                "autotune")
         return a.value, b.value, c.value
+
+    # live timing ------------------------------------------------------------
+    NPHASES = 14
+
+    def profile(self, enable: bool = True):
+        """Record HIP events around every kernel group on the plan's stream."""
+        self._sync_stream()
+        _check(_load().hpnfft_profile(self._h, 1 if enable else 0), "profile")
+
+    def profile_read(self) -> dict:
+        """{phase: (total_ms, launches)} for the calls since the last read."""
+        import numpy as np
+        ms = np.zeros(self.NPHASES, dtype=np.float64)
+        cnt = np.zeros(self.NPHASES, dtype=np.int64)
+        _check(_load().hpnfft_profile_read(self._h, ms.ctypes.data_as(ctypes.c_void_p),
+                                           cnt.ctypes.data_as(ctypes.c_void_p)), "profile_read")
+        lib = _load()
+        return {lib.hpnfft_phase_name(i).decode(): (float(ms[i]), int(cnt[i]))
+                for i in range(self.NPHASES) if cnt[i]}
 
     # batch graph
     def capture(self, f: torch.Tensor, fhat_out: torch.Tensor):

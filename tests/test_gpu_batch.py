@@ -1,0 +1,137 @@
+"""Batching (many independent transforms with uneven M and N per launch) and
+HIP-graph replay.
+
+  * a mixed batch against the oracle, transform by transform;
+  * the batch equals the same transforms run one plan at a time;
+  * the graph-captured batch adjoint, replayed several times with other eager
+    GPU work and synchronisations between replays, matches the eager result
+    every time;
+  * the 256-transform workload (M log-uniform in [1e3, 1e6], N in
+    {32, 48, 64, 96}^3, complex64, m = 4) on sampled frequencies per transform.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def H():
+    from paper_2001_01583_amd import hpnfft
+    hpnfft._load()
+    return hpnfft
+
+
+def _pack(elems, prec):
+    cd = np.complex128 if prec == "f64" else np.complex64
+    x = np.concatenate([e["x"] for e in elems])
+    f = np.concatenate([e["f"] for e in elems]).astype(cd)
+    return x, f
+
+
+def _mixed(seed, sizes):
+    g = W.rng(seed)
+    out = []
+    for (N, M) in sizes:
+        out.append(dict(N=N, x=W.uniform_points(M, 3, g), f=W.complex_normal(M, g)))
+    return out
+
+
+SIZES = [((16, 16, 16), 900), ((24, 24, 24), 50), ((32, 16, 24), 3000), ((16, 16, 16), 1),
+         ((12, 12, 12), 400), ((32, 32, 32), 5000)]
+
+
+@pytest.mark.parametrize("prec,m,tol", [("f64", 8, 1e-12), ("f32", 4, 1e-5)])
+def test_mixed_batch_against_oracle(H, oracle_mod, prec, m, tol):
+    elems = _mixed(501, SIZES)
+    x, f = _pack(elems, prec)
+    plan = H.Plan([e["N"] for e in elems], [e["x"].shape[0] for e in elems], m=m, precision=prec)
+    plan.set_points(torch.from_numpy(x).cuda())
+    out = plan.adjoint(torch.from_numpy(f).cuda()).cpu().numpy().astype(np.complex128)
+    fo = W.rng(502)
+    fh_all = []
+    for b, e in enumerate(elems):
+        po, fo_off = plan.offsets(b)
+        nb = int(np.prod(e["N"]))
+        fu = f[po:po + e["x"].shape[0]].astype(np.complex128)
+        ref = oracle_mod.ndft_adjoint(e["N"], e["x"], fu).reshape(-1)
+        err = oracle_mod.rel_l2(out[fo_off:fo_off + nb], ref)
+        print("batch %s b=%d N=%s M=%d rel-l2 %.3e" % (prec, b, e["N"], e["x"].shape[0], err))
+        assert err <= tol
+        fh_all.append(W.complex_normal(nb, fo))
+    # forward of the whole batch
+    cd = np.complex128 if prec == "f64" else np.complex64
+    fh = np.concatenate(fh_all).astype(cd)
+    back = plan.forward(torch.from_numpy(fh).cuda()).cpu().numpy().astype(np.complex128)
+    for b, e in enumerate(elems):
+        po, fo_off = plan.offsets(b)
+        nb = int(np.prod(e["N"]))
+        ref = oracle_mod.ndft_forward(e["N"], e["x"], fh[fo_off:fo_off + nb].astype(np.complex128).reshape(e["N"]))
+        err = oracle_mod.rel_l2(back[po:po + e["x"].shape[0]], ref)
+        assert err <= tol
+
+
+def test_batch_equals_single_plans(H):
+    elems = _mixed(503, SIZES)
+    x, f = _pack(elems, "f64")
+    plan = H.Plan([e["N"] for e in elems], [e["x"].shape[0] for e in elems], m=6, precision="f64")
+    plan.set_points(torch.from_numpy(x).cuda())
+    out = plan.adjoint(torch.from_numpy(f).cuda()).cpu().numpy()
+    for b, e in enumerate(elems):
+        po, fo = plan.offsets(b)
+        single = H.Plan(e["N"], e["x"].shape[0], m=6, precision="f64")
+        single.set_points(torch.from_numpy(e["x"]).cuda())
+        s = single.adjoint(torch.from_numpy(f[po:po + e["x"].shape[0]]).cuda()).cpu().numpy().reshape(-1)
+        nb = s.size
+        assert np.linalg.norm(out[fo:fo + nb] - s) <= 1e-13 * np.linalg.norm(s)
+
+
+def test_graph_replay_matches_eager(H):
+    elems = _mixed(504, SIZES)
+    x, f = _pack(elems, "f32")
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        plan = H.Plan([e["N"] for e in elems], [e["x"].shape[0] for e in elems], m=4, precision="f32")
+        plan.set_points(torch.from_numpy(x).cuda())
+        ft = torch.from_numpy(f).cuda()
+        eager = plan.adjoint(ft).clone()
+        out = torch.empty_like(eager)
+        plan.capture(ft, out)
+        other = torch.randn(1 << 20, device="cuda")
+        for rep in range(4):
+            out.zero_()
+            plan.replay()
+            torch.cuda.synchronize()
+            err = (out - eager).abs().max().item() / eager.abs().max().item()
+            print("replay %d max rel diff %.3e" % (rep, err))
+            assert err <= 1e-5
+            # eager work and another plan's eager call between replays
+            other = other * 1.0001 + 1.0
+            plan.adjoint(ft)
+            torch.cuda.synchronize()
+    torch.cuda.synchronize()
+
+
+def test_c4_batch_sampled(H, oracle_mod):
+    """The 256-transform workload, 8 sampled frequencies per transform."""
+    elems = W.c4(256)
+    x, f = _pack(elems, "f32")
+    plan = H.Plan([e["N"] for e in elems], [e["x"].shape[0] for e in elems], m=4, precision="f32")
+    plan.set_points(torch.from_numpy(x).cuda())
+    out = plan.adjoint(torch.from_numpy(f).cuda()).cpu().numpy().astype(np.complex128)
+    g = W.rng(505)
+    worst = 0.0
+    for b in range(0, 256, 5):
+        e = elems[b]
+        po, fo = plan.offsets(b)
+        nb = int(np.prod(e["N"]))
+        kidx = W.sample_indices(nb, 8, g)
+        fu = f[po:po + e["x"].shape[0]].astype(np.complex128)
+        ref = oracle_mod.ndft_adjoint(e["N"], e["x"], fu, kidx=kidx)
+        err = oracle_mod.rel_l2(out[fo:fo + nb][kidx], ref)
+        worst = max(worst, err)
+    print("C4 worst sampled rel-l2 %.3e" % worst)
+    assert worst <= 1e-5

@@ -235,3 +235,22 @@ def test_c2_full_size_sampled(H, oracle_mod, prec, m):
     print("C2 %s m=%d adjoint %.3e forward %.3e" % (prec, m, e1, e2))
     target = 1e-12 if prec == "f64" else 1e-5
     assert e1 <= target and e2 <= target
+
+
+def test_c3_clustered_precision(H, oracle_mod):
+    """N = 128^3, M = 2^23 (half uniform, half in 64 Gaussian clusters of
+    std 0.02), m = 4: the FP32 path against the FP64 path over all of I_N,
+    and both against the oracle on 48 sampled frequencies; <= 1e-5."""
+    c = W.c3()
+    g = W.rng(307)
+    x, f = c["x"], c["f"]
+    got32, _ = run_adjoint(H, c["N"], x, f, 4, "f32")
+    got64, _ = run_adjoint(H, c["N"], x, f, 4, "f64")
+    e_32_64 = oracle_mod.rel_l2(got32, got64)
+    kidx = W.sample_indices(128 ** 3, 48, g)
+    ref = oracle_mod.ndft_adjoint(c["N"], x, f_used(f, "f32"), kidx=kidx)
+    e32 = oracle_mod.rel_l2(got32.reshape(-1)[kidx], ref)
+    ref64 = oracle_mod.ndft_adjoint(c["N"], x, f, kidx=kidx)
+    e64 = oracle_mod.rel_l2(got64.reshape(-1)[kidx], ref64)
+    print("C3 fp32 vs fp64 (all I_N) %.3e; fp32 vs oracle %.3e; fp64(m=4) vs oracle %.3e" % (e_32_64, e32, e64))
+    assert e_32_64 <= 1e-5 and e32 <= 1e-5 and e64 <= tol(4, "f64")
