@@ -65,7 +65,7 @@ __host__ __device__ constexpr size_t rec_off_pz(int M2, size_t R) { return 3 * M
 
 // LDS layout of the spread / interpolation kernels (bytes from the start of
 // the dynamic LDS block).  kind: 0 spread, 1 interpolation, 2 gradient.
-//   [tile][stage: cap records][slot_p: cap ints][run_p0: 3T^2][run_soff: 3T^2+1]
+//   [tile][stage: cap records][slot maps: 2 x cap ints][run_p0: 3T^2][run_soff: 3T^2+1]
 //   [scan scratch: 32 ints][interpolation outputs: cap x 2 NO reals]
 constexpr size_t kLdsLimit = 160 * 1024 - 512;
 struct LdsLayout {
@@ -82,7 +82,7 @@ __host__ __device__ inline LdsLayout lds_layout(int T, int Zs, int M2, size_t R,
     L.tile = 0;
     L.stage = align16((size_t)Zs * P * P * 2 * R * ((kind == 0 && comp) ? 2 : 1));
     L.slot_p = L.stage + (size_t)cap * st;
-    L.run_p0 = L.slot_p + (size_t)cap * 4;
+    L.run_p0 = L.slot_p + (size_t)cap * 8;
     L.run_soff = L.run_p0 + nr * 4;
     L.sh = align16(L.run_soff + (nr + 1) * 4);
     L.out = L.sh + 32 * 4;
@@ -96,7 +96,7 @@ inline LdsLayout lds_fit(int T, int Zs, int M2, size_t R, int kind, bool comp)
     LdsLayout lo = lds_layout(T, Zs, M2, R, kind, comp, 0);
     if (lo.total > kLdsLimit) return LdsLayout{};
     size_t st = kind == 2 ? rec_size(M2, R, true) : rec_prefix(M2, R);
-    size_t per = st + 4 + (kind ? 2 * (kind == 2 ? 4 : 1) * R : 0);
+    size_t per = st + 8 + (kind ? 2 * (kind == 2 ? 4 : 1) * R : 0);
     int cap = (int)((kLdsLimit - lo.total) / per);
     if (cap > 2048) cap = 2048;
     while (cap > 0 && lds_layout(T, Zs, M2, R, kind, comp, cap).total > kLdsLimit) --cap;

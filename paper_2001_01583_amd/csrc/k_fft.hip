@@ -21,6 +21,7 @@ namespace hpnfft {
 
 constexpr int kFftThreads = 256;
 constexpr int kFftCap = 2112;  // complex elements per LDS buffer
+constexpr int kLoadU = 8;      // loads in flight per thread
 
 template <typename R> struct C2 { R x, y; };
 
@@ -180,13 +181,29 @@ __global__ __launch_bounds__(kFftThreads) void k_fft(int pass, const Xform *__re
     };
 
     // ---- load ----
+    // kLoadU independent loads per thread are in flight before any LDS write
+    // (indices clamped into range, so the loads need no branch).
     if (g.crop) {
         const int tot = cnt * n;
-        for (int e = tid; e < tot; e += nthr) {
-            int p, j;
-            if (inner == 1) { p = e / n; j = e - p * n; }
-            else { j = e / cnt; p = e - j * cnt; }
-            bufA[p * ld + j] = src[addr(p, j, n)];
+        for (int base = 0; base < tot; base += kLoadU * nthr) {
+            R vx[kLoadU], vy[kLoadU];
+            int at[kLoadU];
+#pragma unroll
+            for (int u = 0; u < kLoadU; ++u) {
+                int e = base + tid + u * nthr;
+                at[u] = -1;
+                int ec = e < tot ? e : tot - 1;
+                int p, j;
+                if (inner == 1) { p = ec / n; j = ec - p * n; }
+                else { j = ec / cnt; p = ec - j * cnt; }
+                C2<R> w = src[addr(p, j, n)];
+                vx[u] = w.x;
+                vy[u] = w.y;
+                if (e < tot) at[u] = p * ld + j;
+            }
+#pragma unroll
+            for (int u = 0; u < kLoadU; ++u)
+                if (at[u] >= 0) bufA[at[u]] = C2<R>{vx[u], vy[u]};
         }
     } else {
         for (int e = tid; e < cnt * n; e += nthr) {
@@ -195,20 +212,33 @@ __global__ __launch_bounds__(kFftThreads) void k_fft(int pass, const Xform *__re
         }
         __syncthreads();
         const int N = g.N, tot = cnt * N;
-        for (int e = tid; e < tot; e += nthr) {
-            int p, i;
-            if (inner == 1) { p = e / N; i = e - p * N; }
-            else { i = e / cnt; p = e - i * cnt; }
-            C2<R> v = src[addr(p, i, N)];
-            if (g.roll_in) {
-                int ii = W.inner0 + p;
-                double f = X.roll[0][i] * X.roll[1][ii / X.N[2]] * X.roll[2][ii % X.N[2]];
-                v.x = (R)(v.x * f);
-                v.y = (R)(v.y * f);
+        for (int base = 0; base < tot; base += kLoadU * nthr) {
+            R vx[kLoadU], vy[kLoadU];
+            int at[kLoadU];
+#pragma unroll
+            for (int u = 0; u < kLoadU; ++u) {
+                int e = base + tid + u * nthr;
+                at[u] = -1;
+                int ec = e < tot ? e : tot - 1;
+                int p, i;
+                if (inner == 1) { p = ec / N; i = ec - p * N; }
+                else { i = ec / cnt; p = ec - i * cnt; }
+                C2<R> w = src[addr(p, i, N)];
+                if (g.roll_in) {
+                    int ii = W.inner0 + p;
+                    double f = X.roll[0][i] * X.roll[1][ii / X.N[2]] * X.roll[2][ii % X.N[2]];
+                    w.x = (R)(w.x * f);
+                    w.y = (R)(w.y * f);
+                }
+                vx[u] = w.x;
+                vy[u] = w.y;
+                int bin = i - N / 2;
+                if (bin < 0) bin += n;
+                if (e < tot) at[u] = p * ld + bin;
             }
-            int bin = i - N / 2;
-            if (bin < 0) bin += n;
-            bufA[p * ld + bin] = v;
+#pragma unroll
+            for (int u = 0; u < kLoadU; ++u)
+                if (at[u] >= 0) bufA[at[u]] = C2<R>{vx[u], vy[u]};
         }
     }
     __syncthreads();

@@ -219,24 +219,56 @@ __device__ inline int build_runs(const ItemGeom &g, int T, const int *__restrict
     return total;
 }
 
-// Step 2: slot -> sorted point map of the chunk [cs, cs + cnt) and the copy of
-// the records (st16 16-byte units each) into LDS.  Contains barriers.
-__device__ inline void stage_chunk(int cs, int cnt, int nr, const int *run_p0, const int *run_soff, int *slot_p,
-                                   uint4 *stage, int st16, const uint4 *__restrict__ rec, int rs16)
+// Step 2: chunks of the item's point stream are staged into LDS.  While a
+// chunk is swept, the next chunk's records are already loading into
+// registers (up to PF 16-byte units per thread; any remainder is copied
+// after the sweep), so HBM latency overlaps the sweep.
+
+// 16-byte unit of the record copies (a native vector type, so that the
+// prefetch array is kept in registers).
+typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+
+// slot -> sorted point map of the chunk [cs, cs + cnt).  No barrier.
+__device__ inline void chunk_slots(int cs, int cnt, int nr, const int *run_p0, const int *run_soff, int *slot_p)
 {
-    const int tid = threadIdx.x, nthr = blockDim.x;
-    for (int s = tid; s < cnt; s += nthr) {
+    for (int s = threadIdx.x; s < cnt; s += blockDim.x) {
         int v = cs + s;
         int r = find_run(run_soff, nr, v);
         slot_p[s] = run_p0[r] + (v - run_soff[r]);
     }
-    __syncthreads();
+}
+
+template <int PF>
+__device__ inline void chunk_fetch(int cnt, const int *slot_p, int st16, const v4u *__restrict__ rec, int rs16,
+                                   v4u (&reg)[PF])
+{
+    // every thread loads PF units; indices past the chunk reload unit 0 (the
+    // chunk is never empty), so the loads need no branch and the array stays
+    // in registers
     const int tot = cnt * st16;
-    for (int e = tid; e < tot; e += nthr) {
-        int sl = e / st16, q = e - sl * st16;
-        stage[e] = rec[(size_t)slot_p[sl] * rs16 + q];
+#pragma unroll
+    for (int k = 0; k < PF; ++k) {
+        int e = threadIdx.x + k * blockDim.x;
+        e = e < tot ? e : 0;
+        int sl = e / st16;
+        reg[k] = rec[(size_t)slot_p[sl] * rs16 + (e - sl * st16)];
     }
-    __syncthreads();
+}
+
+template <int PF>
+__device__ inline void chunk_store(int cnt, const int *slot_p, int st16, const v4u *__restrict__ rec, int rs16,
+                                   const v4u (&reg)[PF], v4u *stage)
+{
+    const int tot = cnt * st16;
+#pragma unroll
+    for (int k = 0; k < PF; ++k) {
+        int e = threadIdx.x + k * blockDim.x;
+        if (e < tot) stage[e] = reg[k];
+    }
+    for (int e = threadIdx.x + PF * blockDim.x; e < tot; e += blockDim.x) {
+        int sl = e / st16;
+        stage[e] = rec[(size_t)slot_p[sl] * rs16 + (e - sl * st16)];
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -247,7 +279,7 @@ template <typename R, int M2, bool COMP>
 __global__ __launch_bounds__(1024) void k_spread(const Xform *__restrict__ xfs,
                                                  const SItem *__restrict__ items, int nitems,
                                                  int *__restrict__ queue, int T, int Zs, int cap,
-                                                 const uint4 *__restrict__ rec, int rs16,
+                                                 const v4u *__restrict__ rec, int rs16,
                                                  const int *__restrict__ cell_start)
 {
     constexpr int m = M2 / 2;
@@ -264,13 +296,15 @@ __global__ __launch_bounds__(1024) void k_spread(const Xform *__restrict__ xfs,
     const int plane = P * P;
     R *acc = reinterpret_cast<R *>(smem + LL.tile);
     unsigned long long *pairs = reinterpret_cast<unsigned long long *>(smem + LL.tile);
-    uint4 *stage = reinterpret_cast<uint4 *>(smem + LL.stage);
-    int *slot_p = reinterpret_cast<int *>(smem + LL.slot_p);
+    v4u *stage = reinterpret_cast<v4u *>(smem + LL.stage);
+    int *slot_a = reinterpret_cast<int *>(smem + LL.slot_p);
+    int *slot_b = slot_a + cap;
     int *run_p0 = reinterpret_cast<int *>(smem + LL.run_p0);
     int *run_soff = reinterpret_cast<int *>(smem + LL.run_soff);
     int *sh = reinterpret_cast<int *>(smem + LL.sh);
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int wave = tid >> 6, lane = tid & 63, nwaves = nthr >> 6;
+    constexpr int PF = (sizeof(R) == 8 && M2 >= 12) ? 2 : 4;
 
     for (int it = next_item(queue, &s_item); it < nitems; it = next_item(queue, &s_item)) {
         const ItemGeom g = item_geom(items[it], xfs[items[it].xf], T, Zs, M2);
@@ -289,9 +323,27 @@ __global__ __launch_bounds__(1024) void k_spread(const Xform *__restrict__ xfs,
         const int nr = 3 * (g.le - g.lb);
         const int S = build_runs<M2>(g, T, cell_start, run_p0, run_soff, sh);
 
-        for (int cs = 0; cs < S; cs += cap) {
+        const int nch = (S + cap - 1) / cap;
+        v4u reg[PF];
+        if (nch > 0) {
+            const int c0n = min(cap, S);
+            chunk_slots(0, c0n, nr, run_p0, run_soff, slot_a);
+            __syncthreads();
+            chunk_fetch<PF>(c0n, slot_a, ST16, rec, rs16, reg);
+            chunk_store<PF>(c0n, slot_a, ST16, rec, rs16, reg, stage);
+            __syncthreads();
+        }
+        for (int ch = 0; ch < nch; ++ch) {
+            const int cs = ch * cap;
             const int cnt = min(cap, S - cs);
-            stage_chunk(cs, cnt, nr, run_p0, run_soff, slot_p, stage, ST16, rec, rs16);
+            int *slot_n = (ch & 1) ? slot_a : slot_b;
+            const bool more = ch + 1 < nch;
+            const int cntn = more ? min(cap, S - cs - cap) : 0;
+            if (more) {
+                chunk_slots(cs + cap, cntn, nr, run_p0, run_soff, slot_n);
+                __syncthreads();
+                chunk_fetch<PF>(cntn, slot_n, ST16, rec, rs16, reg);
+            }
             const int r_lo = find_run(run_soff, nr, cs);
             const int r_hi = find_run(run_soff, nr, cs + cnt - 1);
             const int ntask = (r_hi - r_lo + 1) * NRG;
@@ -357,6 +409,10 @@ __global__ __launch_bounds__(1024) void k_spread(const Xform *__restrict__ xfs,
                 for (int s = 0; s < M2; ++s) flush(s, Bw + (s >= rr ? s - rr : s - rr + M2));
             }
             __syncthreads();
+            if (more) {
+                chunk_store<PF>(cntn, slot_n, ST16, rec, rs16, reg, stage);
+                __syncthreads();
+            }
         }
 
         R *grid = reinterpret_cast<R *>(xfs[items[it].xf].grid);
@@ -388,7 +444,7 @@ __global__ __launch_bounds__(1024) void k_spread(const Xform *__restrict__ xfs,
 template <typename R, int M2, bool GRAD>
 __global__ __launch_bounds__(interp_max_threads(sizeof(R), M2, GRAD)) void k_interp(
     const Xform *__restrict__ xfs, const SItem *__restrict__ items, int nitems, int *__restrict__ queue,
-    int T, int Zs, int cap, const uint4 *__restrict__ rec, int rs16, const int *__restrict__ cell_start,
+    int T, int Zs, int cap, const v4u *__restrict__ rec, int rs16, const int *__restrict__ cell_start,
     R *__restrict__ outs)
 {
     constexpr int m = M2 / 2;
@@ -405,14 +461,16 @@ __global__ __launch_bounds__(interp_max_threads(sizeof(R), M2, GRAD)) void k_int
     const int P = T + M2 - 1;
     const int plane = P * P;
     R *tile = reinterpret_cast<R *>(smem + LL.tile);
-    uint4 *stage = reinterpret_cast<uint4 *>(smem + LL.stage);
-    int *slot_p = reinterpret_cast<int *>(smem + LL.slot_p);
+    v4u *stage = reinterpret_cast<v4u *>(smem + LL.stage);
+    int *slot_a = reinterpret_cast<int *>(smem + LL.slot_p);
+    int *slot_b = slot_a + cap;
     int *run_p0 = reinterpret_cast<int *>(smem + LL.run_p0);
     int *run_soff = reinterpret_cast<int *>(smem + LL.run_soff);
     int *sh = reinterpret_cast<int *>(smem + LL.sh);
     R *oacc = reinterpret_cast<R *>(smem + LL.out);
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int wave = tid >> 6, lane = tid & 63, nwaves = nthr >> 6;
+    constexpr int PF = (sizeof(R) == 8 && M2 >= 12) || GRAD ? 2 : 4;
 
     for (int it = next_item(queue, &s_item); it < nitems; it = next_item(queue, &s_item)) {
         const ItemGeom g = item_geom(items[it], xfs[items[it].xf], T, Zs, M2);
@@ -430,9 +488,28 @@ __global__ __launch_bounds__(interp_max_threads(sizeof(R), M2, GRAD)) void k_int
         const int nr = 3 * (g.le - g.lb);
         const int S = build_runs<M2>(g, T, cell_start, run_p0, run_soff, sh);
 
-        for (int cs = 0; cs < S; cs += cap) {
+        const int nch = (S + cap - 1) / cap;
+        v4u reg[PF];
+        if (nch > 0) {
+            const int c0n = min(cap, S);
+            chunk_slots(0, c0n, nr, run_p0, run_soff, slot_a);
+            __syncthreads();
+            chunk_fetch<PF>(c0n, slot_a, ST16, rec, rs16, reg);
+            chunk_store<PF>(c0n, slot_a, ST16, rec, rs16, reg, stage);
+            __syncthreads();
+        }
+        for (int ch = 0; ch < nch; ++ch) {
+            const int cs = ch * cap;
             const int cnt = min(cap, S - cs);
-            stage_chunk(cs, cnt, nr, run_p0, run_soff, slot_p, stage, ST16, rec, rs16);
+            int *slot_p = (ch & 1) ? slot_b : slot_a;
+            int *slot_n = (ch & 1) ? slot_a : slot_b;
+            const bool more = ch + 1 < nch;
+            const int cntn = more ? min(cap, S - cs - cap) : 0;
+            if (more) {
+                chunk_slots(cs + cap, cntn, nr, run_p0, run_soff, slot_n);
+                __syncthreads();
+                chunk_fetch<PF>(cntn, slot_n, ST16, rec, rs16, reg);
+            }
             const int r_lo = find_run(run_soff, nr, cs);
             const int r_hi = find_run(run_soff, nr, cs + cnt - 1);
             // task = one run piece (all row groups); the piece's points are
@@ -535,6 +612,10 @@ __global__ __launch_bounds__(interp_max_threads(sizeof(R), M2, GRAD)) void k_int
                 if (v != R(0)) atomicAdd(&outs[(size_t)slot_p[e / (2 * NO)] * (2 * NO) + e % (2 * NO)], v);
             }
             __syncthreads();
+            if (more) {
+                chunk_store<PF>(cntn, slot_n, ST16, rec, rs16, reg, stage);
+                __syncthreads();
+            }
         }
     }
 }
@@ -568,7 +649,7 @@ static hipError_t spread_m(const Xform *dxf, const SItem *items, int nitems, int
     int grid = std::min(cu_count() * per_cu, nitems);
     if (grid < 1) return hipSuccess;
     hipLaunchKernelGGL(kern, dim3(grid), dim3(t.threads), LL.total, s, dxf, items, nitems, queue, t.T, t.Zs,
-                       LL.cap, (const uint4 *)rec, (int)(rec_bytes / 16), cs);
+                       LL.cap, (const v4u *)rec, (int)(rec_bytes / 16), cs);
     return hipGetLastError();
 }
 
@@ -588,7 +669,7 @@ static hipError_t interp_m(const Xform *dxf, const SItem *items, int nitems, int
     if (grid < 1) return hipSuccess;
     int threads = std::min(t.threads, interp_max_threads(sizeof(R), M2, GRAD));
     hipLaunchKernelGGL(kern, dim3(grid), dim3(threads), LL.total, s, dxf, items, nitems, queue, t.T, t.Zs,
-                       LL.cap, (const uint4 *)rec, (int)(rec_bytes / 16), cs, outs);
+                       LL.cap, (const v4u *)rec, (int)(rec_bytes / 16), cs, outs);
     return hipGetLastError();
 }
 

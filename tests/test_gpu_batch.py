@@ -135,3 +135,22 @@ def test_c4_batch_sampled(H, oracle_mod):
         worst = max(worst, err)
     print("C4 worst sampled rel-l2 %.3e" % worst)
     assert worst <= 1e-5
+
+
+def test_autotuner_keeps_results(H, oracle_mod):
+    """The tiling autotuner times candidate tilings on the plan's own points
+    and keeps the fastest; results before and after agree with the oracle."""
+    g = W.rng(506)
+    N = (24, 24, 24)
+    x = W.uniform_points(20000, 3, g)
+    f = W.complex_normal(20000, g).astype(np.complex64)
+    plan = H.Plan(N, 20000, m=4, precision="f32")
+    plan.set_points(torch.from_numpy(x).cuda())
+    before = plan.adjoint(torch.from_numpy(f).cuda()).cpu().numpy()
+    tiles = plan.autotune()
+    assert tiles == plan.tiles and tiles[0] >= 4 and tiles[2] % 64 == 0
+    after = plan.adjoint(torch.from_numpy(f).cuda()).cpu().numpy()
+    kidx = W.sample_indices(24 ** 3, 64, g)
+    ref = oracle_mod.ndft_adjoint(N, x, f.astype(np.complex128), kidx=kidx)
+    for out in (before, after):
+        assert oracle_mod.rel_l2(out.reshape(-1)[kidx].astype(np.complex128), ref) <= 1e-5
