@@ -107,9 +107,13 @@ inline LdsLayout lds_fit(int T, int Zs, int M2, size_t R, int kind, bool comp)
 // Threads per workgroup the interpolation kernel is compiled for: float64
 // windows of 2m >= 12 (and the gradient variant from 2m >= 6) need more than
 // the 128 registers a 1024-thread workgroup leaves per lane.
+__host__ __device__ constexpr int spread_max_threads(int real_bytes, int M2)
+{
+    return real_bytes == 8 && M2 >= 12 ? 512 : 1024;
+}
 __host__ __device__ constexpr int interp_max_threads(int real_bytes, int M2, bool grad)
 {
-    return (real_bytes == 8 && (M2 >= 12 || (grad && M2 >= 6))) || (grad && M2 >= 14) ? 512 : 1024;
+    return (real_bytes == 8 && (M2 >= 6 || grad)) || M2 >= 12 ? 512 : 1024;
 }
 
 // FFT pass identifiers.

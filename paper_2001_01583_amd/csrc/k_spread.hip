@@ -31,8 +31,13 @@
 #include <algorithm>
 
 #include "internal.h"
+#include "wave_reduce.h"
 
 namespace hpnfft {
+
+// Value known to be equal on all lanes of the wavefront, moved to a scalar
+// register so that branches on it are scalar branches.
+__device__ inline int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
 __device__ inline int wrapn(int c, int n)
 {
@@ -48,55 +53,39 @@ __device__ inline void seg_range(int U, int z0, int zs, int m, int n0, int *a, i
     *b = hi > n0 - 1 ? n0 - 1 : hi;
 }
 
-template <int CTRL>
-__device__ inline float dpp_mov(float v)
+// Compensated float adds into two LDS cells (the real and imaginary part of
+// one grid value), each holding (sum, compensation) as one 64-bit word:
+// TwoSum (Knuth) of the stored sum and v gives the new sum and its exact
+// rounding error, which joins the compensation; each pair is published with
+// a 64-bit compare-and-swap.  Both parts are in flight together.  The
+// initial read is only a guess (a stale or torn value just fails the CAS).
+// (gfx950's native LDS float32 atomic add is about 13x slower than this.)
+__device__ __forceinline__ unsigned long long twosum_pair(unsigned long long old, float v)
 {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
-}
-template <int CTRL>
-__device__ inline double dpp_mov(double v)
-{
-    long long b = __double_as_longlong(v);
-    int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), CTRL, 0xF, 0xF, true);
-    int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, true);
-    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-
-// Sum over the 64 lanes; every lane receives the same total.  Within a row of
-// 16 lanes: xor-1 and xor-2 quad permutations, then half-row and row mirrors;
-// across rows: two lane-xor shuffles.
-template <typename R>
-__device__ inline R wave_sum(R v)
-{
-    v += dpp_mov<0xB1>(v);   // quad_perm [1,0,3,2]
-    v += dpp_mov<0x4E>(v);   // quad_perm [2,3,0,1]
-    v += dpp_mov<0x141>(v);  // row_half_mirror
-    v += dpp_mov<0x140>(v);  // row_mirror
-    v += __shfl_xor(v, 16, 64);
-    v += __shfl_xor(v, 32, 64);
-    return v;
+    const float sm = __uint_as_float((unsigned int)old);
+    const float cp = __uint_as_float((unsigned int)(old >> 32));
+    const float t = sm + v;
+    const float bp = t - sm;
+    const float e = (sm - (t - bp)) + (v - bp);
+    return (unsigned long long)__float_as_uint(t) | ((unsigned long long)__float_as_uint(cp + e) << 32);
 }
 
-// Compensated float add into an LDS cell holding (sum, compensation) as one
-// 64-bit word: TwoSum (Knuth) of the stored sum and v gives the new sum and
-// its exact rounding error, which joins the compensation; the pair is
-// published with a 64-bit compare-and-swap.  (gfx950's native LDS float32
-// atomic add is about 13x slower than this loop when uncontended.)
-__device__ inline void lds_add_comp(unsigned long long *cell, float v)
+__device__ __forceinline__ void lds_add_comp2(unsigned long long *cell, float vr, float vi)
 {
-    unsigned long long old = *reinterpret_cast<volatile unsigned long long *>(cell);
-    for (;;) {
-        float sm = __uint_as_float((unsigned int)old);
-        float cp = __uint_as_float((unsigned int)(old >> 32));
-        float t = sm + v;
-        float bp = t - sm;
-        float e = (sm - (t - bp)) + (v - bp);
-        unsigned long long nw = (unsigned long long)__float_as_uint(t) |
-                                ((unsigned long long)__float_as_uint(cp + e) << 32);
-        unsigned long long prev = atomicCAS(cell, old, nw);
-        if (prev == old) return;
-        old = prev;
-    }
+    unsigned long long o0 = cell[0], o1 = cell[1];
+    bool d0 = false, d1 = false;
+    do {
+        if (!d0) {
+            const unsigned long long pr = atomicCAS(cell, o0, twosum_pair(o0, vr));
+            d0 = pr == o0;
+            o0 = pr;
+        }
+        if (!d1) {
+            const unsigned long long pr = atomicCAS(cell + 1, o1, twosum_pair(o1, vi));
+            d1 = pr == o1;
+            o1 = pr;
+        }
+    } while (!(d0 && d1));
 }
 
 // Exclusive scan of one int per thread over the workgroup (<= 1024 threads);
@@ -228,6 +217,14 @@ __device__ inline int build_runs(const ItemGeom &g, int T, const int *__restrict
 // prefetch array is kept in registers).
 typedef unsigned int v4u __attribute__((ext_vector_type(4)));
 
+// Window base of a staged point: first tap plane along dim 0 plus 2m (so
+// that it is never negative), as a wave-uniform value.
+constexpr int kNoPlane = 0x7fffffff;
+__device__ inline int plane_of(const v4u *stage, int sl, int st16, int off_pz, int m)
+{
+    return uni(reinterpret_cast<const int *>(stage + sl * st16)[off_pz]) + m + 1;
+}
+
 // slot -> sorted point map of the chunk [cs, cs + cnt).  No barrier.
 __device__ inline void chunk_slots(int cs, int cnt, int nr, const int *run_p0, const int *run_soff, int *slot_p)
 {
@@ -276,7 +273,7 @@ __device__ inline void chunk_store(int cnt, const int *slot_p, int st16, const v
 // cell is a (sum, compensation) pair updated by lds_add_comp.  The float64
 // path adds with the native LDS float64 atomic.
 template <typename R, int M2, bool COMP>
-__global__ __launch_bounds__(1024) void k_spread(const Xform *__restrict__ xfs,
+__global__ __launch_bounds__(spread_max_threads(sizeof(R), M2)) void k_spread(const Xform *__restrict__ xfs,
                                                  const SItem *__restrict__ items, int nitems,
                                                  int *__restrict__ queue, int T, int Zs, int cap,
                                                  const v4u *__restrict__ rec, int rs16,
@@ -303,7 +300,7 @@ __global__ __launch_bounds__(1024) void k_spread(const Xform *__restrict__ xfs,
     int *run_soff = reinterpret_cast<int *>(smem + LL.run_soff);
     int *sh = reinterpret_cast<int *>(smem + LL.sh);
     const int tid = threadIdx.x, nthr = blockDim.x;
-    const int wave = tid >> 6, lane = tid & 63, nwaves = nthr >> 6;
+    const int wave = uni(tid >> 6), lane = tid & 63, nwaves = nthr >> 6;
     constexpr int PF = (sizeof(R) == 8 && M2 >= 12) ? 2 : 4;
 
     for (int it = next_item(queue, &s_item); it < nitems; it = next_item(queue, &s_item)) {
@@ -344,20 +341,20 @@ __global__ __launch_bounds__(1024) void k_spread(const Xform *__restrict__ xfs,
                 __syncthreads();
                 chunk_fetch<PF>(cntn, slot_n, ST16, rec, rs16, reg);
             }
-            const int r_lo = find_run(run_soff, nr, cs);
-            const int r_hi = find_run(run_soff, nr, cs + cnt - 1);
+            const int r_lo = uni(find_run(run_soff, nr, cs));
+            const int r_hi = uni(find_run(run_soff, nr, cs + cnt - 1));
             const int ntask = (r_hi - r_lo + 1) * NRG;
             for (int task = wave; task < ntask; task += nwaves) {
                 const int r = r_lo + task / NRG;
                 const int rg = task % NRG;
-                const int a = max(run_soff[r], cs) - cs;
-                const int b = min(run_soff[r + 1], cs + cnt) - cs;
+                const int a = uni(max(run_soff[r], cs) - cs);
+                const int b = uni(min(run_soff[r + 1], cs + cnt) - cs);
                 if (a >= b) continue;
                 const int li = g.lb + r / 3;
                 const int U = (r % 3 - 1) * g.n0;
                 const int ly = li / T, lx = li % T;
                 const int row = rg * 64 + lane;
-                const bool active = row < ROWS;
+                const bool active = ROWS % 64 == 0 || row < ROWS;
                 const int dy = active ? row / M2 : 0, dx = active ? row % M2 : 0;
                 const size_t lrow = (size_t)(ly + dy) * P + (lx + dx);
                 const int qshift = U - g.z0 - M2;  // slab-relative plane = q + qshift
@@ -366,47 +363,58 @@ __global__ __launch_bounds__(1024) void k_spread(const Xform *__restrict__ xfs,
 #pragma unroll
                 for (int s = 0; s < M2; ++s) wr[s] = wi[s] = R(0);
 
-                auto flush = [&](int s, int q) {
-                    int qr = q + qshift;
-                    if (active && qr >= 0 && qr < g.zs) {
-                        size_t o = ((size_t)qr * plane + lrow) * 2;
+                // add slot s (plane q) into the LDS tile
+                auto flush = [&](int s, int q) __attribute__((always_inline)) {
+                    if (active) {
+                        const size_t o = ((size_t)(q + qshift) * plane + lrow) * 2;
                         if (COMP) {
-                            lds_add_comp(&pairs[o], (float)wr[s]);
-                            lds_add_comp(&pairs[o + 1], (float)wi[s]);
+                            lds_add_comp2(&pairs[o], (float)wr[s], (float)wi[s]);
                         } else {
                             atomicAdd(&acc[o], wr[s]);
                             atomicAdd(&acc[o + 1], wi[s]);
                         }
                     }
-                    wr[s] = R(0);
-                    wi[s] = R(0);
                 };
 
-                int Bw = -1;  // window base plane (first tap plane + 2m), uniform
-                for (int sl = a; sl < b; ++sl) {
-                    const R *ps = reinterpret_cast<const R *>(stage + sl * ST16);
-                    const int B = reinterpret_cast<const int *>(ps)[OFF_PZ] - m + 1 + M2;
-                    if (Bw >= 0 && B != Bw) {
-                        const int rr = Bw % M2;
+                // Plane-major sweep: plane q (in window units, q = first
+                // tap plane + 2m) lives in slot q mod 2m.  The plane loop is
+                // unrolled 2m times, so the slot to retire is a constant;
+                // points whose window starts at plane p are added before p
+                // is retired (after that, their slot is reused for p + 2m).
+                // Only planes f_lo .. f_lo + nf - 1 lie in the slab; the
+                // others are dropped.
+                const int B0 = plane_of(stage, a, ST16, OFF_PZ, m);
+                const int Blast = plane_of(stage, b - 1, ST16, OFF_PZ, m);
+                const int f_lo = max(B0, -qshift);
+                const int nf = max(min(Blast + M2 - 1, g.zs - 1 - qshift) - f_lo + 1, 0);
+                const int p_end = max(Blast, f_lo + nf - 1);
+                int sl = a, Bn = B0, last = B0;
+                int p = B0 - B0 % M2;
+                while (p <= p_end) {
 #pragma unroll
-                        for (int s = 0; s < M2; ++s) {
-                            const int q = Bw + (s >= rr ? s - rr : s - rr + M2);
-                            if (q < B) flush(s, q);
+                    for (int k = 0; k < M2; ++k) {
+                        while (Bn == p) {
+                            const R *ps = reinterpret_cast<const R *>(stage + sl * ST16);
+                            const R w12 = active ? ps[M2 + dy] * ps[2 * M2 + dx] : R(0);
+                            const R sr = ps[OFF_F] * w12, si = ps[OFF_F + 1] * w12;
+#pragma unroll
+                            for (int s = 0; s < M2; ++s) {
+                                const R wz = ps[s];
+                                wr[s] = fma(sr, wz, wr[s]);
+                                wi[s] = fma(si, wz, wi[s]);
+                            }
+                            last = p;
+                            ++sl;
+                            Bn = sl < b ? plane_of(stage, sl, ST16, OFF_PZ, m) : kNoPlane;
                         }
+                        if ((unsigned)(p - f_lo) < (unsigned)nf) flush(k, p);
+                        wr[k] = R(0);
+                        wi[k] = R(0);
+                        ++p;
                     }
-                    Bw = B;
-                    const R w12 = active ? ps[M2 + dy] * ps[2 * M2 + dx] : R(0);
-                    const R sr = ps[OFF_F] * w12, si = ps[OFF_F + 1] * w12;
-#pragma unroll
-                    for (int s = 0; s < M2; ++s) {
-                        const R wz = ps[s];
-                        wr[s] = fma(sr, wz, wr[s]);
-                        wi[s] = fma(si, wz, wi[s]);
-                    }
+                    // window empty and the next point far ahead: skip the gap
+                    if (last + M2 <= p && Bn != kNoPlane && Bn - Bn % M2 > p) p = Bn - Bn % M2;
                 }
-                const int rr = Bw % M2;
-#pragma unroll
-                for (int s = 0; s < M2; ++s) flush(s, Bw + (s >= rr ? s - rr : s - rr + M2));
             }
             __syncthreads();
             if (more) {
@@ -469,7 +477,7 @@ __global__ __launch_bounds__(interp_max_threads(sizeof(R), M2, GRAD)) void k_int
     int *sh = reinterpret_cast<int *>(smem + LL.sh);
     R *oacc = reinterpret_cast<R *>(smem + LL.out);
     const int tid = threadIdx.x, nthr = blockDim.x;
-    const int wave = tid >> 6, lane = tid & 63, nwaves = nthr >> 6;
+    const int wave = uni(tid >> 6), lane = tid & 63, nwaves = nthr >> 6;
     constexpr int PF = (sizeof(R) == 8 && M2 >= 12) || GRAD ? 2 : 4;
 
     for (int it = next_item(queue, &s_item); it < nitems; it = next_item(queue, &s_item)) {
@@ -510,15 +518,15 @@ __global__ __launch_bounds__(interp_max_threads(sizeof(R), M2, GRAD)) void k_int
                 __syncthreads();
                 chunk_fetch<PF>(cntn, slot_n, ST16, rec, rs16, reg);
             }
-            const int r_lo = find_run(run_soff, nr, cs);
-            const int r_hi = find_run(run_soff, nr, cs + cnt - 1);
+            const int r_lo = uni(find_run(run_soff, nr, cs));
+            const int r_hi = uni(find_run(run_soff, nr, cs + cnt - 1));
             // task = one run piece (all row groups); the piece's points are
             // taken 64 at a time, lane (slot - first) owning the outputs of
             // its slot, so every slot has exactly one writer.
             for (int task = wave; task <= r_hi - r_lo; task += nwaves) {
                 const int r = r_lo + task;
-                const int a = max(run_soff[r], cs) - cs;
-                const int b = min(run_soff[r + 1], cs + cnt) - cs;
+                const int a = uni(max(run_soff[r], cs) - cs);
+                const int b = uni(min(run_soff[r + 1], cs + cnt) - cs);
                 if (a >= b) continue;
                 const int li = g.lb + r / 3;
                 const int U = (r % 3 - 1) * g.n0;
@@ -530,79 +538,128 @@ __global__ __launch_bounds__(interp_max_threads(sizeof(R), M2, GRAD)) void k_int
 #pragma unroll
                     for (int i = 0; i < 2 * NO; ++i) ores[i] = R(0);
                     for (int rg = 0; rg < NRG; ++rg) {
-                const int row = rg * 64 + lane;
-                const bool active = row < ROWS;
-                const int dy = active ? row / M2 : 0, dx = active ? row % M2 : 0;
-                const size_t lrow = (size_t)(ly + dy) * P + (lx + dx);
+                        const int row = rg * 64 + lane;
+                        const bool active = ROWS % 64 == 0 || row < ROWS;
+                        const int dy = active ? row / M2 : 0, dx = active ? row % M2 : 0;
+                        const size_t lrow = (size_t)(ly + dy) * P + (lx + dx);
 
-                R gr[M2], gi[M2];
+                        R gr[M2], gi[M2];
 #pragma unroll
-                for (int s = 0; s < M2; ++s) gr[s] = gi[s] = R(0);
-                int Bw = -1;
-                for (int sl = c0; sl < c1; ++sl) {
-                    const R *ps = reinterpret_cast<const R *>(stage + sl * ST16);
-                    const int B = reinterpret_cast<const int *>(ps)[OFF_PZ] - m + 1 + M2;
-                    if (B != Bw) {
-                        const int rn = B % M2;
-                        const int ro = Bw >= 0 ? Bw % M2 : 0;
+                        for (int s = 0; s < M2; ++s) gr[s] = gi[s] = R(0);
+                        // Plane-major sweep (as in the spread): slot q mod 2m
+                        // holds plane q; at plane p the plane p + 2m - 1
+                        // enters, then the points whose window starts at p
+                        // are evaluated.  Partials of consecutive points feed
+                        // a binary counter of cross-lane halving steps: level
+                        // 1 pairs points, level 2 quads, level 3 octets.
+                        auto load = [&](int s, int q) __attribute__((always_inline)) {
+                            const int qr = q + qshift;
+                            if (active && (unsigned)qr < (unsigned)g.zs) {
+                                const size_t o = ((size_t)qr * plane + lrow) * 2;
+                                gr[s] = tile[o];
+                                gi[s] = tile[o + 1];
+                            } else {
+                                gr[s] = R(0);
+                                gi[s] = R(0);
+                            }
+                        };
+                        R s0[2 * NO], s1[2 * NO], s2[2 * NO];
+                        auto feed = [&](int t, R (&v)[2 * NO]) {
+                            if (!(t & 1)) {
 #pragma unroll
-                        for (int s = 0; s < M2; ++s) {
-                            const int qold = Bw + (s >= ro ? s - ro : s - ro + M2);
-                            if (Bw < 0 || qold < B) {
-                                const int qn = B + (s >= rn ? s - rn : s - rn + M2);
-                                const int qr = qn + qshift;
-                                if (active && qr >= 0 && qr < g.zs) {
-                                    size_t o = ((size_t)qr * plane + lrow) * 2;
-                                    gr[s] = tile[o];
-                                    gi[s] = tile[o + 1];
-                                } else {
-                                    gr[s] = R(0);
-                                    gi[s] = R(0);
+                                for (int i = 0; i < 2 * NO; ++i) s0[i] = v[i];
+                                return;
+                            }
+#pragma unroll
+                            for (int i = 0; i < 2 * NO; ++i) v[i] = halve32(s0[i], v[i]);
+                            if (!(t & 2)) {
+#pragma unroll
+                                for (int i = 0; i < 2 * NO; ++i) s1[i] = v[i];
+                                return;
+                            }
+#pragma unroll
+                            for (int i = 0; i < 2 * NO; ++i) v[i] = halve16(s1[i], v[i]);
+                            if (!(t & 4)) {
+#pragma unroll
+                                for (int i = 0; i < 2 * NO; ++i) s2[i] = v[i];
+                                return;
+                            }
+                            // octet t-7 .. t complete: 8-lane group j holds
+                            // point t - 7 + bitrev3(j); lane 8j + (t >> 3) keeps it
+#pragma unroll
+                            for (int i = 0; i < 2 * NO; ++i) {
+                                const R tot = halve8_sum(s2[i], v[i]);
+                                if ((lane & 7) == (t >> 3)) ores[i] += tot;
+                            }
+                        };
+                        int sl = c0;
+                        int Bn = plane_of(stage, c0, ST16, OFF_PZ, m);
+                        int p = Bn - Bn % M2;
+#pragma unroll
+                        for (int s = 0; s < M2 - 1; ++s)
+                            if (p + s >= Bn) load(s, p + s);
+                        while (sl < c1) {
+#pragma unroll
+                            for (int k = 0; k < M2; ++k) {
+                                if (Bn <= p + M2 - 1) load((k + M2 - 1) % M2, p + M2 - 1);
+                                while (Bn == p) {
+                                    const R *ps = reinterpret_cast<const R *>(stage + sl * ST16);
+                                    R sr = R(0), si = R(0);
+#pragma unroll
+                                    for (int s = 0; s < M2; ++s) {
+                                        sr = fma(gr[s], ps[s], sr);
+                                        si = fma(gi[s], ps[s], si);
+                                    }
+                                    const R w1 = active ? ps[M2 + dy] : R(0);
+                                    const R w2 = active ? ps[2 * M2 + dx] : R(0);
+                                    const R w12 = w1 * w2;
+                                    R v[2 * NO];
+                                    v[0] = sr * w12;
+                                    v[1] = si * w12;
+                                    if constexpr (GRAD) {
+                                        const R *dp = ps + OFF_D;
+                                        R dr = R(0), di = R(0);
+#pragma unroll
+                                        for (int s = 0; s < M2; ++s) {
+                                            dr = fma(gr[s], dp[s], dr);
+                                            di = fma(gi[s], dp[s], di);
+                                        }
+                                        const R d1 = active ? dp[M2 + dy] * w2 : R(0);
+                                        const R d2 = active ? w1 * dp[2 * M2 + dx] : R(0);
+                                        v[2] = dr * w12;
+                                        v[3] = di * w12;
+                                        v[4] = sr * d1;
+                                        v[5] = si * d1;
+                                        v[6] = sr * d2;
+                                        v[7] = si * d2;
+                                    }
+                                    feed(sl - c0, v);
+                                    ++sl;
+                                    Bn = sl < c1 ? plane_of(stage, sl, ST16, OFF_PZ, m) : kNoPlane;
                                 }
+                                ++p;
+                            }
+                            // skip a gap: restart the window at the next point
+                            if (sl < c1 && Bn - Bn % M2 > p) {
+                                p = Bn - Bn % M2;
+#pragma unroll
+                                for (int s = 0; s < M2 - 1; ++s)
+                                    if (p + s >= Bn) load(s, p + s);
                             }
                         }
-                        Bw = B;
-                    }
-                    R sr = R(0), si = R(0);
+                        // pad the last octet with zero partials
+                        for (int t = c1 - c0; t & 7; ++t) {
+                            R v[2 * NO];
 #pragma unroll
-                    for (int s = 0; s < M2; ++s) {
-                        sr = fma(gr[s], ps[s], sr);
-                        si = fma(gi[s], ps[s], si);
-                    }
-                    const R w1 = active ? ps[M2 + dy] : R(0);
-                    const R w2 = active ? ps[2 * M2 + dx] : R(0);
-                    const R w12 = w1 * w2;
-                    R v[2 * NO];
-                    v[0] = sr * w12;
-                    v[1] = si * w12;
-                    if (GRAD) {
-                        const R *dp = ps + OFF_D;
-                        R dr = R(0), di = R(0);
-#pragma unroll
-                        for (int s = 0; s < M2; ++s) {
-                            dr = fma(gr[s], dp[s], dr);
-                            di = fma(gi[s], dp[s], di);
+                            for (int i = 0; i < 2 * NO; ++i) v[i] = R(0);
+                            feed(t, v);
                         }
-                        const R d1 = active ? dp[M2 + dy] * w2 : R(0);
-                        const R d2 = active ? w1 * dp[2 * M2 + dx] : R(0);
-                        v[2] = dr * w12;
-                        v[3] = di * w12;
-                        v[4] = sr * d1;
-                        v[5] = si * d1;
-                        v[6] = sr * d2;
-                        v[7] = si * d2;
                     }
-                    const bool mine = lane == sl - c0;
+                    const int j8 = lane >> 3;
+                    const int own = (lane & 7) * 8 + (((j8 & 1) << 2) | (j8 & 2) | (j8 >> 2));
+                    if (own < c1 - c0) {
 #pragma unroll
-                    for (int i = 0; i < 2 * NO; ++i) {
-                        R tsum = wave_sum(v[i]);
-                        if (mine) ores[i] += tsum;
-                    }
-                }
-                    }
-                    if (lane < c1 - c0) {
-#pragma unroll
-                        for (int i = 0; i < 2 * NO; ++i) oacc[(c0 + lane) * 2 * NO + i] = ores[i];
+                        for (int i = 0; i < 2 * NO; ++i) oacc[(c0 + own) * 2 * NO + i] = ores[i];
                     }
                 }
             }
@@ -648,7 +705,8 @@ static hipError_t spread_m(const Xform *dxf, const SItem *items, int nitems, int
     if (per_cu < 1) per_cu = 1;
     int grid = std::min(cu_count() * per_cu, nitems);
     if (grid < 1) return hipSuccess;
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(t.threads), LL.total, s, dxf, items, nitems, queue, t.T, t.Zs,
+    int threads = std::min(t.threads, spread_max_threads(sizeof(R), M2));
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(threads), LL.total, s, dxf, items, nitems, queue, t.T, t.Zs,
                        LL.cap, (const v4u *)rec, (int)(rec_bytes / 16), cs);
     return hipGetLastError();
 }
