@@ -97,7 +97,7 @@ def copy_calibration(torch):
     a = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device="cuda").fill_(1.0)
     b = torch.empty_like(a)
     torch.cuda.synchronize()
-    b.copy_(a)
+    torch.mul(a, 1.0, out=b)  # an elementwise kernel: 1 GiB read, 1 GiB written
     torch.cuda.synchronize()
     del a, b
 
@@ -123,7 +123,8 @@ def summarize_counters(fetch_dir: str, write_dir: str, out_json: str, command: s
     write = load(write_dir, "WRITE_SIZE")
 
     def copy_kib(d):
-        cands = [(k, v) for k, v in d.items() if "copy" in k.lower() or "elementwise" in k.lower()]
+        # the calibration kernel: torch.mul(a, 1.0, out=b) over 1 GiB
+        cands = [(k, v) for k, v in d.items() if "MulFunctor" in k]
         return max(cands, key=lambda kv: kv[1]) if cands else (None, None)
 
     ck, cf = copy_kib(fetch)
@@ -229,18 +230,19 @@ def cpu_baseline(data, gpu):
     g = W.rng(99)
     x, f, fhat = data["x"], data["f"], data["fhat"]
     nall = N[0] * N[1] * N[2]
-    # calibrate: a few outputs, then size the sample to ~12 s (adjoint) + ~6 s (forward)
-    k8 = W.sample_indices(nall, 8, g)
+    # calibrate on enough outputs to occupy every host thread, then size the
+    # sample to ~12 s (adjoint) + ~6 s (forward)
+    kc = W.sample_indices(nall, 128, g)
     t0 = time.perf_counter()
-    oracle.ndft_adjoint(N, x, f, kidx=k8)
-    t_k = (time.perf_counter() - t0) / 8
-    nk = int(max(16, min(4096, 12.0 / max(t_k, 1e-6))))
+    oracle.ndft_adjoint(N, x, f, kidx=kc)
+    t_k = (time.perf_counter() - t0) / 128
+    nk = int(max(128, min(32768, 12.0 / max(t_k, 1e-7))))
     kidx = W.sample_indices(nall, nk, g)
-    j8 = W.sample_indices(M, 8, g)
+    jc = W.sample_indices(M, 512, g)
     t0 = time.perf_counter()
-    oracle.ndft_forward(N, x, fhat, jidx=j8)
-    t_j = (time.perf_counter() - t0) / 8
-    nj = int(max(16, min(8192, 6.0 / max(t_j, 1e-6))))
+    oracle.ndft_forward(N, x, fhat, jidx=jc)
+    t_j = (time.perf_counter() - t0) / 512
+    nj = int(max(512, min(262144, 6.0 / max(t_j, 1e-7))))
     jidx = W.sample_indices(M, nj, g)
 
     errs = {}
@@ -265,7 +267,7 @@ def cpu_baseline(data, gpu):
         errs[key] = {"adjoint": float("%.3e" % ea), "forward": float("%.3e" % ef)}
     t_adj_full = ta * nall / nk
     t_fwd_full = tf * M / nj
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    cores = oracle.threads()
     base = {"value": round(M / (t_adj_full + t_fwd_full), 1), "unit": "points/s", "cores": cores,
             "kind": "oracle",
             "sample": "FP64 direct NDFT: %d sampled frequencies of the adjoint (Eq. 5, %.1f s) and %d "

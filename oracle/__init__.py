@@ -62,6 +62,8 @@ def _load():
             lib.oracle_ewald_recip_forces.restype = ctypes.c_int
             lib.oracle_rel_l2.argtypes = [ctypes.c_int64, _f64p, _f64p]
             lib.oracle_rel_l2.restype = ctypes.c_double
+            lib.oracle_threads.argtypes = []
+            lib.oracle_threads.restype = ctypes.c_int
             _lib = lib
     return _lib
 
@@ -189,6 +191,11 @@ def ewald_recip_forces(r, q, L, alpha, kmax):
     _load().oracle_ewald_recip_forces(q.size, _p(r), _p(q), float(L), float(alpha), int(kmax),
                                       _p(S), _p(F))
     return F
+
+
+def threads() -> int:
+    """Host threads the oracle's parallel loops use."""
+    return int(_load().oracle_threads())
 
 
 def rel_l2(a, s) -> float:

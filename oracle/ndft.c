@@ -25,6 +25,7 @@
  * interleaved (re, im); points are M x d row-major.
  */
 #include <math.h>
+#include <omp.h>
 #include <stddef.h>
 #include <stdint.h>
 
@@ -347,4 +348,16 @@ double oracle_rel_l2(int64_t n, const double *a, const double *s)
         nsum_add(&den, s[i] * s[i]);
     }
     return sqrt(nsum_get(&num) / nsum_get(&den));
+}
+
+/* Threads the OpenMP loops above run on (reported beside timings). */
+int oracle_threads(void)
+{
+    int n = 1;
+#pragma omp parallel
+    {
+#pragma omp single
+        n = omp_get_num_threads();
+    }
+    return n;
 }
