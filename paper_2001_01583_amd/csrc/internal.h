@@ -124,17 +124,13 @@ enum Pass { P_ADJ0 = 0, P_ADJ1, P_ADJ2, P_FWD0, P_FWD1, P_FWD2, P_COUNT };
 template <typename R> struct Launch;
 
 hipError_t launch_zero(void *p, size_t bytes, hipStream_t s);
-hipError_t launch_bin_count(const double *x, const float *xf32, long long M, const Xform &X,
-                            int T, int m, int *counts, int *rank, int *err, hipStream_t s);
+hipError_t launch_bin_count(const double *x, const float *xf32, long long M, const Xform &X, int T, int *counts,
+                            int *rank, int *err, double *xs_out, hipStream_t s);
 hipError_t launch_scan(int *data, long long n, int *tmp, hipStream_t s);
-hipError_t launch_bin_scatter(const double *x, const float *xf32, long long M, const Xform &X,
-                              int T, int m, const int *cell_start, const int *rank,
-                              int *perm, unsigned char *rec, size_t rec_bytes, size_t off_pz,
-                              double *us, hipStream_t s);
-
 template <typename R>
-hipError_t launch_psi(const double *us, long long M, long long poff, const Xform &X, int m, double b,
-                      double inv_peak, unsigned char *rec, size_t rec_bytes, bool grad, hipStream_t s);
+hipError_t launch_bin_scatter(const double *x, const float *xf32, long long M, const Xform &X, int T, int m,
+                              double b, double inv_peak, const int *cell_start, const int *rank, int *perm,
+                              unsigned char *rec, size_t rec_bytes, bool grad, hipStream_t s);
 template <typename R>
 hipError_t launch_gather(const void *f, const int *perm, long long total, unsigned char *rec,
                          size_t rec_bytes, size_t off_f, hipStream_t s);

@@ -43,10 +43,14 @@ __device__ inline int sort_key(const int c[3], int T, int ntx, int n0)
     return line * n0 + c[0];
 }
 
+// Count pass: cell and sort key of every point, its rank among the points of
+// its cell (the counting sort's first half), the domain check, and the
+// float64 copy of the coordinates that later passes (and the tiling
+// autotuner) read.  xs_out may be null when x already is that copy.
 template <typename XT>
-__global__ void k_bin_count(const XT *__restrict__ x, long long M, int n0, int n1, int n2,
-                            int T, int ntx, int *__restrict__ counts, int *__restrict__ rank,
-                            int *__restrict__ err)
+__global__ void k_bin_count(const XT *__restrict__ x, long long M, int n0, int n1, int n2, int T, int ntx,
+                            int *__restrict__ counts, int *__restrict__ rank, int *__restrict__ err,
+                            double *__restrict__ xs_out)
 {
     long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= M) return;
@@ -55,69 +59,89 @@ __global__ void k_bin_count(const XT *__restrict__ x, long long M, int n0, int n
     int c[3];
     for (int t = 0; t < 3; ++t) {
         double u;
-        c[t] = cell_of((double)x[j * 3 + t], n[t], &u, &bad);
+        const double xv = (double)x[j * 3 + t];
+        if (xs_out) xs_out[j * 3 + t] = xv;
+        c[t] = cell_of(xv, n[t], &u, &bad);
     }
     if (bad) atomicOr(err, 1);
     rank[j] = atomicAdd(&counts[sort_key(c, T, ntx, n0)], 1);
 }
 
-template <typename XT>
-__global__ void k_bin_scatter(const XT *__restrict__ x, long long M, long long poff, int n0, int n1,
-                              int n2, int T, int ntx, const int *__restrict__ cell_start,
-                              const int *__restrict__ rank, int *__restrict__ perm,
-                              unsigned char *__restrict__ rec, size_t rec_bytes, size_t off_pz,
-                              double *__restrict__ us)
+// Scatter of the points into sorted order, with the window values of each
+// point tabulated into its record on the way (one thread per point).  Tap t
+// (0..2m-1) of a point in cell c with offset u sits on grid cell c - m + 1 + t,
+// at grid-unit distance u + m - 1 - t.  Along dim 0 the taps are stored
+// rotated: slot s holds tap (s - (c0 - m + 1)) mod 2m, so that a register
+// window indexed by plane mod 2m needs no per-point shuffling.  Values are
+// evaluated in float64 and rounded once for the float32 path.
+typedef unsigned int v4u_bin __attribute__((ext_vector_type(4)));
+typedef unsigned int v2u_bin __attribute__((ext_vector_type(2)));
+
+// Store NB bytes from registers to a 16-byte aligned address with 16-byte
+// stores (and one 8-byte store for a remainder).
+template <int NB, typename T>
+__device__ inline void store_block(unsigned char *dst, const T *src)
 {
-    long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const unsigned char *b = reinterpret_cast<const unsigned char *>(src);
+#pragma unroll
+    for (int i = 0; i < NB / 16; ++i) {
+        v4u_bin v;
+        __builtin_memcpy(&v, b + 16 * i, 16);
+        reinterpret_cast<v4u_bin *>(dst)[i] = v;
+    }
+    if constexpr (NB % 16 != 0) {
+        v2u_bin v;
+        __builtin_memcpy(&v, b + 16 * (NB / 16), 8);
+        *reinterpret_cast<v2u_bin *>(dst + 16 * (NB / 16)) = v;
+    }
+}
+
+template <typename R, int M2, bool GRAD>
+__global__ __launch_bounds__(256) void k_bin_scatter(const double *__restrict__ xd, const float *__restrict__ xf,
+                                                     long long M, long long poff, int n0, int n1, int n2, int T,
+                                                     int ntx, const int *__restrict__ cell_start,
+                                                     const int *__restrict__ rank, int *__restrict__ perm,
+                                                     unsigned char *__restrict__ rec, size_t rec_bytes, double b,
+                                                     double inv_peak)
+{
+    constexpr int m = M2 / 2;
+    constexpr int NW = 3 * M2;
+    static_assert((NW * sizeof(R)) % 8 == 0, "window block is a whole number of 8-byte units");
+    const long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= M) return;
     const int n[3] = {n0, n1, n2};
     bool bad = false;
     int c[3];
     double u[3];
-    for (int t = 0; t < 3; ++t) c[t] = cell_of((double)x[j * 3 + t], n[t], &u[t], &bad);
-    long long pos = poff + cell_start[sort_key(c, T, ntx, n0)] + rank[j];
-    perm[pos] = (int)(poff + j);
-    *reinterpret_cast<int *>(rec + pos * rec_bytes + off_pz) = c[0];
-    us[pos * 3 + 0] = u[0];
-    us[pos * 3 + 1] = u[1];
-    us[pos * 3 + 2] = u[2];
-}
-
-// Window values of the sorted points, one thread per (point, dimension, tap),
-// written into the point records (consecutive threads write consecutive
-// words).  Tap t (0..2m-1) of a point in cell c with offset u sits on grid
-// cell c - m + 1 + t, at grid-unit distance u + m - 1 - t.  Along dim 0 the
-// taps are stored rotated: slot s = (c0 - m + 1 + t) mod 2m, so that a
-// register window indexed by plane mod 2m needs no per-point shuffling.
-template <typename R>
-__global__ void k_psi(const double *__restrict__ us, long long M, long long poff, int m, double b,
-                      double inv_peak, int n0, int n1, int n2, unsigned char *__restrict__ rec,
-                      size_t rec_bytes, int grad)
-{
-    const int M2 = 2 * m;
-    long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= M * 3 * M2) return;
-    long long p = poff + g / (3 * M2);
-    int rem = (int)(g % (3 * M2));
-    int dim = rem / M2, t = rem - dim * M2;
-    unsigned char *rp = rec + p * rec_bytes;
-    double u = us[p * 3 + dim];
-    int s = t;
-    if (dim == 0) {
-        int c0 = *reinterpret_cast<const int *>(rp + rec_off_pz(M2, sizeof(R)));
-        int r = (c0 - m + 1) % M2;
-        s = t + (r < 0 ? r + M2 : r);
-        if (s >= M2) s -= M2;
+    for (int t = 0; t < 3; ++t) {
+        const double xv = xd ? xd[j * 3 + t] : (double)xf[j * 3 + t];
+        c[t] = cell_of(xv, n[t], &u[t], &bad);
     }
-    double nd = dim == 0 ? n0 : (dim == 1 ? n1 : n2);
-    double dist = u + (double)(m - 1 - t);
-    // evaluated in float64 for both paths (the float path stores the values
-    // rounded once)
-    R *dst = reinterpret_cast<R *>(rp) + dim * M2 + s;
-    *dst = (R)kb_phi(dist, m, b, inv_peak);
-    if (grad)
-        *(reinterpret_cast<R *>(rp + rec_prefix(M2, sizeof(R))) + dim * M2 + s) =
-            (R)(nd * kb_dphi(dist, m, b, inv_peak));
+    const long long pos = poff + cell_start[sort_key(c, T, ntx, n0)] + rank[j];
+    perm[pos] = (int)(poff + j);
+    unsigned char *rp = rec + pos * rec_bytes;
+
+    int rot = (c[0] - m + 1) % M2;
+    if (rot < 0) rot += M2;
+    R w[NW];
+    R dw[GRAD ? NW : 1];
+#pragma unroll
+    for (int dim = 0; dim < 3; ++dim) {
+#pragma unroll
+        for (int sl = 0; sl < M2; ++sl) {
+            int t = sl;
+            if (dim == 0) {
+                t = sl - rot;
+                if (t < 0) t += M2;
+            }
+            const double dist = u[dim] + (double)(m - 1 - t);
+            w[dim * M2 + sl] = (R)kb_phi(dist, m, b, inv_peak);
+            if constexpr (GRAD) dw[dim * M2 + sl] = (R)((double)n[dim] * kb_dphi(dist, m, b, inv_peak));
+        }
+    }
+    store_block<NW * sizeof(R)>(rp, w);
+    *reinterpret_cast<int *>(rp + rec_off_pz(M2, sizeof(R))) = c[0];
+    if constexpr (GRAD) store_block<NW * sizeof(R)>(rp + rec_prefix(M2, sizeof(R)), dw);
 }
 
 // ---------------------------------------------------------------------------
@@ -190,48 +214,59 @@ hipError_t launch_scan(int *data, long long n, int *tmp, hipStream_t s)
 }
 
 // ---------------------------------------------------------------------------
-hipError_t launch_bin_count(const double *x, const float *xf32, long long M, const Xform &X, int T,
-                            int m, int *counts, int *rank, int *err, hipStream_t s)
+hipError_t launch_bin_count(const double *x, const float *xf32, long long M, const Xform &X, int T, int *counts,
+                            int *rank, int *err, double *xs_out, hipStream_t s)
 {
-    (void)m;
-    unsigned nb = (unsigned)((M + 255) / 256);
+    if (M <= 0) return hipSuccess;
+    const unsigned nb = (unsigned)((M + 255) / 256);
     if (x)
-        hipLaunchKernelGGL(k_bin_count<double>, dim3(nb), dim3(256), 0, s, x, M, X.n[0], X.n[1],
-                           X.n[2], T, X.ntx, counts, rank, err);
+        hipLaunchKernelGGL(k_bin_count<double>, dim3(nb), dim3(256), 0, s, x, M, X.n[0], X.n[1], X.n[2], T,
+                           X.ntx, counts, rank, err, xs_out);
     else
-        hipLaunchKernelGGL(k_bin_count<float>, dim3(nb), dim3(256), 0, s, xf32, M, X.n[0], X.n[1],
-                           X.n[2], T, X.ntx, counts, rank, err);
+        hipLaunchKernelGGL(k_bin_count<float>, dim3(nb), dim3(256), 0, s, xf32, M, X.n[0], X.n[1], X.n[2], T,
+                           X.ntx, counts, rank, err, xs_out);
     return hipGetLastError();
 }
 
-hipError_t launch_bin_scatter(const double *x, const float *xf32, long long M, const Xform &X, int T,
-                              int m, const int *cell_start, const int *rank, int *perm, unsigned char *rec,
-                              size_t rec_bytes, size_t off_pz, double *us, hipStream_t s)
+template <typename R, int M2>
+static void scatter_m(const double *x, const float *xf32, long long M, const Xform &X, int T,
+                      const int *cell_start, const int *rank, int *perm, unsigned char *rec, size_t rec_bytes,
+                      double b, double inv_peak, bool grad, hipStream_t s)
 {
-    (void)m;
-    unsigned nb = (unsigned)((M + 255) / 256);
-    if (x)
-        hipLaunchKernelGGL(k_bin_scatter<double>, dim3(nb), dim3(256), 0, s, x, M, X.poff, X.n[0],
-                           X.n[1], X.n[2], T, X.ntx, cell_start, rank, perm, rec, rec_bytes, off_pz, us);
-    else
-        hipLaunchKernelGGL(k_bin_scatter<float>, dim3(nb), dim3(256), 0, s, xf32, M, X.poff, X.n[0],
-                           X.n[1], X.n[2], T, X.ntx, cell_start, rank, perm, rec, rec_bytes, off_pz, us);
-    return hipGetLastError();
+    const unsigned nb = (unsigned)((M + 255) / 256);
+    auto k = grad ? k_bin_scatter<R, M2, true> : k_bin_scatter<R, M2, false>;
+    hipLaunchKernelGGL(k, dim3(nb), dim3(256), 0, s, x, xf32, M, X.poff, X.n[0], X.n[1], X.n[2], T, X.ntx,
+                       cell_start, rank, perm, rec, rec_bytes, b, inv_peak);
 }
 
 template <typename R>
-hipError_t launch_psi(const double *us, long long M, long long poff, const Xform &X, int m, double b,
-                      double inv_peak, unsigned char *rec, size_t rec_bytes, bool grad, hipStream_t s)
+hipError_t launch_bin_scatter(const double *x, const float *xf32, long long M, const Xform &X, int T, int m,
+                              double b, double inv_peak, const int *cell_start, const int *rank, int *perm,
+                              unsigned char *rec, size_t rec_bytes, bool grad, hipStream_t s)
 {
-    unsigned nb = (unsigned)((M * 3 * 2 * m + 255) / 256);
-    hipLaunchKernelGGL(k_psi<R>, dim3(nb), dim3(256), 0, s, us, M, poff, m, b, inv_peak, X.n[0], X.n[1],
-                       X.n[2], rec, rec_bytes, grad ? 1 : 0);
+    if (M <= 0) return hipSuccess;
+    switch (m) {
+#define HPNFFT_SCATTER_CASE(MM) \
+    case MM: scatter_m<R, 2 * MM>(x, xf32, M, X, T, cell_start, rank, perm, rec, rec_bytes, b, inv_peak, grad, s); break;
+        HPNFFT_SCATTER_CASE(1)
+        HPNFFT_SCATTER_CASE(2)
+        HPNFFT_SCATTER_CASE(3)
+        HPNFFT_SCATTER_CASE(4)
+        HPNFFT_SCATTER_CASE(5)
+        HPNFFT_SCATTER_CASE(6)
+        HPNFFT_SCATTER_CASE(7)
+        HPNFFT_SCATTER_CASE(8)
+#undef HPNFFT_SCATTER_CASE
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
-template hipError_t launch_psi<double>(const double *, long long, long long, const Xform &, int, double,
-                                       double, unsigned char *, size_t, bool, hipStream_t);
-template hipError_t launch_psi<float>(const double *, long long, long long, const Xform &, int, double,
-                                      double, unsigned char *, size_t, bool, hipStream_t);
+template hipError_t launch_bin_scatter<double>(const double *, const float *, long long, const Xform &, int, int,
+                                               double, double, const int *, const int *, int *, unsigned char *,
+                                               size_t, bool, hipStream_t);
+template hipError_t launch_bin_scatter<float>(const double *, const float *, long long, const Xform &, int, int,
+                                              double, double, const int *, const int *, int *, unsigned char *,
+                                              size_t, bool, hipStream_t);
 
 }  // namespace hpnfft

@@ -28,27 +28,31 @@ __device__ inline int line_cost(const int *cs_line, int n0, int z0, int zs, int 
     return c;
 }
 
-// One thread per (tile, slab, line); tcost must be zeroed beforehand.
-__global__ void k_tile_cost(const int *__restrict__ cell_start, int n0, int T, int Zs, int m,
-                            int ntiles, int nslab, int *__restrict__ tcost,
-                            unsigned long long *__restrict__ total)
+// One workgroup per (tile, slab): its threads sum the line costs, the total
+// is stored in tcost (no zeroing needed) and added to the grand total.
+__global__ __launch_bounds__(256) void k_tile_cost(const int *__restrict__ cell_start, int n0, int T, int Zs,
+                                                   int m, int nslab, int *__restrict__ tcost,
+                                                   unsigned long long *__restrict__ total)
 {
-    __shared__ unsigned long long blk;
+    __shared__ int blk;
     if (threadIdx.x == 0) blk = 0;
     __syncthreads();
-    long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    long long n = (long long)ntiles * nslab * T * T;
-    if (g < n) {
-        int li = (int)(g % (T * T));
-        long long ts = g / (T * T);
-        int slab = (int)(ts % nslab), tile = (int)(ts / nslab);
-        int z0 = slab * Zs, zs = min(Zs, n0 - z0);
-        int c = line_cost(cell_start + ((long long)tile * T * T + li) * n0, n0, z0, zs, m);
-        atomicAdd(&tcost[ts], c);
-        atomicAdd(&blk, (unsigned long long)c);
-    }
+    const int ts = blockIdx.x;
+    const int slab = ts % nslab, tile = ts / nslab;
+    const int z0 = slab * Zs, zs = min(Zs, n0 - z0);
+    const int nl = T * T;
+    int c = 0;
+    for (int li = threadIdx.x; li < nl; li += blockDim.x)
+        c += line_cost(cell_start + ((long long)tile * nl + li) * n0, n0, z0, zs, m);
+    // wavefront sum, then one LDS add per wavefront
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+    if ((threadIdx.x & 63) == 0) atomicAdd(&blk, c);
     __syncthreads();
-    if (threadIdx.x == 0) atomicAdd(total, blk);
+    if (threadIdx.x == 0) {
+        tcost[ts] = blk;
+        atomicAdd(total, (unsigned long long)blk);
+    }
 }
 
 // One wavefront per (tile, slab): the T*T line costs are prefix-summed across
@@ -120,9 +124,10 @@ __global__ void k_make_items(const int *__restrict__ cell_start, int xf, int n0,
 hipError_t launch_tile_cost(const int *cell_start, const Xform &X, int T, int Zs, int m, int *tcost,
                             unsigned long long *total, hipStream_t s)
 {
-    long long n = (long long)X.ntx * X.nty * X.nslab * T * T;
-    hipLaunchKernelGGL(k_tile_cost, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, cell_start, X.n[0], T,
-                       Zs, m, X.ntx * X.nty, X.nslab, tcost, total);
+    const long long nts = (long long)X.ntx * X.nty * X.nslab;
+    if (nts <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_tile_cost, dim3((unsigned)nts), dim3(256), 0, s, cell_start, X.n[0], T, Zs, m, X.nslab,
+                       tcost, total);
     return hipGetLastError();
 }
 

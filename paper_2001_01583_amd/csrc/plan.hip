@@ -54,7 +54,7 @@ int fft_count(int n)
 }
 
 struct Layout {
-    size_t counters, setp, grids, tmpA, tmpB, cell_start, scan_tmp, rank, perm, us, xs, rec, outs, tcost,
+    size_t counters, setp, grids, tmpA, tmpB, cell_start, scan_tmp, rank, perm, xs, rec, outs, tcost,
         items, fit[3], ewald, roll, tw, xf, total;
     size_t rec_bytes = 0;
     std::vector<size_t> grid_off, tmpA_off, tmpB_off, key_off, tcost_off, roll_off;
@@ -196,7 +196,6 @@ void build_layout(hpnfft_plan_s *p)
     L.scan_tmp = take((size_t)(nb + nb / 2048 + 64) * 4);
     L.rank = take((size_t)maxM * 4);
     L.perm = take((size_t)p->Mtot * 4);
-    L.us = take((size_t)p->Mtot * 24);
     L.xs = take((size_t)p->Mtot * 24);
     L.rec_bytes = rec_size(p->M2(), p->rbytes(), p->grad());
     L.rec = take((size_t)p->Mtot * L.rec_bytes);
@@ -361,33 +360,34 @@ void drop_records(hpnfft_plan_s *p)
 
 // Bin, sort and tabulate the stored points (p->ws + L.xs); then build the
 // spread / interpolation work list.  Synchronises once.
-int bin_points(hpnfft_plan_s *p)
+// x / x32: the caller's points (their float64 copy is written to p->ws +
+// L.xs on the way), or both null to re-bin the stored copy.
+int bin_points(hpnfft_plan_s *p, const double *x = nullptr, const float *x32 = nullptr)
 {
     const Layout &L = p->L;
     hipStream_t s = p->stream;
     int *setp = p->at<int>(L.setp);  // [0] err, [1] nitems, [2] overflow, [4..5] total (u64)
     HCHECK(launch_zero(setp, 256, s));
-    const double *xs = p->at<double>(L.xs);
+    double *xs = p->at<double>(L.xs);
+    const bool stored = !x && !x32;
     unsigned long long *total = reinterpret_cast<unsigned long long *>(setp + 4);
     for (int b = 0; b < p->B; ++b) {
         const Xform &X = p->hx[b];
         int *cs = p->at<int>(L.key_off[b]);
         HCHECK(launch_zero(cs, (size_t)p->keys[b] * 4, s));
-        const double *xb = xs + X.poff * 3;
-        HCHECK(launch_bin_count(xb, nullptr, X.M, X, p->til.T, p->m, cs, p->at<int>(L.rank), setp, s));
+        double *xb = xs + X.poff * 3;
+        HCHECK(launch_bin_count(stored ? xb : (x ? x + X.poff * 3 : nullptr), x32 ? x32 + X.poff * 3 : nullptr,
+                                X.M, X, p->til.T, cs, p->at<int>(L.rank), setp, stored ? nullptr : xb, s));
         HCHECK(launch_scan(cs, p->keys[b], p->at<int>(L.scan_tmp), s));
-        HCHECK(launch_bin_scatter(xb, nullptr, X.M, X, p->til.T, p->m, cs, p->at<int>(L.rank),
-                                  p->at<int>(L.perm), p->at<unsigned char>(L.rec), L.rec_bytes,
-                                  rec_off_pz(p->M2(), p->rbytes()), p->at<double>(L.us), s));
         if (p->prec == HPNFFT_F32)
-            HCHECK(launch_psi<float>(p->at<double>(L.us), X.M, X.poff, X, p->m, p->b, p->inv_peak,
-                                     p->at<unsigned char>(L.rec), L.rec_bytes, p->grad(), s));
+            HCHECK(launch_bin_scatter<float>(xb, nullptr, X.M, X, p->til.T, p->m, p->b, p->inv_peak, cs,
+                                             p->at<int>(L.rank), p->at<int>(L.perm), p->at<unsigned char>(L.rec),
+                                             L.rec_bytes, p->grad(), s));
         else
-            HCHECK(launch_psi<double>(p->at<double>(L.us), X.M, X.poff, X, p->m, p->b, p->inv_peak,
-                                      p->at<unsigned char>(L.rec), L.rec_bytes, p->grad(), s));
-        int *tc = p->at<int>(L.tcost_off[b]);
-        HCHECK(launch_zero(tc, (size_t)X.ntx * X.nty * X.nslab * 4, s));
-        HCHECK(launch_tile_cost(cs, X, p->til.T, p->til.Zs, p->m, tc, total, s));
+            HCHECK(launch_bin_scatter<double>(xb, nullptr, X.M, X, p->til.T, p->m, p->b, p->inv_peak, cs,
+                                              p->at<int>(L.rank), p->at<int>(L.perm),
+                                              p->at<unsigned char>(L.rec), L.rec_bytes, p->grad(), s));
+        HCHECK(launch_tile_cost(cs, X, p->til.T, p->til.Zs, p->m, p->at<int>(L.tcost_off[b]), total, s));
     }
     const int cap_div = p->cus * 4;
     for (int b = 0; b < p->B; ++b) {
@@ -657,23 +657,10 @@ static int set_points_any(hpnfft_plan p, const double *x, const float *x32)
     if (!p || (!x && !x32)) return HPNFFT_EINVAL;
     if (!p->have_ws) return HPNFFT_ESTATE;
     p->have_points = false;
-    // keep a float64 copy of the points (used again by the autotuner)
-    double *xs = p->at<double>(p->L.xs);
-    if (x) {
-        HCHECK(hipMemcpyAsync(xs, x, (size_t)p->Mtot * 24, hipMemcpyDeviceToDevice, p->stream));
-    } else {
-        // promote float32 coordinates exactly: stage through the us buffer
-        std::vector<float> h((size_t)p->Mtot * 3);
-        HCHECK(hipMemcpyAsync(h.data(), x32, h.size() * 4, hipMemcpyDeviceToHost, p->stream));
-        HCHECK(hipStreamSynchronize(p->stream));
-        std::vector<double> hd(h.begin(), h.end());
-        HCHECK(hipMemcpyAsync(xs, hd.data(), hd.size() * 8, hipMemcpyHostToDevice, p->stream));
-        HCHECK(hipStreamSynchronize(p->stream));
-    }
     int rc;
     {
         PhaseTimer t(p, HPNFFT_PH_SET_POINTS);
-        rc = bin_points(p);
+        rc = bin_points(p, x, x32);
     }
     p->have_points = rc == HPNFFT_OK;
     return rc;
@@ -827,7 +814,7 @@ int hpnfft_autotune(hpnfft_plan p, void *scratch_f, void *scratch_fhat, int *til
         if (rc) return rc;
         HCHECK(hipMemcpyAsync(p->at<double>(p->L.xs), hx.data(), hx.size() * 8, hipMemcpyHostToDevice,
                               p->stream));
-        rc = bin_points(p);
+        rc = bin_points(p, nullptr, nullptr);
         p->have_points = rc == HPNFFT_OK;
         return rc;
     };

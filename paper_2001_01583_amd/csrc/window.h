@@ -24,48 +24,67 @@ HPNFFT_HD double kb_shape(double sigma) { return M_PI * (2.0 - 1.0 / sigma); }
 // Phi(0) for the normalisation.
 HPNFFT_HD double kb_peak(int m, double b) { return sinh(b * m) / (M_PI * m); }
 
-// Normalised window value at grid-unit distance t.
-HPNFFT_HD double kb_phi(double t, int m, double b, double inv_peak)
+// sinh(x)/x and (x cosh x - sinh x)/x^3 for x >= 0: power series below
+// x = 0.5 (ten terms, truncation below 1e-21 relative), else one exp.
+HPNFFT_HD double sinhc(double x)
 {
-    double r2 = (double)m * m - t * t;
-    if (r2 < 0.0) {
-        // |t| can exceed m only by rounding at the truncation edge.
-        if (r2 < -1e-12 * m * m) return 0.0;
-        r2 = 0.0;
+    if (x < 0.5) {
+        const double z2 = x * x;
+        double term = 1.0, acc = 1.0;
+        for (int k = 1; k <= 9; ++k) {
+            term *= z2 / ((2.0 * k) * (2.0 * k + 1.0));
+            acc += term;
+        }
+        return acc;
     }
-    double r = sqrt(r2);
-    double br = b * r;
-    double v = (br < 1e-8) ? b * (1.0 + br * br / 6.0) : sinh(br) / r;
-    return v * (1.0 / M_PI) * inv_peak;
+    const double e = exp(x);
+    return 0.5 * (e - 1.0 / e) / x;
 }
-
-// Normalised derivative dPhi/dt:
-//   dPhi/dt = -t (b r cosh(b r) - sinh(b r)) / (pi r^3),
-// with the series b^3/3 + b^5 r^2/30 + ... of (b r cosh - sinh)/r^3 near r = 0.
-HPNFFT_HD double kb_dphi(double t, int m, double b, double inv_peak)
+HPNFFT_HD double sinhc_d(double x)
 {
-    double r2 = (double)m * m - t * t;
-    if (r2 < 0.0) {
-        if (r2 < -1e-12 * m * m) return 0.0;
-        r2 = 0.0;
-    }
-    double r = sqrt(r2);
-    double br = b * r;
-    double q;  // (b r cosh(b r) - sinh(b r)) / r^3
-    if (br < 0.5) {
-        // sum_{k>=1} b^3 (br)^{2k-2} * 2k / (2k+1)!
-        double z2 = br * br, term = 1.0, acc = 0.0;
-        double fact = 6.0;  // (2k+1)! for k = 1
+    if (x < 0.5) {
+        // sum_{k>=1} x^(2k-2) * 2k / (2k+1)!
+        const double z2 = x * x;
+        double term = 1.0, acc = 0.0, fact = 6.0;
         for (int k = 1; k <= 10; ++k) {
             acc += term * (2.0 * k) / fact;
             term *= z2;
             fact *= (2.0 * k + 2.0) * (2.0 * k + 3.0);
         }
-        q = b * b * b * acc;
-    } else {
-        q = (br * cosh(br) - sinh(br)) / (r2 * r);
+        return acc;
     }
-    return -t * q * (1.0 / M_PI) * inv_peak;
+    const double e = exp(x), ei = 1.0 / e;
+    return (0.5 * x * (e + ei) - 0.5 * (e - ei)) / (x * x * x);
+}
+
+// r = sqrt(m^2 - t^2), or -1 where |t| > m beyond rounding.
+HPNFFT_HD double kb_radius(double t, int m)
+{
+    double r2 = (double)m * m - t * t;
+    if (r2 < 0.0) {
+        // |t| can exceed m only by rounding at the truncation edge.
+        if (r2 < -1e-12 * m * m) return -1.0;
+        r2 = 0.0;
+    }
+    return sqrt(r2);
+}
+
+// Normalised window value at grid-unit distance t:
+// sinh(b r)/(pi r) = b sinhc(b r)/pi.
+HPNFFT_HD double kb_phi(double t, int m, double b, double inv_peak)
+{
+    const double r = kb_radius(t, m);
+    if (r < 0.0) return 0.0;
+    return b * sinhc(b * r) * (1.0 / M_PI) * inv_peak;
+}
+
+// Normalised derivative dPhi/dt:
+//   dPhi/dt = -t (b r cosh(b r) - sinh(b r)) / (pi r^3) = -t b^3 sinhc_d(b r) / pi.
+HPNFFT_HD double kb_dphi(double t, int m, double b, double inv_peak)
+{
+    const double r = kb_radius(t, m);
+    if (r < 0.0) return 0.0;
+    return -t * b * b * b * sinhc_d(b * r) * (1.0 / M_PI) * inv_peak;
 }
 
 // Modified Bessel function I0 by its all-positive power series
