@@ -68,6 +68,16 @@ __host__ __device__ constexpr size_t rec_off_pz(int M2, size_t R) { return 3 * M
 //   [tile][stage: cap records][slot maps: 2 x cap ints][run_p0: 3T^2][run_soff: 3T^2+1]
 //   [scan scratch: 32 ints][interpolation outputs: cap x 2 NO reals]
 constexpr size_t kLdsLimit = 160 * 1024 - 512;
+
+// Row pitch (cells) of the spread's LDS tile.  The tile stores real and
+// imaginary parts as separate arrays of 8-byte cells (a float32 (sum,
+// compensation) pair, or a float64), so the lanes of one tap row touch
+// consecutive cells; for 2m <= 8 the pitch is padded to 8 (mod 16) cells so
+// that consecutive rows fall on disjoint LDS banks.
+__host__ __device__ constexpr int spread_pitch(int T, int M2)
+{
+    return M2 <= 8 ? ((T + M2 - 1 + 7) / 16) * 16 + 8 : T + M2 - 1;
+}
 struct LdsLayout {
     size_t tile, stage, slot_p, run_p0, run_soff, sh, out, total;
     int cap;
@@ -80,7 +90,8 @@ __host__ __device__ inline LdsLayout lds_layout(int T, int Zs, int M2, size_t R,
     size_t nr = (size_t)3 * T * T;
     int NO = kind == 2 ? 4 : 1;
     L.tile = 0;
-    L.stage = align16((size_t)Zs * P * P * 2 * R * ((kind == 0 && comp) ? 2 : 1));
+    L.stage = kind == 0 ? align16((size_t)Zs * P * spread_pitch(T, M2) * 16)
+                        : align16((size_t)Zs * P * P * 2 * R);
     L.slot_p = L.stage + (size_t)cap * st;
     L.run_p0 = L.slot_p + (size_t)cap * 8;
     L.run_soff = L.run_p0 + nr * 4;
@@ -109,11 +120,11 @@ inline LdsLayout lds_fit(int T, int Zs, int M2, size_t R, int kind, bool comp)
 // the 128 registers a 1024-thread workgroup leaves per lane.
 __host__ __device__ constexpr int spread_max_threads(int real_bytes, int M2)
 {
-    return real_bytes == 8 && M2 >= 12 ? 512 : 1024;
+    return 1024;
 }
 __host__ __device__ constexpr int interp_max_threads(int real_bytes, int M2, bool grad)
 {
-    return (real_bytes == 8 && (M2 >= 6 || grad)) || M2 >= 12 ? 512 : 1024;
+    return grad && (real_bytes == 8 || M2 >= 12) ? 512 : 1024;
 }
 
 // FFT pass identifiers.

@@ -54,7 +54,8 @@ __device__ inline void seg_range(int U, int z0, int zs, int m, int n0, int *a, i
 }
 
 // Compensated float adds into two LDS cells (the real and imaginary part of
-// one grid value), each holding (sum, compensation) as one 64-bit word:
+// one grid value, kept in separate arrays), each holding (sum,
+// compensation) as one 64-bit word:
 // TwoSum (Knuth) of the stored sum and v gives the new sum and its exact
 // rounding error, which joins the compensation; each pair is published with
 // a 64-bit compare-and-swap.  Both parts are in flight together.  The
@@ -70,18 +71,19 @@ __device__ __forceinline__ unsigned long long twosum_pair(unsigned long long old
     return (unsigned long long)__float_as_uint(t) | ((unsigned long long)__float_as_uint(cp + e) << 32);
 }
 
-__device__ __forceinline__ void lds_add_comp2(unsigned long long *cell, float vr, float vi)
+__device__ __forceinline__ void lds_add_comp2(unsigned long long *cre, unsigned long long *cim, float vr,
+                                              float vi)
 {
-    unsigned long long o0 = cell[0], o1 = cell[1];
+    unsigned long long o0 = *cre, o1 = *cim;
     bool d0 = false, d1 = false;
     do {
         if (!d0) {
-            const unsigned long long pr = atomicCAS(cell, o0, twosum_pair(o0, vr));
+            const unsigned long long pr = atomicCAS(cre, o0, twosum_pair(o0, vr));
             d0 = pr == o0;
             o0 = pr;
         }
         if (!d1) {
-            const unsigned long long pr = atomicCAS(cell + 1, o1, twosum_pair(o1, vi));
+            const unsigned long long pr = atomicCAS(cim, o1, twosum_pair(o1, vi));
             d1 = pr == o1;
             o1 = pr;
         }
@@ -290,7 +292,10 @@ __global__ __launch_bounds__(spread_max_threads(sizeof(R), M2)) void k_spread(co
     __shared__ int s_item;
     const LdsLayout LL = lds_layout(T, Zs, M2, sizeof(R), 0, COMP, cap);
     const int P = T + M2 - 1;
-    const int plane = P * P;
+    // tile: real parts [Zs][P][pitch] of 8-byte cells, then imaginary parts
+    const int pitch = spread_pitch(T, M2);
+    const int plane = P * pitch;
+    const size_t im_off = (size_t)Zs * plane;
     R *acc = reinterpret_cast<R *>(smem + LL.tile);
     unsigned long long *pairs = reinterpret_cast<unsigned long long *>(smem + LL.tile);
     v4u *stage = reinterpret_cast<v4u *>(smem + LL.stage);
@@ -308,13 +313,13 @@ __global__ __launch_bounds__(spread_max_threads(sizeof(R), M2)) void k_spread(co
         const int nz = g.zs * g.nrows * P;
         for (int i = tid; i < nz; i += nthr) {
             int z = i / (g.nrows * P), rem = i - z * g.nrows * P;
-            size_t o = ((size_t)z * plane + (size_t)(g.ry0 + rem / P) * P + rem % P) * 2;
+            const size_t o = (size_t)z * plane + (size_t)(g.ry0 + rem / P) * pitch + rem % P;
             if (COMP) {
                 pairs[o] = 0ull;
-                pairs[o + 1] = 0ull;
+                pairs[o + im_off] = 0ull;
             } else {
                 acc[o] = R(0);
-                acc[o + 1] = R(0);
+                acc[o + im_off] = R(0);
             }
         }
         const int nr = 3 * (g.le - g.lb);
@@ -356,7 +361,7 @@ __global__ __launch_bounds__(spread_max_threads(sizeof(R), M2)) void k_spread(co
                 const int row = rg * 64 + lane;
                 const bool active = ROWS % 64 == 0 || row < ROWS;
                 const int dy = active ? row / M2 : 0, dx = active ? row % M2 : 0;
-                const size_t lrow = (size_t)(ly + dy) * P + (lx + dx);
+                const size_t lrow = (size_t)(ly + dy) * pitch + (lx + dx);
                 const int qshift = U - g.z0 - M2;  // slab-relative plane = q + qshift
 
                 R wr[M2], wi[M2];
@@ -366,12 +371,12 @@ __global__ __launch_bounds__(spread_max_threads(sizeof(R), M2)) void k_spread(co
                 // add slot s (plane q) into the LDS tile
                 auto flush = [&](int s, int q) __attribute__((always_inline)) {
                     if (active) {
-                        const size_t o = ((size_t)(q + qshift) * plane + lrow) * 2;
+                        const size_t o = (size_t)(q + qshift) * plane + lrow;
                         if (COMP) {
-                            lds_add_comp2(&pairs[o], (float)wr[s], (float)wi[s]);
+                            lds_add_comp2(&pairs[o], &pairs[o + im_off], (float)wr[s], (float)wi[s]);
                         } else {
                             atomicAdd(&acc[o], wr[s]);
-                            atomicAdd(&acc[o + 1], wi[s]);
+                            atomicAdd(&acc[o + im_off], wi[s]);
                         }
                     }
                 };
@@ -427,15 +432,15 @@ __global__ __launch_bounds__(spread_max_threads(sizeof(R), M2)) void k_spread(co
         for (int i = tid; i < nz; i += nthr) {
             int z = i / (g.nrows * P), rem = i - z * g.nrows * P;
             int y = g.ry0 + rem / P, xx = rem % P;
-            size_t o = ((size_t)z * plane + (size_t)y * P + xx) * 2;
+            const size_t o = (size_t)z * plane + (size_t)y * pitch + xx;
             R vr, vi;
             if (COMP) {
-                unsigned long long a0 = pairs[o], a1 = pairs[o + 1];
+                unsigned long long a0 = pairs[o], a1 = pairs[o + im_off];
                 vr = (R)(__uint_as_float((unsigned int)a0) + __uint_as_float((unsigned int)(a0 >> 32)));
                 vi = (R)(__uint_as_float((unsigned int)a1) + __uint_as_float((unsigned int)(a1 >> 32)));
             } else {
                 vr = acc[o];
-                vi = acc[o + 1];
+                vi = acc[o + im_off];
             }
             int gy = wrapn(g.Y0 + y - m + 1, g.n1), gx = wrapn(g.X0 + xx - m + 1, g.n2);
             size_t gi = (((size_t)(g.z0 + z) * g.n1 + gy) * g.n2 + gx) * 2;
