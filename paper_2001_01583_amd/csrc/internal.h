@@ -51,17 +51,27 @@ struct Tiling {
 
 __host__ __device__ constexpr size_t align16(size_t v) { return (v + 15) & ~(size_t)15; }
 
-// Record of one sorted point (16-byte aligned, contiguous per z-line run):
+// Record of one sorted point (16-byte aligned, contiguous per run):
 //   [psi: 3 x 2m window values (dim 0 rotated, dims 1, 2 natural)]
-//   [f: the point's value, complex]  [plane index c0 (int)]  [pad]
+//   [f: the point's value, complex]  [plane index c0 (int)]
+//   [line offset in its block of lines (int)]  [pad]
 //   [dpsi: 3 x 2m window derivatives, gradient plans only]
-__host__ __device__ constexpr size_t rec_prefix(int M2, size_t R) { return align16(3 * M2 * R + 2 * R + 4); }
+__host__ __device__ constexpr size_t rec_prefix(int M2, size_t R) { return align16(3 * M2 * R + 2 * R + 8); }
 __host__ __device__ constexpr size_t rec_size(int M2, size_t R, bool grad)
 {
     return rec_prefix(M2, R) + (grad ? align16(3 * M2 * R) : 0);
 }
 __host__ __device__ constexpr size_t rec_off_f(int M2, size_t R) { return 3 * M2 * R; }
 __host__ __device__ constexpr size_t rec_off_pz(int M2, size_t R) { return 3 * M2 * R + 2 * R; }
+__host__ __device__ constexpr size_t rec_off_xr(int M2, size_t R) { return 3 * M2 * R + 2 * R + 4; }
+
+// Block width: z-lines (fixed cells in dims 1 and 2) are grouped in blocks of
+// BW lines adjacent along dim 2, and the points of a block are sorted by
+// plane as one run.  With 2m = 8 a wavefront covers the 8 x 8 tap rows of a
+// line; over a block of 8 lines each lane owns two rows of the block's 8 x 15
+// footprint, so the register window a lane retires per plane serves the
+// points of 8 lines instead of one.  Other windows use single lines.
+__host__ __device__ constexpr int block_w(int M2) { return M2 == 8 ? 8 : 1; }
 
 // LDS layout of the spread / interpolation kernels (bytes from the start of
 // the dynamic LDS block).  kind: 0 spread, 1 interpolation, 2 gradient.
@@ -124,7 +134,7 @@ __host__ __device__ constexpr int spread_max_threads(int real_bytes, int M2)
 }
 __host__ __device__ constexpr int interp_max_threads(int real_bytes, int M2, bool grad)
 {
-    return grad && (real_bytes == 8 || M2 >= 12) ? 512 : 1024;
+    return (grad && (real_bytes == 8 || M2 >= 12)) || (real_bytes == 8 && block_w(M2) > 1) ? 512 : 1024;
 }
 
 // FFT pass identifiers.
@@ -135,8 +145,8 @@ enum Pass { P_ADJ0 = 0, P_ADJ1, P_ADJ2, P_FWD0, P_FWD1, P_FWD2, P_COUNT };
 template <typename R> struct Launch;
 
 hipError_t launch_zero(void *p, size_t bytes, hipStream_t s);
-hipError_t launch_bin_count(const double *x, const float *xf32, long long M, const Xform &X, int T, int *counts,
-                            int *rank, int *err, double *xs_out, hipStream_t s);
+hipError_t launch_bin_count(const double *x, const float *xf32, long long M, const Xform &X, int T, int BW,
+                            int *counts, int *rank, int *err, double *xs_out, hipStream_t s);
 hipError_t launch_scan(int *data, long long n, int *tmp, hipStream_t s);
 template <typename R>
 hipError_t launch_bin_scatter(const double *x, const float *xf32, long long M, const Xform &X, int T, int m,

@@ -7,10 +7,13 @@
 // dims 1 and 2) holds a contiguous, plane-ordered run of points; the spread
 // and interpolation kernels then sweep those runs with register windows.
 //
-// Sort key of a point with cell (c0, c1, c2):
+// Sort key of a point with cell (c0, c1, c2), lines grouped in blocks of BW
+// lines along dim 2 (BW divides T):
 //   tile  = (c1 / T) * ntx + (c2 / T)
-//   line  = tile * T*T + (c1 % T) * T + (c2 % T)
-//   key   = line * n0 + c0
+//   block = tile * T*T/BW + (c1 % T) * T/BW + (c2 % T) / BW
+//   key   = (block * n0 + c0) * BW + (c2 % T) % BW
+// so a block's points are ordered by plane, then by line.  With BW = 1 a
+// block is one line.
 #include "internal.h"
 #include "window.h"
 
@@ -36,11 +39,12 @@ __device__ inline int cell_of(double xv, int n, double *u, bool *bad)
     return wrap_cell((int)fl, n);
 }
 
-__device__ inline int sort_key(const int c[3], int T, int ntx, int n0)
+__device__ inline int sort_key(const int c[3], int T, int ntx, int n0, int BW)
 {
-    int tile = (c[1] / T) * ntx + (c[2] / T);
-    int line = tile * T * T + (c[1] % T) * T + (c[2] % T);
-    return line * n0 + c[0];
+    const int tile = (c[1] / T) * ntx + (c[2] / T);
+    const int lx = c[2] % T;
+    const int block = tile * (T * T / BW) + (c[1] % T) * (T / BW) + lx / BW;
+    return (block * n0 + c[0]) * BW + lx % BW;
 }
 
 // Count pass: cell and sort key of every point, its rank among the points of
@@ -49,7 +53,7 @@ __device__ inline int sort_key(const int c[3], int T, int ntx, int n0)
 // autotuner) read.  xs_out may be null when x already is that copy.
 template <typename XT>
 __global__ void k_bin_count(const XT *__restrict__ x, long long M, int n0, int n1, int n2, int T, int ntx,
-                            int *__restrict__ counts, int *__restrict__ rank, int *__restrict__ err,
+                            int BW, int *__restrict__ counts, int *__restrict__ rank, int *__restrict__ err,
                             double *__restrict__ xs_out)
 {
     long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -64,7 +68,7 @@ __global__ void k_bin_count(const XT *__restrict__ x, long long M, int n0, int n
         c[t] = cell_of(xv, n[t], &u, &bad);
     }
     if (bad) atomicOr(err, 1);
-    rank[j] = atomicAdd(&counts[sort_key(c, T, ntx, n0)], 1);
+    rank[j] = atomicAdd(&counts[sort_key(c, T, ntx, n0, BW)], 1);
 }
 
 // Scatter of the points into sorted order, with the window values of each
@@ -117,7 +121,7 @@ __global__ __launch_bounds__(256) void k_bin_scatter(const double *__restrict__ 
         const double xv = xd ? xd[j * 3 + t] : (double)xf[j * 3 + t];
         c[t] = cell_of(xv, n[t], &u[t], &bad);
     }
-    const long long pos = poff + cell_start[sort_key(c, T, ntx, n0)] + rank[j];
+    const long long pos = poff + cell_start[sort_key(c, T, ntx, n0, block_w(M2))] + rank[j];
     perm[pos] = (int)(poff + j);
     unsigned char *rp = rec + pos * rec_bytes;
 
@@ -140,7 +144,7 @@ __global__ __launch_bounds__(256) void k_bin_scatter(const double *__restrict__ 
         }
     }
     store_block<NW * sizeof(R)>(rp, w);
-    *reinterpret_cast<int *>(rp + rec_off_pz(M2, sizeof(R))) = c[0];
+    *reinterpret_cast<int2 *>(rp + rec_off_pz(M2, sizeof(R))) = make_int2(c[0], (c[2] % T) % block_w(M2));
     if constexpr (GRAD) store_block<NW * sizeof(R)>(rp + rec_prefix(M2, sizeof(R)), dw);
 }
 
@@ -214,17 +218,17 @@ hipError_t launch_scan(int *data, long long n, int *tmp, hipStream_t s)
 }
 
 // ---------------------------------------------------------------------------
-hipError_t launch_bin_count(const double *x, const float *xf32, long long M, const Xform &X, int T, int *counts,
-                            int *rank, int *err, double *xs_out, hipStream_t s)
+hipError_t launch_bin_count(const double *x, const float *xf32, long long M, const Xform &X, int T, int BW,
+                            int *counts, int *rank, int *err, double *xs_out, hipStream_t s)
 {
     if (M <= 0) return hipSuccess;
     const unsigned nb = (unsigned)((M + 255) / 256);
     if (x)
         hipLaunchKernelGGL(k_bin_count<double>, dim3(nb), dim3(256), 0, s, x, M, X.n[0], X.n[1], X.n[2], T,
-                           X.ntx, counts, rank, err, xs_out);
+                           X.ntx, BW, counts, rank, err, xs_out);
     else
         hipLaunchKernelGGL(k_bin_count<float>, dim3(nb), dim3(256), 0, s, xf32, M, X.n[0], X.n[1], X.n[2], T,
-                           X.ntx, counts, rank, err, xs_out);
+                           X.ntx, BW, counts, rank, err, xs_out);
     return hipGetLastError();
 }
 

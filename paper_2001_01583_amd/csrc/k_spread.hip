@@ -155,8 +155,9 @@ __device__ inline ItemGeom item_geom(const SItem &W, const Xform &X, int T, int 
     g.Y0 = (W.tile / X.ntx) * T;
     g.z0 = W.slab * Zs;
     g.zs = min(Zs, g.n0 - g.z0);
-    g.ry0 = W.lb / T;
-    g.nrows = (W.le - 1) / T + M2 - g.ry0;
+    const int LPR = T / block_w(M2);  // runs per tile row
+    g.ry0 = W.lb / LPR;
+    g.nrows = (W.le - 1) / LPR + M2 - g.ry0;
     g.lb = W.lb;
     g.le = W.le;
     g.tile = W.tile;
@@ -165,7 +166,8 @@ __device__ inline ItemGeom item_geom(const SItem &W, const Xform &X, int T, int 
     return g;
 }
 
-// Step 1: run list of the item.  Run r = 3 * (line - lb) + (segment + 1);
+// Step 1: run list of the item.  A line here is one sorted run: a block of
+// BW z-lines (see block_w).  Run r = 3 * (line - lb) + (segment + 1);
 // run_p0[r] = first sorted point, run_soff = exclusive prefix of run sizes
 // (run_soff[nr] = S).  Returns S.  Contains barriers.
 template <int M2>
@@ -180,16 +182,18 @@ __device__ inline int build_runs(const ItemGeom &g, int T, const int *__restrict
     for (int i = 0; i < k; ++i) {
         int r = tid * k + i;
         if (r >= nr) break;
+        constexpr int BW = block_w(M2);
+        const int LPR = T / BW;
         int li = g.lb + r / 3, U = (r % 3 - 1) * g.n0;
-        int ly = li / T, lx = li % T;
+        int ly = li / LPR, lx = (li % LPR) * BW;
         int cnt = 0, p0 = 0;
         if (g.Y0 + ly < g.n1 && g.X0 + lx < g.n2) {
             int a, b;
             seg_range(U, g.z0, g.zs, m, g.n0, &a, &b);
             if (a <= b) {
-                const int *cs = cell_start + g.key_off + ((long long)g.tile * T * T + li) * g.n0;
-                p0 = cs[a];
-                cnt = cs[b + 1] - p0;
+                const int *cs = cell_start + g.key_off + ((long long)g.tile * (T * T / BW) + li) * g.n0 * BW;
+                p0 = cs[a * BW];
+                cnt = cs[(b + 1) * BW] - p0;
             }
         }
         run_p0[r] = (int)(g.poff + p0);
@@ -287,10 +291,15 @@ __global__ __launch_bounds__(spread_max_threads(sizeof(R), M2)) void k_spread(co
     constexpr int ST16 = (int)(rec_prefix(M2, sizeof(R)) / 16);
     constexpr int OFF_F = (int)(rec_off_f(M2, sizeof(R)) / sizeof(R));
     constexpr int OFF_PZ = (int)(rec_off_pz(M2, sizeof(R)) / 4);
+    constexpr int OFF_XR = (int)(rec_off_xr(M2, sizeof(R)) / 4);
+    constexpr int BW = block_w(M2);
+    constexpr int NW = BW > 1 ? 2 : 1;  // tile rows per lane
+    static_assert(BW == 1 || BW * BW == 64, "a blocked sweep maps (dy, xm) onto the 64 lanes");
     extern __shared__ uint4 smem16[];
     unsigned char *smem = reinterpret_cast<unsigned char *>(smem16);
     __shared__ int s_item;
     const LdsLayout LL = lds_layout(T, Zs, M2, sizeof(R), 0, COMP, cap);
+    const int LPR = T / BW;  // runs (blocks of lines) per tile row
     const int P = T + M2 - 1;
     // tile: real parts [Zs][P][pitch] of 8-byte cells, then imaginary parts
     const int pitch = spread_pitch(T, M2);
@@ -346,37 +355,67 @@ __global__ __launch_bounds__(spread_max_threads(sizeof(R), M2)) void k_spread(co
                 __syncthreads();
                 chunk_fetch<PF>(cntn, slot_n, ST16, rec, rs16, reg);
             }
+            // Tasks (times row groups): blocks of lines hold long runs, so
+            // their tasks are equal ranges of the chunk's points (about two
+            // per wavefront), each sweeping the run pieces it covers; single
+            // lines hold short runs and take one run per task.
             const int r_lo = uni(find_run(run_soff, nr, cs));
             const int r_hi = uni(find_run(run_soff, nr, cs + cnt - 1));
-            const int ntask = (r_hi - r_lo + 1) * NRG;
+            const int piece = max(16, (cnt + 2 * nwaves - 1) / (2 * nwaves));
+            const int ntask = (BW > 1 ? (cnt + piece - 1) / piece : r_hi - r_lo + 1) * NRG;
             for (int task = wave; task < ntask; task += nwaves) {
-                const int r = r_lo + task / NRG;
-                const int rg = task % NRG;
-                const int a = uni(max(run_soff[r], cs) - cs);
-                const int b = uni(min(run_soff[r + 1], cs + cnt) - cs);
+              const int rg = task % NRG;
+              int lo = cs, hi = cs + cnt, rf = r_lo + task / NRG;
+              if (BW > 1) {
+                  lo = cs + (task / NRG) * piece;
+                  hi = min(cs + cnt, lo + piece);
+                  rf = uni(find_run(run_soff, nr, lo));
+              }
+              for (int r = rf; r < nr && uni(run_soff[r]) < hi && (BW > 1 || r == rf); ++r) {
+                const int a = uni(max(run_soff[r], lo) - cs);
+                const int b = uni(min(run_soff[r + 1], hi) - cs);
                 if (a >= b) continue;
                 const int li = g.lb + r / 3;
                 const int U = (r % 3 - 1) * g.n0;
-                const int ly = li / T, lx = li % T;
+                const int ly = li / LPR, lx = (li % LPR) * BW;  // the run's first line
                 const int row = rg * 64 + lane;
                 const bool active = ROWS % 64 == 0 || row < ROWS;
-                const int dy = active ? row / M2 : 0, dx = active ? row % M2 : 0;
-                const size_t lrow = (size_t)(ly + dy) * pitch + (lx + dx);
+                // Rows of the LDS tile this lane owns.  Single lines: tap
+                // row (dy, dx) of the line.  Blocks of 8 lines (2m = 8):
+                // lane (dy, xm) owns columns lx + xm and lx + xm + 8 of tap
+                // row dy; a point on line lx + j reaches column lx + xm
+                // (dx = xm - j) when xm >= j, else lx + xm + 8.
+                const int dy = active ? row / (BW > 1 ? BW : M2) : 0;
+                const int xm = active ? row % (BW > 1 ? BW : M2) : 0;
+                size_t lrow[NW];
+                bool row_ok[NW];
+                lrow[0] = (size_t)(ly + dy) * pitch + (lx + xm);
+                row_ok[0] = active;
+                if constexpr (NW > 1) {
+                    lrow[1] = lrow[0] + BW;
+                    row_ok[1] = xm < BW - 1;  // column lx + 15 is outside every footprint
+                }
                 const int qshift = U - g.z0 - M2;  // slab-relative plane = q + qshift
 
-                R wr[M2], wi[M2];
+                R wr[NW][M2], wi[NW][M2];
 #pragma unroll
-                for (int s = 0; s < M2; ++s) wr[s] = wi[s] = R(0);
+                for (int w = 0; w < NW; ++w)
+#pragma unroll
+                    for (int s = 0; s < M2; ++s) wr[w][s] = wi[w][s] = R(0);
 
-                // add slot s (plane q) into the LDS tile
+                // add slot s (plane q) of the lane's rows into the LDS tile
                 auto flush = [&](int s, int q) __attribute__((always_inline)) {
-                    if (active) {
-                        const size_t o = (size_t)(q + qshift) * plane + lrow;
-                        if (COMP) {
-                            lds_add_comp2(&pairs[o], &pairs[o + im_off], (float)wr[s], (float)wi[s]);
-                        } else {
-                            atomicAdd(&acc[o], wr[s]);
-                            atomicAdd(&acc[o + im_off], wi[s]);
+                    const size_t o = (size_t)(q + qshift) * plane;
+#pragma unroll
+                    for (int w = 0; w < NW; ++w) {
+                        if (row_ok[w]) {
+                            if (COMP) {
+                                lds_add_comp2(&pairs[o + lrow[w]], &pairs[o + lrow[w] + im_off], (float)wr[w][s],
+                                              (float)wi[w][s]);
+                            } else {
+                                atomicAdd(&acc[o + lrow[w]], wr[w][s]);
+                                atomicAdd(&acc[o + lrow[w] + im_off], wi[w][s]);
+                            }
                         }
                     }
                 };
@@ -400,26 +439,44 @@ __global__ __launch_bounds__(spread_max_threads(sizeof(R), M2)) void k_spread(co
                     for (int k = 0; k < M2; ++k) {
                         while (Bn == p) {
                             const R *ps = reinterpret_cast<const R *>(stage + sl * ST16);
-                            const R w12 = active ? ps[M2 + dy] * ps[2 * M2 + dx] : R(0);
-                            const R sr = ps[OFF_F] * w12, si = ps[OFF_F + 1] * w12;
+                            R sr[NW], si[NW];
+                            if constexpr (NW > 1) {
+                                const int j = uni(reinterpret_cast<const int *>(ps)[OFF_XR]);
+                                const bool hi = xm < j;
+                                const int dx = hi ? xm + BW - j : xm - j;
+                                const R w12 = ps[M2 + dy] * ps[2 * M2 + dx];
+                                const R fr = ps[OFF_F] * w12, fi = ps[OFF_F + 1] * w12;
+                                sr[0] = hi ? R(0) : fr;
+                                si[0] = hi ? R(0) : fi;
+                                sr[1] = hi ? fr : R(0);
+                                si[1] = hi ? fi : R(0);
+                            } else {
+                                const R w12 = active ? ps[M2 + dy] * ps[2 * M2 + xm] : R(0);
+                                sr[0] = ps[OFF_F] * w12;
+                                si[0] = ps[OFF_F + 1] * w12;
+                            }
 #pragma unroll
                             for (int s = 0; s < M2; ++s) {
                                 const R wz = ps[s];
-                                wr[s] = fma(sr, wz, wr[s]);
-                                wi[s] = fma(si, wz, wi[s]);
+#pragma unroll
+                                for (int w = 0; w < NW; ++w) {
+                                    wr[w][s] = fma(sr[w], wz, wr[w][s]);
+                                    wi[w][s] = fma(si[w], wz, wi[w][s]);
+                                }
                             }
                             last = p;
                             ++sl;
                             Bn = sl < b ? plane_of(stage, sl, ST16, OFF_PZ, m) : kNoPlane;
                         }
                         if ((unsigned)(p - f_lo) < (unsigned)nf) flush(k, p);
-                        wr[k] = R(0);
-                        wi[k] = R(0);
+#pragma unroll
+                        for (int w = 0; w < NW; ++w) wr[w][k] = wi[w][k] = R(0);
                         ++p;
                     }
                     // window empty and the next point far ahead: skip the gap
                     if (last + M2 <= p && Bn != kNoPlane && Bn - Bn % M2 > p) p = Bn - Bn % M2;
                 }
+              }
             }
             __syncthreads();
             if (more) {
@@ -467,10 +524,14 @@ __global__ __launch_bounds__(interp_max_threads(sizeof(R), M2, GRAD)) void k_int
     constexpr int ST16 = (int)(rec_size(M2, sizeof(R), GRAD) / 16);
     constexpr int OFF_PZ = (int)(rec_off_pz(M2, sizeof(R)) / 4);
     constexpr int OFF_D = (int)(rec_prefix(M2, sizeof(R)) / sizeof(R));
+    constexpr int OFF_XR = (int)(rec_off_xr(M2, sizeof(R)) / 4);
+    constexpr int BW = block_w(M2);
+    constexpr int NW = BW > 1 ? 2 : 1;  // tile rows per lane
     extern __shared__ uint4 smem16[];
     unsigned char *smem = reinterpret_cast<unsigned char *>(smem16);
     __shared__ int s_item;
     const LdsLayout LL = lds_layout(T, Zs, M2, sizeof(R), GRAD ? 2 : 1, false, cap);
+    const int LPR = T / BW;  // runs (blocks of lines) per tile row
     const int P = T + M2 - 1;
     const int plane = P * P;
     R *tile = reinterpret_cast<R *>(smem + LL.tile);
@@ -523,19 +584,28 @@ __global__ __launch_bounds__(interp_max_threads(sizeof(R), M2, GRAD)) void k_int
                 __syncthreads();
                 chunk_fetch<PF>(cntn, slot_n, ST16, rec, rs16, reg);
             }
+            // Tasks as in the spread (ranges for blocks of lines, one run for
+            // single lines); a task evaluates each run piece it covers (all
+            // row groups), 64 points at a time, one lane owning the outputs
+            // of each point, so every slot has exactly one writer.
             const int r_lo = uni(find_run(run_soff, nr, cs));
             const int r_hi = uni(find_run(run_soff, nr, cs + cnt - 1));
-            // task = one run piece (all row groups); the piece's points are
-            // taken 64 at a time, lane (slot - first) owning the outputs of
-            // its slot, so every slot has exactly one writer.
-            for (int task = wave; task <= r_hi - r_lo; task += nwaves) {
-                const int r = r_lo + task;
-                const int a = uni(max(run_soff[r], cs) - cs);
-                const int b = uni(min(run_soff[r + 1], cs + cnt) - cs);
+            const int piece = max(16, (cnt + 2 * nwaves - 1) / (2 * nwaves));
+            const int ntask = BW > 1 ? (cnt + piece - 1) / piece : r_hi - r_lo + 1;
+            for (int task = wave; task < ntask; task += nwaves) {
+              int lo = cs, hi = cs + cnt, rf = r_lo + task;
+              if (BW > 1) {
+                  lo = cs + task * piece;
+                  hi = min(cs + cnt, lo + piece);
+                  rf = uni(find_run(run_soff, nr, lo));
+              }
+              for (int r = rf; r < nr && uni(run_soff[r]) < hi && (BW > 1 || r == rf); ++r) {
+                const int a = uni(max(run_soff[r], lo) - cs);
+                const int b = uni(min(run_soff[r + 1], hi) - cs);
                 if (a >= b) continue;
                 const int li = g.lb + r / 3;
                 const int U = (r % 3 - 1) * g.n0;
-                const int ly = li / T, lx = li % T;
+                const int ly = li / LPR, lx = (li % LPR) * BW;  // the run's first line
                 const int qshift = U - g.z0 - M2;
                 for (int c0 = a; c0 < b; c0 += 64) {
                     const int c1 = min(b, c0 + 64);
@@ -545,12 +615,23 @@ __global__ __launch_bounds__(interp_max_threads(sizeof(R), M2, GRAD)) void k_int
                     for (int rg = 0; rg < NRG; ++rg) {
                         const int row = rg * 64 + lane;
                         const bool active = ROWS % 64 == 0 || row < ROWS;
-                        const int dy = active ? row / M2 : 0, dx = active ? row % M2 : 0;
-                        const size_t lrow = (size_t)(ly + dy) * P + (lx + dx);
+                        // tile rows of this lane (as in the spread)
+                        const int dy = active ? row / (BW > 1 ? BW : M2) : 0;
+                        const int xm = active ? row % (BW > 1 ? BW : M2) : 0;
+                        size_t lrow[NW];
+                        bool row_ok[NW];
+                        lrow[0] = (size_t)(ly + dy) * P + (lx + xm);
+                        row_ok[0] = active;
+                        if constexpr (NW > 1) {
+                            lrow[1] = lrow[0] + BW;
+                            row_ok[1] = xm < BW - 1;
+                        }
 
-                        R gr[M2], gi[M2];
+                        R gr[NW][M2], gi[NW][M2];
 #pragma unroll
-                        for (int s = 0; s < M2; ++s) gr[s] = gi[s] = R(0);
+                        for (int w = 0; w < NW; ++w)
+#pragma unroll
+                            for (int s = 0; s < M2; ++s) gr[w][s] = gi[w][s] = R(0);
                         // Plane-major sweep (as in the spread): slot q mod 2m
                         // holds plane q; at plane p the plane p + 2m - 1
                         // enters, then the points whose window starts at p
@@ -559,13 +640,16 @@ __global__ __launch_bounds__(interp_max_threads(sizeof(R), M2, GRAD)) void k_int
                         // 1 pairs points, level 2 quads, level 3 octets.
                         auto load = [&](int s, int q) __attribute__((always_inline)) {
                             const int qr = q + qshift;
-                            if (active && (unsigned)qr < (unsigned)g.zs) {
-                                const size_t o = ((size_t)qr * plane + lrow) * 2;
-                                gr[s] = tile[o];
-                                gi[s] = tile[o + 1];
-                            } else {
-                                gr[s] = R(0);
-                                gi[s] = R(0);
+#pragma unroll
+                            for (int w = 0; w < NW; ++w) {
+                                if (row_ok[w] && (unsigned)qr < (unsigned)g.zs) {
+                                    const size_t o = ((size_t)qr * plane + lrow[w]) * 2;
+                                    gr[w][s] = tile[o];
+                                    gi[w][s] = tile[o + 1];
+                                } else {
+                                    gr[w][s] = R(0);
+                                    gi[w][s] = R(0);
+                                }
                             }
                         };
                         R s0[2 * NO], s1[2 * NO], s2[2 * NO];
@@ -609,11 +693,30 @@ __global__ __launch_bounds__(interp_max_threads(sizeof(R), M2, GRAD)) void k_int
                                 if (Bn <= p + M2 - 1) load((k + M2 - 1) % M2, p + M2 - 1);
                                 while (Bn == p) {
                                     const R *ps = reinterpret_cast<const R *>(stage + sl * ST16);
-                                    R sr = R(0), si = R(0);
+                                    // the lane's row for this point: single
+                                    // lines use row 0; in a block, row 1 when
+                                    // the point's line lies right of column xm
+                                    int dx = xm;
+                                    bool hi = false;
+                                    if constexpr (NW > 1) {
+                                        const int j = uni(reinterpret_cast<const int *>(ps)[OFF_XR]);
+                                        hi = xm < j;
+                                        dx = hi ? xm + BW - j : xm - j;
+                                    }
+                                    R sr, si;
+                                    {
+                                        R ar[NW], ai[NW];
 #pragma unroll
-                                    for (int s = 0; s < M2; ++s) {
-                                        sr = fma(gr[s], ps[s], sr);
-                                        si = fma(gi[s], ps[s], si);
+                                        for (int w = 0; w < NW; ++w) {
+                                            ar[w] = ai[w] = R(0);
+#pragma unroll
+                                            for (int s = 0; s < M2; ++s) {
+                                                ar[w] = fma(gr[w][s], ps[s], ar[w]);
+                                                ai[w] = fma(gi[w][s], ps[s], ai[w]);
+                                            }
+                                        }
+                                        sr = (NW > 1 && hi) ? ar[NW - 1] : ar[0];
+                                        si = (NW > 1 && hi) ? ai[NW - 1] : ai[0];
                                     }
                                     const R w1 = active ? ps[M2 + dy] : R(0);
                                     const R w2 = active ? ps[2 * M2 + dx] : R(0);
@@ -623,11 +726,20 @@ __global__ __launch_bounds__(interp_max_threads(sizeof(R), M2, GRAD)) void k_int
                                     v[1] = si * w12;
                                     if constexpr (GRAD) {
                                         const R *dp = ps + OFF_D;
-                                        R dr = R(0), di = R(0);
+                                        R dr, di;
+                                        {
+                                            R ar[NW], ai[NW];
 #pragma unroll
-                                        for (int s = 0; s < M2; ++s) {
-                                            dr = fma(gr[s], dp[s], dr);
-                                            di = fma(gi[s], dp[s], di);
+                                            for (int w = 0; w < NW; ++w) {
+                                                ar[w] = ai[w] = R(0);
+#pragma unroll
+                                                for (int s = 0; s < M2; ++s) {
+                                                    ar[w] = fma(gr[w][s], dp[s], ar[w]);
+                                                    ai[w] = fma(gi[w][s], dp[s], ai[w]);
+                                                }
+                                            }
+                                            dr = (NW > 1 && hi) ? ar[NW - 1] : ar[0];
+                                            di = (NW > 1 && hi) ? ai[NW - 1] : ai[0];
                                         }
                                         const R d1 = active ? dp[M2 + dy] * w2 : R(0);
                                         const R d2 = active ? w1 * dp[2 * M2 + dx] : R(0);
@@ -667,6 +779,7 @@ __global__ __launch_bounds__(interp_max_threads(sizeof(R), M2, GRAD)) void k_int
                         for (int i = 0; i < 2 * NO; ++i) oacc[(c0 + own) * 2 * NO + i] = ores[i];
                     }
                 }
+              }
             }
             __syncthreads();
             for (int e = tid; e < cnt * 2 * NO; e += nthr) {

@@ -111,6 +111,7 @@ bool tiling_fits(const hpnfft_plan_s *p, Tiling t)
 {
     if (t.T < 4 || t.T > 32 || t.Zs < 2 || t.Zs > 64) return false;
     if (t.threads < 64 || t.threads > 1024 || t.threads % 64) return false;
+    if (t.T % block_w(p->M2())) return false;  // whole blocks of lines per tile row
     bool comp = p->prec == HPNFFT_F32;
     if (!lds_fit(t.T, t.Zs, p->M2(), p->rbytes(), 0, comp).cap) return false;
     if (!lds_fit(t.T, t.Zs, p->M2(), p->rbytes(), 1, false).cap) return false;
@@ -127,7 +128,8 @@ bool tiling_fits(const hpnfft_plan_s *p, Tiling t)
 Tiling default_tiling(const hpnfft_plan_s *p)
 {
     const int M2 = p->M2();
-    const int target = std::max(4, 22 - M2);
+    // blocked 2m = 8 sweeps: tiles of one block of lines per row fit best
+    const int target = block_w(M2) > 1 ? 8 : std::max(4, 22 - M2);
     std::vector<int> Ts = {4, 6, 8, 12, 16, 24, 32};
     std::stable_sort(Ts.begin(), Ts.end(),
                      [&](int a, int b) { return std::abs(a - target) < std::abs(b - target); });
@@ -377,7 +379,7 @@ int bin_points(hpnfft_plan_s *p, const double *x = nullptr, const float *x32 = n
         HCHECK(launch_zero(cs, (size_t)p->keys[b] * 4, s));
         double *xb = xs + X.poff * 3;
         HCHECK(launch_bin_count(stored ? xb : (x ? x + X.poff * 3 : nullptr), x32 ? x32 + X.poff * 3 : nullptr,
-                                X.M, X, p->til.T, cs, p->at<int>(L.rank), setp, stored ? nullptr : xb, s));
+                                X.M, X, p->til.T, block_w(p->M2()), cs, p->at<int>(L.rank), setp, stored ? nullptr : xb, s));
         HCHECK(launch_scan(cs, p->keys[b], p->at<int>(L.scan_tmp), s));
         if (p->prec == HPNFFT_F32)
             HCHECK(launch_bin_scatter<float>(xb, nullptr, X.M, X, p->til.T, p->m, p->b, p->inv_peak, cs,
