@@ -73,6 +73,11 @@ __host__ __device__ constexpr size_t rec_off_xr(int M2, size_t R) { return 3 * M
 // points of 8 lines instead of one.  Other windows use single lines.
 __host__ __device__ constexpr int block_w(int M2) { return M2 == 8 ? 8 : 1; }
 
+// Coefficients of the per-tap window polynomials (see fit_window_poly).
+constexpr int kPolyF32 = 10;
+constexpr int kPolyF64 = 17;
+constexpr int kPolyMax = 17;
+
 // LDS layout of the spread / interpolation kernels (bytes from the start of
 // the dynamic LDS block).  kind: 0 spread, 1 interpolation, 2 gradient.
 //   [tile][stage: cap records][slot maps: 2 x cap ints][run_p0: 3T^2][run_soff: 3T^2+1]
@@ -150,7 +155,7 @@ hipError_t launch_bin_count(const double *x, const float *xf32, long long M, con
 hipError_t launch_scan(int *data, long long n, int *tmp, hipStream_t s);
 template <typename R>
 hipError_t launch_bin_scatter(const double *x, const float *xf32, long long M, const Xform &X, int T, int m,
-                              double b, double inv_peak, const int *cell_start, const int *rank, int *perm,
+                              double b, double inv_peak, const double *poly, const int *cell_start, const int *rank, int *perm,
                               unsigned char *rec, size_t rec_bytes, bool grad, hipStream_t s);
 template <typename R>
 hipError_t launch_gather(const void *f, const int *perm, long long total, unsigned char *rec,

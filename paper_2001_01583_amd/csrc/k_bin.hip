@@ -100,16 +100,27 @@ __device__ inline void store_block(unsigned char *dst, const T *src)
     }
 }
 
+// Polynomial in v with NC coefficients (c[k] multiplies v^k), by Horner's rule.
+template <int NC>
+__device__ inline double horner(const double *__restrict__ c, double v)
+{
+    double r = c[NC - 1];
+#pragma unroll
+    for (int k = NC - 2; k >= 0; --k) r = fma(r, v, c[k]);
+    return r;
+}
+
 template <typename R, int M2, bool GRAD>
 __global__ __launch_bounds__(256) void k_bin_scatter(const double *__restrict__ xd, const float *__restrict__ xf,
                                                      long long M, long long poff, int n0, int n1, int n2, int T,
                                                      int ntx, const int *__restrict__ cell_start,
                                                      const int *__restrict__ rank, int *__restrict__ perm,
                                                      unsigned char *__restrict__ rec, size_t rec_bytes, double b,
-                                                     double inv_peak)
+                                                     double inv_peak, const double *__restrict__ poly)
 {
     constexpr int m = M2 / 2;
     constexpr int NW = 3 * M2;
+    constexpr int NC = sizeof(R) == 4 ? kPolyF32 : kPolyF64;
     static_assert((NW * sizeof(R)) % 8 == 0, "window block is a whole number of 8-byte units");
     const long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= M) return;
@@ -129,18 +140,33 @@ __global__ __launch_bounds__(256) void k_bin_scatter(const double *__restrict__ 
     if (rot < 0) rot += M2;
     R w[NW];
     R dw[GRAD ? NW : 1];
+    // values in tap order (the tap index, hence the polynomial, is the same
+    // for every thread)
 #pragma unroll
     for (int dim = 0; dim < 3; ++dim) {
 #pragma unroll
-        for (int sl = 0; sl < M2; ++sl) {
-            int t = sl;
-            if (dim == 0) {
-                t = sl - rot;
-                if (t < 0) t += M2;
-            }
+        for (int t = 0; t < M2; ++t) {
             const double dist = u[dim] + (double)(m - 1 - t);
-            w[dim * M2 + sl] = (R)kb_phi(dist, m, b, inv_peak);
-            if constexpr (GRAD) dw[dim * M2 + sl] = (R)((double)n[dim] * kb_dphi(dist, m, b, inv_peak));
+            w[dim * M2 + t] = (R)(poly ? horner<NC>(poly + t * NC, 2.0 * u[dim] - 1.0) : kb_phi(dist, m, b, inv_peak));
+            if constexpr (GRAD) dw[dim * M2 + t] = (R)((double)n[dim] * kb_dphi(dist, m, b, inv_peak));
+        }
+    }
+    // dim 0 into slot order, slot s = (tap + rot) mod 2m: a rotation by rot
+    // composed of conditional rotations by 1, 2, 4, ... (constant indices)
+#pragma unroll
+    for (int k = 1; k < M2; k <<= 1) {
+        if (rot & k) {
+            R tmp[M2], dtmp[GRAD ? M2 : 1];
+#pragma unroll
+            for (int s = 0; s < M2; ++s) {
+                tmp[s] = w[(s - k + M2) % M2];
+                if constexpr (GRAD) dtmp[s] = dw[(s - k + M2) % M2];
+            }
+#pragma unroll
+            for (int s = 0; s < M2; ++s) {
+                w[s] = tmp[s];
+                if constexpr (GRAD) dw[s] = dtmp[s];
+            }
         }
     }
     store_block<NW * sizeof(R)>(rp, w);
@@ -235,23 +261,23 @@ hipError_t launch_bin_count(const double *x, const float *xf32, long long M, con
 template <typename R, int M2>
 static void scatter_m(const double *x, const float *xf32, long long M, const Xform &X, int T,
                       const int *cell_start, const int *rank, int *perm, unsigned char *rec, size_t rec_bytes,
-                      double b, double inv_peak, bool grad, hipStream_t s)
+                      double b, double inv_peak, const double *poly, bool grad, hipStream_t s)
 {
     const unsigned nb = (unsigned)((M + 255) / 256);
     auto k = grad ? k_bin_scatter<R, M2, true> : k_bin_scatter<R, M2, false>;
     hipLaunchKernelGGL(k, dim3(nb), dim3(256), 0, s, x, xf32, M, X.poff, X.n[0], X.n[1], X.n[2], T, X.ntx,
-                       cell_start, rank, perm, rec, rec_bytes, b, inv_peak);
+                       cell_start, rank, perm, rec, rec_bytes, b, inv_peak, poly);
 }
 
 template <typename R>
 hipError_t launch_bin_scatter(const double *x, const float *xf32, long long M, const Xform &X, int T, int m,
-                              double b, double inv_peak, const int *cell_start, const int *rank, int *perm,
-                              unsigned char *rec, size_t rec_bytes, bool grad, hipStream_t s)
+                              double b, double inv_peak, const double *poly, const int *cell_start, const int *rank,
+                              int *perm, unsigned char *rec, size_t rec_bytes, bool grad, hipStream_t s)
 {
     if (M <= 0) return hipSuccess;
     switch (m) {
 #define HPNFFT_SCATTER_CASE(MM) \
-    case MM: scatter_m<R, 2 * MM>(x, xf32, M, X, T, cell_start, rank, perm, rec, rec_bytes, b, inv_peak, grad, s); break;
+    case MM: scatter_m<R, 2 * MM>(x, xf32, M, X, T, cell_start, rank, perm, rec, rec_bytes, b, inv_peak, poly, grad, s); break;
         HPNFFT_SCATTER_CASE(1)
         HPNFFT_SCATTER_CASE(2)
         HPNFFT_SCATTER_CASE(3)
@@ -267,10 +293,10 @@ hipError_t launch_bin_scatter(const double *x, const float *xf32, long long M, c
 }
 
 template hipError_t launch_bin_scatter<double>(const double *, const float *, long long, const Xform &, int, int,
-                                               double, double, const int *, const int *, int *, unsigned char *,
-                                               size_t, bool, hipStream_t);
+                                               double, double, const double *, const int *, const int *, int *,
+                                               unsigned char *, size_t, bool, hipStream_t);
 template hipError_t launch_bin_scatter<float>(const double *, const float *, long long, const Xform &, int, int,
-                                              double, double, const int *, const int *, int *, unsigned char *,
-                                              size_t, bool, hipStream_t);
+                                              double, double, const double *, const int *, const int *, int *,
+                                              unsigned char *, size_t, bool, hipStream_t);
 
 }  // namespace hpnfft

@@ -29,117 +29,143 @@ __device__ inline int line_cost(const int *cs_line, int n0, int z0, int zs, int 
     return c;
 }
 
-// One workgroup per (tile, slab): its threads sum the line costs, the total
-// is stored in tcost (no zeroing needed) and added to the grand total.
+// One thread per (tile, slab, run): the run's cost goes to
+// lcost[(tile * nslab + slab) * nl + run] (consecutive threads, consecutive
+// words) and into the grand total (one atomic per wavefront).
 __global__ __launch_bounds__(256) void k_tile_cost(const int *__restrict__ cell_start, int n0, int T, int Zs,
-                                                   int m, int BW, int nslab, int *__restrict__ tcost,
-                                                   unsigned long long *__restrict__ total)
+                                                   int m, int BW, int nslab, long long n,
+                                                   int *__restrict__ lcost, unsigned long long *__restrict__ total)
 {
-    __shared__ int blk;
-    if (threadIdx.x == 0) blk = 0;
-    __syncthreads();
-    const int ts = blockIdx.x;
-    const int slab = ts % nslab, tile = ts / nslab;
-    const int z0 = slab * Zs, zs = min(Zs, n0 - z0);
+    const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const int nl = T * T / BW;
     int c = 0;
-    for (int li = threadIdx.x; li < nl; li += blockDim.x)
-        c += line_cost(cell_start + ((long long)tile * nl + li) * n0 * BW, n0, z0, zs, m, BW);
-    // wavefront sum, then one LDS add per wavefront
+    if (g < n) {
+        const int li = (int)(g % nl);
+        const long long ts = g / nl;
+        const int slab = (int)(ts % nslab), tile = (int)(ts / nslab);
+        const int z0 = slab * Zs, zs = min(Zs, n0 - z0);
+        c = line_cost(cell_start + ((long long)tile * nl + li) * n0 * BW, n0, z0, zs, m, BW);
+        lcost[g] = c;
+    }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
-    if ((threadIdx.x & 63) == 0) atomicAdd(&blk, c);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        tcost[ts] = blk;
-        atomicAdd(total, (unsigned long long)blk);
-    }
+    if ((threadIdx.x & 63) == 0 && c) atomicAdd(total, (unsigned long long)c);
 }
 
-// One wavefront per (tile, slab): the T*T line costs are prefix-summed across
-// the lanes and the pair is cut wherever the running cost crosses a multiple of
-// the cap (a pair within the cap becomes one item).
-__global__ void k_make_items(const int *__restrict__ cell_start, int xf, int n0, int T, int Zs, int m, int BW,
-                             int ntiles, int nslab, const int *__restrict__ tcost,
-                             const unsigned long long *__restrict__ total, int cap_div, int min_cap,
-                             int max_items, SItem *__restrict__ items, int *__restrict__ nitems,
-                             int *__restrict__ overflow)
+// One wavefront per (tile, slab), four per workgroup: the run costs (from
+// k_tile_cost) are prefix-summed across the lanes and the pair is cut wherever
+// the running cost crosses a multiple of the cap (a pair within the cap
+// becomes one item).  The workgroup counts its items first and reserves their
+// slots in the list with one atomic.
+__global__ __launch_bounds__(256) void k_make_items(const int *__restrict__ lcost, int xf, int T, int BW, int ntiles,
+                                                    int nslab, const unsigned long long *__restrict__ total,
+                                                    int cap_div, int min_cap, int max_items,
+                                                    SItem *__restrict__ items, int *__restrict__ nitems,
+                                                    int *__restrict__ overflow)
 {
-    const int lane = threadIdx.x & 63;
-    const int g = (int)(((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
-    if (g >= ntiles * nslab) return;
-    const int tile = g / nslab, slab = g % nslab;
-    const int z0 = slab * Zs, zs = min(Zs, n0 - z0);
-    long long capl = (long long)(*total / (unsigned long long)cap_div);
+    __shared__ int wcount[4], wbase[4];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int g = blockIdx.x * 4 + w;
+    const bool valid = g < ntiles * nslab;
+    const int tile = valid ? g / nslab : 0, slab = valid ? g % nslab : 0;
+    const long long capl = (long long)(*total / (unsigned long long)cap_div);
     const int cap = capl < min_cap ? min_cap : (int)capl;
-    const int c = tcost[g];
     const int nl = T * T / BW;
-    auto emit = [&](int lb, int le) {
-        int idx = atomicAdd(nitems, 1);
-        if (idx >= max_items) {
-            atomicOr(overflow, 1);
+    const int *lc_pair = lcost + (long long)(valid ? g : 0) * nl;
+    int c = 0;
+    if (valid)
+        for (int li = lane; li < nl; li += 64) c += lc_pair[li];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+    const bool any = valid && c > nl;  // points in some run of this pair
+    const bool split = any && c > cap;
+
+    // calls f(lb, le) for every item of the pair, in order
+    auto items_of = [&](auto &&f) {
+        if (!any) return;
+        if (!split) {
+            f(0, nl);
             return;
         }
-        SItem itm;
-        itm.xf = xf;
-        itm.tile = tile;
-        itm.slab = slab;
-        itm.lb = lb;
-        itm.le = le;
-        itm.pad0 = itm.pad1 = itm.pad2 = 0;
-        items[idx] = itm;
-    };
-    if (c <= nl) return;  // no points in any line of this pair
-    if (c <= cap) {
-        if (lane == 0) emit(0, nl);
-        return;
-    }
-    // lines in consecutive blocks of 64: lane k of block handles line base + k
-    int carry = 0;       // cost before this block
-    int lb = 0;          // start of the open item
-    for (int base = 0; base < nl; base += 64) {
-        int li = base + lane;
-        int lc = li < nl ? line_cost(cell_start + ((long long)tile * nl + li) * n0 * BW, n0, z0, zs, m, BW) : 0;
-        int incl = lc;
+        int carry = 0;  // cost before this block of 64 runs
+        int lb = 0;     // start of the open item
+        for (int base = 0; base < nl; base += 64) {
+            const int li = base + lane;
+            const int lc = li < nl ? lc_pair[li] : 0;
+            int incl = lc;
 #pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            int y = __shfl_up(incl, o, 64);
-            if (lane >= o) incl += y;
+            for (int o = 1; o < 64; o <<= 1) {
+                const int y = __shfl_up(incl, o, 64);
+                if (lane >= o) incl += y;
+            }
+            const int before = carry + incl - lc, after = carry + incl;
+            // a cut after run li when the running cost crosses a multiple of cap
+            const bool cut = li < nl && (after / cap) != (before / cap) && li + 1 < nl;
+            unsigned long long mask = __ballot(cut);
+            while (mask) {
+                const int k = __ffsll((long long)mask) - 1;
+                mask &= mask - 1;
+                f(lb, base + k + 1);
+                lb = base + k + 1;
+            }
+            carry += __shfl(incl, 63, 64);
         }
-        int before = carry + incl - lc, after = carry + incl;
-        // a cut after line li when the running cost crosses a multiple of cap
-        bool cut = li < nl && (after / cap) != (before / cap) && li + 1 < nl;
-        unsigned long long mask = __ballot(cut);
-        while (mask) {
-            int k = __ffsll((long long)mask) - 1;
-            mask &= mask - 1;
-            int le = base + k + 1;
-            if (lane == 0) emit(lb, le);
-            lb = le;
+        f(lb, nl);
+    };
+    int nit = 0;
+    items_of([&](int, int) { ++nit; });
+    if (lane == 0) wcount[w] = nit;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int t = 0;
+        for (int k = 0; k < 4; ++k) {
+            wbase[k] = t;
+            t += wcount[k];
         }
-        carry += __shfl(incl, 63, 64);
+        const int base = t ? atomicAdd(nitems, t) : 0;
+        for (int k = 0; k < 4; ++k) wbase[k] += base;
     }
-    if (lane == 0 && lb < nl) emit(lb, nl);
+    __syncthreads();
+    int idx = wbase[w];
+    items_of([&](int lb, int le) {
+        if (lane == 0) {
+            if (idx < max_items) {
+                SItem itm;
+                itm.xf = xf;
+                itm.tile = tile;
+                itm.slab = slab;
+                itm.lb = lb;
+                itm.le = le;
+                itm.pad0 = itm.pad1 = itm.pad2 = 0;
+                items[idx] = itm;
+            } else {
+                atomicOr(overflow, 1);
+            }
+        }
+        ++idx;
+    });
 }
 
-hipError_t launch_tile_cost(const int *cell_start, const Xform &X, int T, int Zs, int m, int *tcost,
+hipError_t launch_tile_cost(const int *cell_start, const Xform &X, int T, int Zs, int m, int *lcost,
                             unsigned long long *total, hipStream_t s)
 {
-    const long long nts = (long long)X.ntx * X.nty * X.nslab;
-    if (nts <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_tile_cost, dim3((unsigned)nts), dim3(256), 0, s, cell_start, X.n[0], T, Zs, m,
-                       block_w(2 * m), X.nslab, tcost, total);
+    const int BW = block_w(2 * m);
+    const long long n = (long long)X.ntx * X.nty * X.nslab * (T * T / BW);
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_tile_cost, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, cell_start, X.n[0], T, Zs,
+                       m, BW, X.nslab, n, lcost, total);
     return hipGetLastError();
 }
 
-hipError_t launch_make_items(const int *cell_start, int xf, const Xform &X, int T, int Zs, int m,
-                             const int *tcost, const unsigned long long *total, int cap_div, int min_cap,
-                             int max_items, SItem *items, int *nitems, int *overflow, hipStream_t s)
+hipError_t launch_make_items(const int *lcost, int xf, const Xform &X, int T, int m, const unsigned long long *total,
+                             int cap_div, int min_cap, int max_items, SItem *items, int *nitems, int *overflow,
+                             hipStream_t s)
 {
-    long long n = (long long)X.ntx * X.nty * X.nslab * 64;  // one wavefront per pair
-    hipLaunchKernelGGL(k_make_items, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, cell_start, xf, X.n[0],
-                       T, Zs, m, block_w(2 * m), X.ntx * X.nty, X.nslab, tcost, total, cap_div, min_cap,
-                       max_items, items, nitems, overflow);
+    const long long pairs = (long long)X.ntx * X.nty * X.nslab;  // one wavefront per pair
+    if (pairs <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_make_items, dim3((unsigned)((pairs + 3) / 4)), dim3(256), 0, s, lcost, xf, T,
+                       block_w(2 * m), X.ntx * X.nty, X.nslab, total, cap_div, min_cap, max_items, items, nitems,
+                       overflow);
     return hipGetLastError();
 }
 

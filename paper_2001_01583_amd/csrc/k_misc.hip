@@ -27,16 +27,22 @@ hipError_t launch_zero(void *p, size_t bytes, hipStream_t s)
     return hipGetLastError();
 }
 
+// Native two-component vector of a real type (one memory operation per
+// complex value).
+template <typename R> struct Cplx;
+template <> struct Cplx<float> { typedef float T __attribute__((ext_vector_type(2))); };
+template <> struct Cplx<double> { typedef double T __attribute__((ext_vector_type(2))); };
+
 template <typename R>
 __global__ void k_gather(const R *__restrict__ f, const int *__restrict__ perm, long long total,
                          unsigned char *__restrict__ rec, size_t rec_bytes, size_t off_f)
 {
     long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= total) return;
-    long long j = perm[p];
-    R *d = reinterpret_cast<R *>(rec + p * rec_bytes + off_f);
-    d[0] = f[2 * j];
-    d[1] = f[2 * j + 1];
+    const long long j = perm[p];
+    // one complex value: a single 8- or 16-byte load and store
+    using C = typename Cplx<R>::T;
+    *reinterpret_cast<C *>(rec + p * rec_bytes + off_f) = reinterpret_cast<const C *>(f)[j];
 }
 
 template <typename R>
@@ -45,9 +51,9 @@ __global__ void k_scatter(const R *__restrict__ outs, const int *__restrict__ pe
 {
     long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= total) return;
-    long long j = perm[p];
-    f[2 * j] = outs[2 * p];
-    f[2 * j + 1] = outs[2 * p + 1];
+    const long long j = perm[p];
+    using C = typename Cplx<R>::T;
+    reinterpret_cast<C *>(f)[j] = reinterpret_cast<const C *>(outs)[p];
 }
 
 // outs4 per sorted point: p, d0 p, d1 p, d2 p (complex).  grad_x = Re(f conj(d p)).

@@ -22,11 +22,11 @@
 #include "window.h"
 
 namespace hpnfft {
-hipError_t launch_tile_cost(const int *cell_start, const Xform &X, int T, int Zs, int m, int *tcost,
+hipError_t launch_tile_cost(const int *cell_start, const Xform &X, int T, int Zs, int m, int *lcost,
                             unsigned long long *total, hipStream_t s);
-hipError_t launch_make_items(const int *cell_start, int xf, const Xform &X, int T, int Zs, int m,
-                             const int *tcost, const unsigned long long *total, int cap_div, int min_cap,
-                             int max_items, SItem *items, int *nitems, int *overflow, hipStream_t s);
+hipError_t launch_make_items(const int *lcost, int xf, const Xform &X, int T, int m, const unsigned long long *total,
+                             int cap_div, int min_cap, int max_items, SItem *items, int *nitems, int *overflow,
+                             hipStream_t s);
 }  // namespace hpnfft
 
 using namespace hpnfft;
@@ -54,7 +54,7 @@ int fft_count(int n)
 }
 
 struct Layout {
-    size_t counters, setp, grids, tmpA, tmpB, cell_start, scan_tmp, rank, perm, xs, rec, outs, tcost,
+    size_t counters, setp, grids, tmpA, tmpB, cell_start, scan_tmp, rank, perm, xs, rec, outs, tcost, poly,
         items, fit[3], ewald, roll, tw, xf, total;
     size_t rec_bytes = 0;
     std::vector<size_t> grid_off, tmpA_off, tmpB_off, key_off, tcost_off, roll_off;
@@ -78,6 +78,7 @@ struct hpnfft_plan_s {
     size_t ws_bytes = 0;
     Layout L;
     bool have_ws = false, have_points = false;
+    bool poly_ok = false;  // window polynomials uploaded (else direct evaluation)
     int nitems = 0;
     int cus = 256;
     int maxn = 0;
@@ -206,7 +207,7 @@ void build_layout(hpnfft_plan_s *p)
     L.tcost = off;
     for (int b = 0; b < p->B; ++b) {
         const Xform &X = p->hx[b];
-        L.tcost_off.push_back(take((size_t)X.ntx * X.nty * X.nslab * 4));
+        L.tcost_off.push_back(take((size_t)X.ntx * X.nty * X.nslab * (T * T / block_w(p->M2())) * 4));
     }
     L.max_items = (int)std::min<long long>(pairs + (long long)p->cus * 4 + 64, 0x7fffffffLL / 64);
     L.items = take((size_t)L.max_items * sizeof(SItem));
@@ -224,6 +225,7 @@ void build_layout(hpnfft_plan_s *p)
     }
     L.ew_blocks = (int)((maxF + 255) / 256);
     L.ewald = take((size_t)L.ew_blocks * 8 + 64);
+    L.poly = take((size_t)p->M2() * kPolyMax * 8);
     L.roll = off;
     for (int b = 0; b < p->B; ++b) {
         const Xform &X = p->hx[b];
@@ -238,6 +240,52 @@ void build_layout(hpnfft_plan_s *p)
     L.xf = take((size_t)p->B * sizeof(Xform));
     L.total = off + 256;
     (void)gbytes;
+}
+
+// Window values along one dimension as polynomials: for tap t the function
+// u -> Phi(u + m - 1 - t), u in [0, 1), is interpolated at nc Chebyshev points
+// of v = 2u - 1 and written in monomials of v (coef[t * nc + k] multiplies
+// v^k).  The window is analytic in t, so the interpolant converges fast: 10
+// coefficients reach ~1e-10 and 16-17 reach ~1e-14 of the peak.  The fit is
+// checked against direct evaluation on a fine grid; false if it misses tol.
+bool fit_window_poly(int m, double b, double ip, int nc, double tol, std::vector<double> &coef)
+{
+    const int M2 = 2 * m, d = nc - 1;
+    coef.assign((size_t)M2 * nc, 0.0);
+    for (int t = 0; t < M2; ++t) {
+        std::vector<long double> fv(nc), ch(nc), mono(nc, 0.0L), tkm1(nc, 0.0L), tk(nc, 0.0L), tn(nc);
+        const long double pi = 3.141592653589793238462643383279502884L;
+        for (int j = 0; j < nc; ++j) {
+            const long double v = cosl(pi * (j + 0.5L) / nc);
+            fv[j] = kb_phi((double)((v + 1.0L) / 2.0L) + (m - 1 - t), m, b, ip);
+        }
+        for (int k = 0; k < nc; ++k) {
+            long double a = 0.0L;
+            for (int j = 0; j < nc; ++j) a += fv[j] * cosl(pi * k * (j + 0.5L) / nc);
+            ch[k] = a * 2.0L / nc;
+        }
+        ch[0] *= 0.5L;
+        // sum_k ch[k] T_k(v) in monomials, T_{k+1} = 2 v T_k - T_{k-1}
+        tkm1[0] = 1.0L;
+        if (d >= 1) tk[1] = 1.0L;
+        mono[0] += ch[0];
+        if (d >= 1) mono[1] += ch[1];
+        for (int k = 1; k < d; ++k) {
+            for (int i = 0; i < nc; ++i) tn[i] = (i ? 2.0L * tk[i - 1] : 0.0L) - tkm1[i];
+            for (int i = 0; i < nc; ++i) mono[i] += ch[k + 1] * tn[i];
+            tkm1 = tk;
+            tk = tn;
+        }
+        for (int i = 0; i < nc; ++i) coef[(size_t)t * nc + i] = (double)mono[i];
+        for (int q = 0; q <= 256; ++q) {
+            const double u = q / 256.0 * (1.0 - 1e-12);
+            const double v = 2.0 * u - 1.0;
+            double r = coef[(size_t)t * nc + d];
+            for (int k = d - 1; k >= 0; --k) r = std::fma(r, v, coef[(size_t)t * nc + k]);
+            if (std::fabs(r - kb_phi(u + (m - 1 - t), m, b, ip)) > tol) return false;
+        }
+    }
+    return true;
 }
 
 int upload_tables(hpnfft_plan_s *p)
@@ -266,6 +314,18 @@ int upload_tables(hpnfft_plan_s *p)
         HCHECK(hipMemcpyAsync(p->ws + L.roll_off[b], h.data(), h.size() * 8, hipMemcpyHostToDevice,
                               p->stream));
         HCHECK(hipStreamSynchronize(p->stream));
+    }
+    // window polynomials for set_points (float32 tables: 10 coefficients;
+    // float64: 17); without a good fit the tables are evaluated directly
+    {
+        const bool f32 = p->prec == HPNFFT_F32;
+        const int nc = f32 ? kPolyF32 : kPolyF64;
+        std::vector<double> coef;
+        p->poly_ok = fit_window_poly(p->m, p->b, p->inv_peak, nc, f32 ? 1e-9 : 5e-14, coef);
+        if (p->poly_ok) {
+            HCHECK(hipMemcpyAsync(p->ws + L.poly, coef.data(), coef.size() * 8, hipMemcpyHostToDevice, p->stream));
+            HCHECK(hipStreamSynchronize(p->stream));
+        }
     }
     // twiddles exp(-2 pi i j / n), computed in FP64 (long double angle), rounded once for float
     for (auto &kv : L.tw_off) {
@@ -382,11 +442,13 @@ int bin_points(hpnfft_plan_s *p, const double *x = nullptr, const float *x32 = n
                                 X.M, X, p->til.T, block_w(p->M2()), cs, p->at<int>(L.rank), setp, stored ? nullptr : xb, s));
         HCHECK(launch_scan(cs, p->keys[b], p->at<int>(L.scan_tmp), s));
         if (p->prec == HPNFFT_F32)
-            HCHECK(launch_bin_scatter<float>(xb, nullptr, X.M, X, p->til.T, p->m, p->b, p->inv_peak, cs,
+            HCHECK(launch_bin_scatter<float>(xb, nullptr, X.M, X, p->til.T, p->m, p->b, p->inv_peak,
+                                             p->poly_ok ? p->at<double>(L.poly) : nullptr, cs,
                                              p->at<int>(L.rank), p->at<int>(L.perm), p->at<unsigned char>(L.rec),
                                              L.rec_bytes, p->grad(), s));
         else
-            HCHECK(launch_bin_scatter<double>(xb, nullptr, X.M, X, p->til.T, p->m, p->b, p->inv_peak, cs,
+            HCHECK(launch_bin_scatter<double>(xb, nullptr, X.M, X, p->til.T, p->m, p->b, p->inv_peak,
+                                              p->poly_ok ? p->at<double>(L.poly) : nullptr, cs,
                                               p->at<int>(L.rank), p->at<int>(L.perm),
                                               p->at<unsigned char>(L.rec), L.rec_bytes, p->grad(), s));
         HCHECK(launch_tile_cost(cs, X, p->til.T, p->til.Zs, p->m, p->at<int>(L.tcost_off[b]), total, s));
@@ -394,9 +456,8 @@ int bin_points(hpnfft_plan_s *p, const double *x = nullptr, const float *x32 = n
     const int cap_div = p->cus * 4;
     for (int b = 0; b < p->B; ++b) {
         const Xform &X = p->hx[b];
-        HCHECK(launch_make_items(p->at<int>(L.key_off[b]), b, X, p->til.T, p->til.Zs, p->m,
-                                 p->at<int>(L.tcost_off[b]), total, cap_div, kMinCap, L.max_items,
-                                 p->at<SItem>(L.items), setp + 1, setp + 2, s));
+        HCHECK(launch_make_items(p->at<int>(L.tcost_off[b]), b, X, p->til.T, p->m, total, cap_div, kMinCap,
+                                 L.max_items, p->at<SItem>(L.items), setp + 1, setp + 2, s));
     }
     int host[4] = {0, 0, 0, 0};
     HCHECK(hipMemcpyAsync(host, setp, sizeof(host), hipMemcpyDeviceToHost, s));
