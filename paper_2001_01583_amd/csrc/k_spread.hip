@@ -304,7 +304,7 @@ __global__ __launch_bounds__(spread_max_threads(sizeof(R), M2)) void k_spread(co
     // tile: real parts [Zs][P][pitch] of 8-byte cells, then imaginary parts
     const int pitch = spread_pitch(T, M2);
     const int plane = P * pitch;
-    const size_t im_off = (size_t)Zs * plane;
+    const int im_off = Zs * plane;  // LDS indices fit in 32 bits
     R *acc = reinterpret_cast<R *>(smem + LL.tile);
     unsigned long long *pairs = reinterpret_cast<unsigned long long *>(smem + LL.tile);
     v4u *stage = reinterpret_cast<v4u *>(smem + LL.stage);
@@ -322,7 +322,7 @@ __global__ __launch_bounds__(spread_max_threads(sizeof(R), M2)) void k_spread(co
         const int nz = g.zs * g.nrows * P;
         for (int i = tid; i < nz; i += nthr) {
             int z = i / (g.nrows * P), rem = i - z * g.nrows * P;
-            const size_t o = (size_t)z * plane + (size_t)(g.ry0 + rem / P) * pitch + rem % P;
+            const int o = z * plane + (g.ry0 + rem / P) * pitch + rem % P;
             if (COMP) {
                 pairs[o] = 0ull;
                 pairs[o + im_off] = 0ull;
@@ -387,9 +387,9 @@ __global__ __launch_bounds__(spread_max_threads(sizeof(R), M2)) void k_spread(co
                 // (dx = xm - j) when xm >= j, else lx + xm + 8.
                 const int dy = active ? row / (BW > 1 ? BW : M2) : 0;
                 const int xm = active ? row % (BW > 1 ? BW : M2) : 0;
-                size_t lrow[NW];
+                int lrow[NW];
                 bool row_ok[NW];
-                lrow[0] = (size_t)(ly + dy) * pitch + (lx + xm);
+                lrow[0] = (ly + dy) * pitch + (lx + xm);
                 row_ok[0] = active;
                 if constexpr (NW > 1) {
                     lrow[1] = lrow[0] + BW;
@@ -405,7 +405,7 @@ __global__ __launch_bounds__(spread_max_threads(sizeof(R), M2)) void k_spread(co
 
                 // add slot s (plane q) of the lane's rows into the LDS tile
                 auto flush = [&](int s, int q) __attribute__((always_inline)) {
-                    const size_t o = (size_t)(q + qshift) * plane;
+                    const int o = (q + qshift) * plane;
 #pragma unroll
                     for (int w = 0; w < NW; ++w) {
                         if (row_ok[w]) {
@@ -489,7 +489,7 @@ __global__ __launch_bounds__(spread_max_threads(sizeof(R), M2)) void k_spread(co
         for (int i = tid; i < nz; i += nthr) {
             int z = i / (g.nrows * P), rem = i - z * g.nrows * P;
             int y = g.ry0 + rem / P, xx = rem % P;
-            const size_t o = (size_t)z * plane + (size_t)y * pitch + xx;
+            const int o = z * plane + y * pitch + xx;
             R vr, vi;
             if (COMP) {
                 unsigned long long a0 = pairs[o], a1 = pairs[o + im_off];
@@ -555,7 +555,7 @@ __global__ __launch_bounds__(interp_max_threads(sizeof(R), M2, GRAD)) void k_int
             int y = g.ry0 + rem / P, xx = rem % P;
             int gy = wrapn(g.Y0 + y - m + 1, g.n1), gx = wrapn(g.X0 + xx - m + 1, g.n2);
             size_t gi = (((size_t)(g.z0 + z) * g.n1 + gy) * g.n2 + gx) * 2;
-            size_t o = ((size_t)z * plane + (size_t)y * P + xx) * 2;
+            const int o = (z * plane + y * P + xx) * 2;
             tile[o] = grid[gi];
             tile[o + 1] = grid[gi + 1];
         }
@@ -618,9 +618,9 @@ __global__ __launch_bounds__(interp_max_threads(sizeof(R), M2, GRAD)) void k_int
                         // tile rows of this lane (as in the spread)
                         const int dy = active ? row / (BW > 1 ? BW : M2) : 0;
                         const int xm = active ? row % (BW > 1 ? BW : M2) : 0;
-                        size_t lrow[NW];
+                        int lrow[NW];
                         bool row_ok[NW];
-                        lrow[0] = (size_t)(ly + dy) * P + (lx + xm);
+                        lrow[0] = (ly + dy) * P + (lx + xm);
                         row_ok[0] = active;
                         if constexpr (NW > 1) {
                             lrow[1] = lrow[0] + BW;
@@ -643,7 +643,7 @@ __global__ __launch_bounds__(interp_max_threads(sizeof(R), M2, GRAD)) void k_int
 #pragma unroll
                             for (int w = 0; w < NW; ++w) {
                                 if (row_ok[w] && (unsigned)qr < (unsigned)g.zs) {
-                                    const size_t o = ((size_t)qr * plane + lrow[w]) * 2;
+                                    const int o = (qr * plane + lrow[w]) * 2;
                                     gr[w][s] = tile[o];
                                     gi[w][s] = tile[o + 1];
                                 } else {
