@@ -2,29 +2,35 @@
 // (the Interpolating step of Algorithm 5) on gfx950.
 //
 // The paper assigns one thread per point and adds every window tap to the
-// grid with an atomic operation.  Here points are sorted by z-line (fixed
-// cells in dims 1 and 2, increasing cell along dim 0), and a work item is a
-// tile of T x T lines restricted to a slab of Zs planes along dim 0.
+// grid with an atomic operation.  Here points are sorted into runs: a z-line
+// (fixed cells in dims 1 and 2) or, for 2m = 8, a block of 8 z-lines adjacent
+// along dim 2, each run ordered by plane along dim 0.  A work item is a tile
+// of T x T z-lines restricted to a slab of Zs planes along dim 0.
 //
 // Per work item a workgroup
-//   1. lists the item's runs: for every line up to three contiguous ranges of
+//   1. lists the item's runs: for every run up to three contiguous ranges of
 //      sorted points (the periodic images whose taps reach the slab), and
 //      numbers their points 0 .. S-1 in run order;
 //   2. for each chunk of `cap` of those points, copies the points' records
 //      (window weights, value, plane index) into LDS with all threads at once
-//      (coalesced 16-byte copies, many loads in flight);
-//   3. sweeps the chunk: one wavefront per (run piece, row group); lane <->
-//      one (dy, dx) tap row of the point's (2m)^2 rows, and along dim 0 a
-//      register window of 2m complex values, slot s holding plane q with
-//      q = s (mod 2m).  Consecutive points of a line share the lane's row, so
-//      their taps accumulate in registers; a plane leaves the window (spread:
-//      one LDS add per row) only when the sweep has passed it.  Weights along
-//      dim 0 are stored pre-rotated per point, so slot indices are constants;
+//      (coalesced 16-byte copies; the next chunk loads into registers while
+//      the current one is swept);
+//   3. sweeps the chunk, one wavefront per task (a run, or for blocks an
+//      equal range of the chunk's points).  Lane <-> one (dy, dx) tap row of
+//      a line's (2m)^2 rows; in a block, lane (dy, xm) owns the tile columns
+//      x0 + xm and x0 + xm + 8 of tap row dy, which between them receive
+//      every tap of row dy from all 8 lines.  Along dim 0 each owned row has
+//      a register window of 2m complex values, slot s holding plane q with
+//      q = s (mod 2m).  The sweep is plane-major: the plane loop is unrolled
+//      2m times, so a plane's slot is a compile-time constant; the points
+//      whose window starts at plane p are added, then plane p leaves the
+//      window (spread: one LDS add per owned row).  Weights along dim 0 are
+//      stored pre-rotated per point to slot order;
 //   4. flushes the LDS tile (the slab's planes with a halo of 2m-1 cells in
 //      dims 1 and 2) to the grid with one atomic add per cell.
 // Interpolation loads the tile from the grid, slides the same register
 // window (loading a plane when it enters) and reduces the (2m)^2 row partials
-// of each point across the wavefront with DPP moves.
+// of each point across the wavefront with swap/DPP halving steps.
 //
 // Work items come from a device queue (one atomic per item) so heavy tiles
 // and uneven batches balance across the compute units.
