@@ -254,3 +254,32 @@ def test_c3_clustered_precision(H, oracle_mod):
     e64 = oracle_mod.rel_l2(got64.reshape(-1)[kidx], ref64)
     print("C3 fp32 vs fp64 (all I_N) %.3e; fp32 vs oracle %.3e; fp64(m=4) vs oracle %.3e" % (e_32_64, e32, e64))
     assert e_32_64 <= 1e-5 and e32 <= 1e-5 and e64 <= tol(4, "f64")
+
+
+@pytest.mark.parametrize("prec,tiles", [("f32", (16, 8, 1024)), ("f32", (8, 4, 512)), ("f64", (16, 12, 512)),
+                                        ("f32", (24, 4, 1024))])
+def test_blocked_runs_tilings(H, oracle_mod, prec, tiles):
+    """2m = 8 sorts points in blocks of 8 z-lines: tiles with one, two and
+    three blocks per row, shallow and deep slabs, a ragged grid (n = 48 x 36 x
+    64: dim 1 is not a multiple of the tile edge) and uneven point density;
+    adjoint and forward against the oracle on sampled outputs."""
+    g = W.rng(611)
+    N = (24, 18, 32)
+    x = W.clustered_points(4500, 3, 500, 0.03, 3, g)
+    M = x.shape[0]
+    f = W.complex_normal(M, g)
+    # m = 4: the window's own truncation error is ~1e-7 (bound 1.2e-6, the
+    # Kaiser-Bessel estimate at sigma = 2); float32 adds rounding up to 1e-5
+    tol = 1.2e-6 if prec == "f64" else 1e-5
+    got, plan = run_adjoint(H, N, x, f, 4, prec, tiles=tiles)
+    assert plan.tiles == tiles
+    kidx = W.sample_indices(int(np.prod(N)), 512, g)
+    ref = oracle_mod.ndft_adjoint(N, x, f_used(f, prec), kidx=kidx)
+    err = oracle_mod.rel_l2(got.reshape(-1)[kidx], ref)
+    fh = W.complex_normal(int(np.prod(N)), g).reshape(N)
+    back, _ = run_forward(H, N, x, fh, 4, prec, tiles=tiles)
+    jidx = W.sample_indices(M, 512, g)
+    ref_f = oracle_mod.ndft_forward(N, x, f_used(fh, prec), jidx=jidx)
+    err_f = oracle_mod.rel_l2(back[jidx], ref_f)
+    print("blocked %s tiles=%s adjoint %.3e forward %.3e" % (prec, tiles, err, err_f))
+    assert err <= tol and err_f <= tol
