@@ -63,9 +63,13 @@ __global__ void k_bin_count(const XT *__restrict__ x, long long M, int n0, int n
     int c[3];
     for (int t = 0; t < 3; ++t) {
         double u;
-        const double xv = (double)x[j * 3 + t];
-        if (xs_out) xs_out[j * 3 + t] = xv;
-        c[t] = cell_of(xv, n[t], &u, &bad);
+        c[t] = cell_of((double)x[j * 3 + t], n[t], &u, &bad);
+    }
+    // the copy runs over the flat array (words j, j + M, j + 2M), so every
+    // store instruction writes one contiguous span
+    if (xs_out) {
+#pragma unroll
+        for (int t = 0; t < 3; ++t) xs_out[j + t * M] = (double)x[j + t * M];
     }
     if (bad) atomicOr(err, 1);
     rank[j] = atomicAdd(&counts[sort_key(c, T, ntx, n0, BW)], 1);
