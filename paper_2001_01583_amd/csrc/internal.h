@@ -87,12 +87,9 @@ constexpr size_t kLdsLimit = 160 * 1024 - 512;
 // Row pitch (cells) of the spread's LDS tile.  The tile stores real and
 // imaginary parts as separate arrays of 8-byte cells (a float32 (sum,
 // compensation) pair, or a float64), so the lanes of one tap row touch
-// consecutive cells; for 2m <= 8 the pitch is padded to 8 (mod 16) cells so
-// that consecutive rows fall on disjoint LDS banks.
-__host__ __device__ constexpr int spread_pitch(int T, int M2)
-{
-    return M2 <= 8 ? ((T + M2 - 1 + 7) / 16) * 16 + 8 : T + M2 - 1;
-}
+// consecutive cells.  Rows are not padded: padding them onto disjoint LDS
+// banks was measured slower (it costs LDS that the staged points need).
+__host__ __device__ constexpr int spread_pitch(int T, int M2) { return T + M2 - 1; }
 struct LdsLayout {
     size_t tile, stage, slot_p, run_p0, run_soff, sh, out, total;
     int cap;
