@@ -277,6 +277,158 @@ def cpu_baseline(data, gpu):
     return base, errs
 
 
+# ---------------------------------------------------------------------------
+# Secondary workloads (--workload c3 | c4 | c5): one JSON line each, same keys.
+def _time(torch, fn, steps, warmup):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def bench_c3(H, torch, W, args):
+    """Precision workload: N = 128^3, M = 2^23 (half uniform, half in 64
+    Gaussian clusters), m = 4; step = set_points + adjoint.  float32 against
+    the float64 GPU path over all of I_N, and both against the oracle on
+    sampled frequencies."""
+    import numpy as np
+
+    import oracle
+    data = W.c3()
+    N, x_np, f_np = data["N"], data["x"], data["f"]
+    Mp = x_np.shape[0]
+    dev = torch.device("cuda", 0)
+    x = torch.from_numpy(x_np).to(dev)
+    res = {}
+    for prec in ("f32", "f64"):
+        cd = torch.complex64 if prec == "f32" else torch.complex128
+        plan = H.Plan(N, Mp, m=4, precision=prec, device=dev)
+        f = torch.from_numpy(f_np).to(dev).to(cd)
+        out = torch.empty(N, dtype=cd, device=dev)
+
+        def step():
+            plan.set_points(x)
+            plan.adjoint(f, out=out)
+        t = _time(torch, step, args.steps, args.warmup)
+        plan.profile(True)
+        step()
+        torch.cuda.synchronize()
+        ph = {k: v[0] / max(v[1], 1) for k, v in plan.profile_read().items()}
+        plan.profile(False)
+        res[prec] = dict(ms=t * 1e3, out=out.cpu().numpy().astype(np.complex128), phases=ph, tiles=plan.tiles)
+        del plan
+        torch.cuda.empty_cache()
+    g = W.rng(98)
+    kidx = W.sample_indices(int(np.prod(N)), 64, g)
+    ref = oracle.ndft_adjoint(N, x_np, f_np.astype(np.complex64).astype(np.complex128), kidx=kidx)
+    ref64 = oracle.ndft_adjoint(N, x_np, f_np, kidx=kidx)
+    e32 = oracle.rel_l2(res["f32"]["out"].reshape(-1)[kidx], ref)
+    e64 = oracle.rel_l2(res["f64"]["out"].reshape(-1)[kidx], ref64)
+    e32_64 = oracle.rel_l2(res["f32"]["out"].reshape(-1), res["f64"]["out"].reshape(-1))
+    r32 = res["f32"]
+    sp_ms = r32["phases"].get("spread", 0.0)
+    return {
+        "metric": METRIC, "value": round(Mp / (r32["ms"] * 1e-3), 1), "unit": "points/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(r32["ms"], 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "precision: NFFT N=128^3 (n=256^3), M=2^23 (half uniform, half in 64 Gaussian "
+                               "clusters, std 0.02), complex64, Kaiser-Bessel m=4; step = set_points + adjoint",
+                   "N": list(N), "M": Mp, "m": 4, "tiles": list(r32["tiles"])},
+        "fp64_m4_ms_per_step": round(res["f64"]["ms"], 4),
+        "fp32_speedup_over_fp64": round(res["f64"]["ms"] / r32["ms"], 3),
+        "rel_l2_f32_vs_f64_gpu_all_IN": float("%.3e" % e32_64),
+        "rel_l2_vs_oracle_sampled": {"f32": float("%.3e" % e32), "f64": float("%.3e" % e64), "k": 64},
+        "phases_f32_ms": {k: round(v, 4) for k, v in r32["phases"].items()},
+    }
+
+
+def bench_c4(H, torch, W, args):
+    """Batching workload: 256 independent adjoints (M log-uniform in
+    [1e3, 1e6], N in {32, 48, 64, 96}^3), float32, m = 4, one launch per
+    phase; the adjoint captured in a HIP graph and replayed."""
+    import numpy as np
+    elems = W.c4(256)
+    dev = torch.device("cuda", 0)
+    x = torch.from_numpy(np.concatenate([e["x"] for e in elems])).to(dev)
+    f = torch.from_numpy(np.concatenate([e["f"] for e in elems]).astype(np.complex64)).to(dev)
+    Ms = [e["x"].shape[0] for e in elems]
+    stream = torch.cuda.Stream(device=dev)
+    with torch.cuda.stream(stream):
+        plan = H.Plan([e["N"] for e in elems], Ms, m=4, precision="f32", device=dev)
+        plan.set_points(x)
+        t_tune = time.perf_counter()
+        plan.autotune()  # bin sizes (tile, slab, threads) chosen on these points
+        t_tune = time.perf_counter() - t_tune
+        t_sp = _time(torch, lambda: plan.set_points(x), max(2, args.steps // 4), 1)
+        out = plan.adjoint(f)
+        t_eager = _time(torch, lambda: plan.adjoint(f, out=out), args.steps, args.warmup)
+        plan.profile(True)
+        plan.adjoint(f, out=out)
+        torch.cuda.synchronize()
+        phases = {k: round(v[0] / max(v[1], 1), 4) for k, v in plan.profile_read().items()}
+        plan.profile(False)
+        gout = torch.empty_like(out)
+        plan.capture(f, gout)
+        t_graph = _time(torch, plan.replay, args.steps, args.warmup)
+        diff = (gout - out).abs().max().item() / max(out.abs().max().item(), 1e-30)
+    Mt = int(sum(Ms))
+    return {
+        "metric": METRIC, "value": round(Mt / t_graph, 1), "unit": "points/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(t_graph * 1e3, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "batching: 256 adjoint NFFTs, M log-uniform in [1e3, 1e6], N in {32,48,64,96}^3, "
+                               "complex64, m=4, autotuned tiling; step = one graph-replayed batched adjoint (points already set)",
+                   "B": 256, "M_total": Mt, "tiles": list(plan.tiles)},
+        "eager_ms_per_step": round(t_eager * 1e3, 4), "set_points_ms": round(t_sp * 1e3, 4),
+        "autotune_s": round(t_tune, 2),
+        "graph_vs_eager_max_rel_diff": float("%.3e" % diff), "phases_ms": phases,
+    }
+
+
+def bench_c5(H, torch, W, args):
+    """Differentiation workload: reciprocal Ewald energy and forces of a
+    fluorite lattice of 24^3 cells (165,888 ions, displacements std 0.01 r0),
+    N = 128^3; step = set_points + adjoint (S) + energy/gbar + backward."""
+    import numpy as np
+    from paper_2001_01583_amd import ewald as E
+    r_np, q_np, L_box = W.fluorite(24, 0.01, seed=5)
+    dev = torch.device("cuda", 0)
+    r = torch.from_numpy(r_np).to(dev)
+    q = torch.from_numpy(q_np).to(dev)
+    lo, hi = E.alpha_window(L_box, 128)
+    alpha = 0.5 * (lo + hi)
+    out = {}
+    for prec, m in (("f64", 8), ("f32", 4)):
+        ew = E.Ewald(r.shape[0], L_box, alpha, N=(128, 128, 128), m=m, precision=prec, device=dev)
+        t = _time(torch, lambda: ew.reciprocal(r, q, forces=True), args.steps, args.warmup)
+        ew.plan.profile(True)
+        U, F = ew.reciprocal(r, q, forces=True)
+        torch.cuda.synchronize()
+        ph = {k: round(v[0] / max(v[1], 1), 4) for k, v in ew.plan.profile_read().items()}
+        ew.plan.profile(False)
+        out[prec] = dict(ms=t * 1e3, U=float(U), F=F.cpu().numpy(), phases=ph)
+        del ew
+        torch.cuda.empty_cache()
+    fdiff = np.abs(out["f32"]["F"] - out["f64"]["F"]).max() / np.abs(out["f64"]["F"]).max()
+    nion = int(r.shape[0])
+    return {
+        "metric": METRIC, "value": round(nion / (out["f64"]["ms"] * 1e-3), 1), "unit": "ions/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(out["f64"]["ms"], 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "Ewald reciprocal energy + forces, fluorite 24^3 cells (165,888 ions, "
+                               "displacement std 0.01 r0), N=128^3, float64 m=8 (float32 m=4 beside); step = "
+                               "set_points + adjoint + Eq. (12) energy + backward (forces)",
+                   "ions": nion, "N": [128, 128, 128], "alpha": round(alpha, 6), "L_box": round(L_box, 6)},
+        "fp32_m4_ms_per_step": round(out["f32"]["ms"], 4),
+        "energy_f64": out["f64"]["U"], "energy_f32": out["f32"]["U"],
+        "forces_f32_vs_f64_max_rel": float("%.3e" % fdiff), "phases_f64_ms": out["f64"]["phases"],
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -289,6 +441,9 @@ def main():
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write profiles/traffic_c2.json from two rocprofv3 --pmc output folders")
     ap.add_argument("--counters-command", default="", help="command line recorded with the summary")
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5"],
+                    help="c2 (default): N=64^3, M=2^20, set_points+adjoint+forward; c3: precision N=128^3, "
+                         "M=2^23; c4: 256-transform batch; c5: Ewald forces, 165,888 ions")
     args = ap.parse_args()
     if args.summarize_counters:
         summarize_counters(args.summarize_counters[0], args.summarize_counters[1],
@@ -309,6 +464,10 @@ def main():
     if not torch.cuda.is_available():
         log("no GPU visible")
         sys.exit(1)
+    if args.workload != "c2":
+        fn = {"c3": bench_c3, "c4": bench_c4, "c5": bench_c5}[args.workload]
+        print(json.dumps(fn(H, torch, W, args)), flush=True)
+        return
     data = W.c2()
     log("workload ready: N=%s M=%d" % (N, M))
     if args.copy_calib:

@@ -276,8 +276,9 @@ class Plan:
         # grow the workspace to fit every candidate (sizes depend on tiling)
         need = self.ws_bytes
         keep = self.tiles
-        for T in (8, 12, 16, 24, 32):
-            for Zs in (8, 16, 32):
+        # the candidate set of hpnfft_autotune
+        for T in (4, 6, 8, 12, 16):
+            for Zs in (8, 16, 24, 32):
                 for th in (512, 1024):
                     if lib.hpnfft_set_tiles(self._h, T, Zs, th) == OK:
                         sz = ctypes.c_size_t()
