@@ -47,6 +47,7 @@ struct Tiling {
     int T;        // tile edge (cells) in dims 2 and 1
     int Zs;       // slab depth (planes) along dim 0
     int threads;  // threads per workgroup of spread / interp
+    int cap_hint = 0;  // points per staging chunk worth reserving (0: as many as fit)
 };
 
 __host__ __device__ constexpr size_t align16(size_t v) { return (v + 15) & ~(size_t)15; }

@@ -814,6 +814,21 @@ static int cu_count()
     return cus;
 }
 
+// Sparse point sets: when the work items hold few points (cap_hint, from
+// the binning), a staging area sized for them leaves LDS for a second
+// workgroup on the compute unit; workgroups then take half the threads, so
+// two independent items (each with its own barriers) share the unit.
+static void shrink_for_sparse(LdsLayout &LL, const Tiling &t, int M2, size_t R, int kind, bool comp, int &threads)
+{
+    if (t.cap_hint <= 0 || t.cap_hint >= LL.cap) return;
+    const int cap = std::max(64, ((t.cap_hint + 63) / 64) * 64);
+    if (cap >= LL.cap) return;
+    const LdsLayout small = lds_layout(t.T, t.Zs, M2, R, kind, comp, cap);
+    if (2 * (small.total + 1024) > 160 * 1024) return;  // still one workgroup per unit
+    LL = small;
+    threads = std::max(64, std::min(threads, 512));
+}
+
 template <typename R, int M2>
 static hipError_t spread_m(const Xform *dxf, const SItem *items, int nitems, int *queue, Tiling t,
                            const unsigned char *rec, size_t rec_bytes, const int *cs, hipStream_t s)
@@ -821,6 +836,8 @@ static hipError_t spread_m(const Xform *dxf, const SItem *items, int nitems, int
     constexpr bool COMP = sizeof(R) == 4;
     LdsLayout LL = lds_fit(t.T, t.Zs, M2, sizeof(R), 0, COMP);
     if (!LL.cap) return hipErrorInvalidValue;
+    int threads = std::min(t.threads, spread_max_threads(sizeof(R), M2));
+    shrink_for_sparse(LL, t, M2, sizeof(R), 0, COMP, threads);
     auto kern = k_spread<R, M2, COMP>;
     hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)LL.total);
@@ -829,7 +846,6 @@ static hipError_t spread_m(const Xform *dxf, const SItem *items, int nitems, int
     if (per_cu < 1) per_cu = 1;
     int grid = std::min(cu_count() * per_cu, nitems);
     if (grid < 1) return hipSuccess;
-    int threads = std::min(t.threads, spread_max_threads(sizeof(R), M2));
     hipLaunchKernelGGL(kern, dim3(grid), dim3(threads), LL.total, s, dxf, items, nitems, queue, t.T, t.Zs,
                        LL.cap, (const v4u *)rec, (int)(rec_bytes / 16), cs);
     return hipGetLastError();
@@ -841,6 +857,8 @@ static hipError_t interp_m(const Xform *dxf, const SItem *items, int nitems, int
 {
     LdsLayout LL = lds_fit(t.T, t.Zs, M2, sizeof(R), GRAD ? 2 : 1, false);
     if (!LL.cap) return hipErrorInvalidValue;
+    int threads = std::min(t.threads, interp_max_threads(sizeof(R), M2, GRAD));
+    shrink_for_sparse(LL, t, M2, sizeof(R), GRAD ? 2 : 1, false, threads);
     auto kern = k_interp<R, M2, GRAD>;
     hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)LL.total);
@@ -849,7 +867,6 @@ static hipError_t interp_m(const Xform *dxf, const SItem *items, int nitems, int
     if (per_cu < 1) per_cu = 1;
     int grid = std::min(cu_count() * per_cu, nitems);
     if (grid < 1) return hipSuccess;
-    int threads = std::min(t.threads, interp_max_threads(sizeof(R), M2, GRAD));
     hipLaunchKernelGGL(kern, dim3(grid), dim3(threads), LL.total, s, dxf, items, nitems, queue, t.T, t.Zs,
                        LL.cap, (const v4u *)rec, (int)(rec_bytes / 16), cs, outs);
     return hipGetLastError();

@@ -459,12 +459,17 @@ int bin_points(hpnfft_plan_s *p, const double *x = nullptr, const float *x32 = n
         HCHECK(launch_make_items(p->at<int>(L.tcost_off[b]), b, X, p->til.T, p->m, total, cap_div, kMinCap,
                                  L.max_items, p->at<SItem>(L.items), setp + 1, setp + 2, s));
     }
-    int host[4] = {0, 0, 0, 0};
+    int host[6] = {0, 0, 0, 0, 0, 0};  // err, nitems, overflow, pad, total cost (u64)
     HCHECK(hipMemcpyAsync(host, setp, sizeof(host), hipMemcpyDeviceToHost, s));
     HCHECK(hipStreamSynchronize(s));
     if (host[0]) return HPNFFT_EDOMAIN;
     if (host[2]) return HPNFFT_ENOMEM;
     p->nitems = std::min(host[1], L.max_items);
+    // staging worth reserving per chunk: twice the mean points per item
+    unsigned long long tot = 0;
+    std::memcpy(&tot, host + 4, sizeof(tot));
+    const long long mean = p->nitems > 0 ? (long long)(tot / (unsigned long long)p->nitems) : 0;
+    p->til.cap_hint = (int)std::min<long long>(2 * mean + 64, 1 << 20);
     return HPNFFT_OK;
 }
 
