@@ -87,10 +87,11 @@ int hpnfft_plan_destroy(hpnfft_plan plan);
 int hpnfft_set_stream(hpnfft_plan plan, void *hip_stream);
 
 /* Spread/interpolation tiling: tile edge in the two fastest grid dimensions
- * (cells), slab depth along the slowest dimension (cells) and threads per
- * workgroup (multiple of 64, <= 1024).  Pass 0 to keep a value.  Must be
- * called before hpnfft_set_workspace.  EINVAL if the tile does not fit the
- * 160 KiB local data share. */
+ * (cells, 4..32), slab depth along the slowest dimension (cells, 2..64) and
+ * threads per workgroup (multiple of 64, <= 1024).  Pass 0 to keep a value.
+ * Must be called before hpnfft_set_workspace.  EINVAL if the tile does not
+ * fit the 160 KiB local data share, or if 2m = 8 and the tile edge is not a
+ * multiple of 8 (those plans sort points in blocks of 8 lines). */
 int hpnfft_set_tiles(hpnfft_plan plan, int tile, int slab, int threads);
 int hpnfft_get_tiles(hpnfft_plan plan, int *tile, int *slab, int *threads);
 

@@ -128,13 +128,12 @@ inline LdsLayout lds_fit(int T, int Zs, int M2, size_t R, int kind, bool comp)
     return lds_layout(T, Zs, M2, R, kind, comp, cap);
 }
 
-// Threads per workgroup the interpolation kernel is compiled for: float64
-// windows of 2m >= 12 (and the gradient variant from 2m >= 6) need more than
-// the 128 registers a 1024-thread workgroup leaves per lane.
-__host__ __device__ constexpr int spread_max_threads(int real_bytes, int M2)
-{
-    return 1024;
-}
+// Threads per workgroup the sweep kernels are compiled for.  A 1024-thread
+// workgroup leaves 128 registers per lane.  The spread fits (float64 with a
+// few spills, measured faster than 512 threads); the interpolation variants
+// that hold more window values per lane (the gradient, float64 blocked
+// lines) are compiled for 512.
+__host__ __device__ constexpr int spread_max_threads(int, int) { return 1024; }
 __host__ __device__ constexpr int interp_max_threads(int real_bytes, int M2, bool grad)
 {
     return (grad && (real_bytes == 8 || M2 >= 12)) || (real_bytes == 8 && block_w(M2) > 1) ? 512 : 1024;
