@@ -82,7 +82,8 @@ constexpr int kPolyMax = 17;
 // LDS layout of the spread / interpolation kernels (bytes from the start of
 // the dynamic LDS block).  kind: 0 spread, 1 interpolation, 2 gradient.
 //   [tile][stage: cap records][slot maps: 2 x cap ints][run_p0: 3T^2][run_soff: 3T^2+1]
-//   [scan scratch: 32 ints][interpolation outputs: cap x 2 NO reals]
+//   [scan scratch: 32 ints][a 16-byte cell that is never changed]
+//   [interpolation outputs: cap x 2 NO reals]
 constexpr size_t kLdsLimit = 160 * 1024 - 512;
 
 // Row pitch (cells) of the spread's LDS tile.  The tile stores real and
@@ -109,7 +110,7 @@ __host__ __device__ inline LdsLayout lds_layout(int T, int Zs, int M2, size_t R,
     L.run_p0 = L.slot_p + (size_t)cap * 8;
     L.run_soff = L.run_p0 + nr * 4;
     L.sh = align16(L.run_soff + (nr + 1) * 4);
-    L.out = L.sh + 32 * 4;
+    L.out = L.sh + 36 * 4;
     L.total = align16(L.out + (kind ? (size_t)cap * 2 * NO * R : 0));
     L.cap = cap;
     return L;

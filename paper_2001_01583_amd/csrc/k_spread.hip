@@ -59,13 +59,17 @@ __device__ inline void seg_range(int U, int z0, int zs, int m, int n0, int *a, i
     *b = hi > n0 - 1 ? n0 - 1 : hi;
 }
 
-// Compensated float adds into two LDS cells (the real and imaginary part of
-// one grid value, kept in separate arrays), each holding (sum,
-// compensation) as one 64-bit word:
-// TwoSum (Knuth) of the stored sum and v gives the new sum and its exact
-// rounding error, which joins the compensation; each pair is published with
-// a 64-bit compare-and-swap.  Both parts are in flight together.  The
-// initial read is only a guess (a stale or torn value just fails the CAS).
+// Compensated float adds into K LDS cells at once (the real and imaginary
+// parts of the lane's tile values, kept in separate arrays), each cell holding
+// (sum, compensation) as one 64-bit word: TwoSum (Knuth) of the stored sum and
+// v gives the new sum and its exact rounding error, which joins the
+// compensation; each pair is published with a 64-bit compare-and-swap.  The K
+// reads, then the K swaps are issued back to back, so a retire costs two LDS
+// round trips whatever K is.  The initial read is only a guess: a swap that
+// finds another value (a wavefront of the same workgroup added to the cell in
+// between) is retried from the value it found.  A lane with nothing to add
+// for cell k passes ok[k] = false and c[k] = a cell that nobody changes: it
+// swaps that cell's value with itself.
 // (gfx950's native LDS float32 atomic add is about 13x slower than this.)
 __device__ __forceinline__ unsigned long long twosum_pair(unsigned long long old, float v)
 {
@@ -77,23 +81,33 @@ __device__ __forceinline__ unsigned long long twosum_pair(unsigned long long old
     return (unsigned long long)__float_as_uint(t) | ((unsigned long long)__float_as_uint(cp + e) << 32);
 }
 
-__device__ __forceinline__ void lds_add_comp2(unsigned long long *cre, unsigned long long *cim, float vr,
-                                              float vi)
+template <int K>
+__device__ __forceinline__ void lds_add_comp(unsigned long long *const (&c)[K], const float (&v)[K],
+                                             const bool (&ok)[K])
 {
-    unsigned long long o0 = *cre, o1 = *cim;
-    bool d0 = false, d1 = false;
-    do {
-        if (!d0) {
-            const unsigned long long pr = atomicCAS(cre, o0, twosum_pair(o0, vr));
-            d0 = pr == o0;
-            o0 = pr;
+    unsigned long long o[K], pr[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) o[k] = *c[k];
+    unsigned long long nw[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) nw[k] = ok[k] ? twosum_pair(o[k], v[k]) : o[k];
+    // keep the K swaps together: they then share one wait
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int k = 0; k < K; ++k) pr[k] = atomicCAS(c[k], o[k], nw[k]);
+    __builtin_amdgcn_sched_barrier(0);
+    bool miss = false;
+#pragma unroll
+    for (int k = 0; k < K; ++k) miss |= pr[k] != o[k];
+    if (__builtin_expect(__any(miss), 0)) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            while (pr[k] != o[k]) {
+                o[k] = pr[k];
+                pr[k] = atomicCAS(c[k], o[k], ok[k] ? twosum_pair(o[k], v[k]) : o[k]);
+            }
         }
-        if (!d1) {
-            const unsigned long long pr = atomicCAS(cim, o1, twosum_pair(o1, vi));
-            d1 = pr == o1;
-            o1 = pr;
-        }
-    } while (!(d0 && d1));
+    }
 }
 
 // Exclusive scan of one int per thread over the workgroup (<= 1024 threads);
@@ -237,6 +251,12 @@ __device__ inline int plane_of(const v4u *stage, int sl, int st16, int off_pz, i
     return uni(reinterpret_cast<const int *>(stage + sl * st16)[off_pz]) + m + 1;
 }
 
+// Plane index and line offset of a staged point (one 8-byte read), raw.
+__device__ inline int2 head_of(const v4u *stage, int sl, int st16, int off_pz)
+{
+    return *reinterpret_cast<const int2 *>(reinterpret_cast<const int *>(stage + sl * st16) + off_pz);
+}
+
 // slot -> sorted point map of the chunk [cs, cs + cnt).  No barrier.
 __device__ inline void chunk_slots(int cs, int cnt, int nr, const int *run_p0, const int *run_soff, int *slot_p)
 {
@@ -297,7 +317,8 @@ __global__ __launch_bounds__(spread_max_threads(sizeof(R), M2)) void k_spread(co
     constexpr int ST16 = (int)(rec_prefix(M2, sizeof(R)) / 16);
     constexpr int OFF_F = (int)(rec_off_f(M2, sizeof(R)) / sizeof(R));
     constexpr int OFF_PZ = (int)(rec_off_pz(M2, sizeof(R)) / 4);
-    constexpr int OFF_XR = (int)(rec_off_xr(M2, sizeof(R)) / 4);
+    static_assert(rec_off_xr(M2, sizeof(R)) == rec_off_pz(M2, sizeof(R)) + 4 && rec_off_pz(M2, sizeof(R)) % 8 == 0,
+                  "head_of reads the plane index and line offset as one int2");
     constexpr int BW = block_w(M2);
     constexpr int NW = BW > 1 ? 2 : 1;  // tile rows per lane
     static_assert(BW == 1 || BW * BW == 64, "a blocked sweep maps (dy, xm) onto the 64 lanes");
@@ -319,6 +340,7 @@ __global__ __launch_bounds__(spread_max_threads(sizeof(R), M2)) void k_spread(co
     int *run_p0 = reinterpret_cast<int *>(smem + LL.run_p0);
     int *run_soff = reinterpret_cast<int *>(smem + LL.run_soff);
     int *sh = reinterpret_cast<int *>(smem + LL.sh);
+    unsigned long long *still = reinterpret_cast<unsigned long long *>(smem + LL.sh + 32 * 4);
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int wave = uni(tid >> 6), lane = tid & 63, nwaves = nthr >> 6;
     constexpr int PF = (sizeof(R) == 8 && M2 >= 12) ? 2 : 4;
@@ -362,12 +384,14 @@ __global__ __launch_bounds__(spread_max_threads(sizeof(R), M2)) void k_spread(co
                 chunk_fetch<PF>(cntn, slot_n, ST16, rec, rs16, reg);
             }
             // Tasks (times row groups): blocks of lines hold long runs, so
-            // their tasks are equal ranges of the chunk's points (about two
-            // per wavefront), each sweeping the run pieces it covers; single
+            // their tasks are equal ranges of the chunk's points (one per
+            // wavefront: a run cut into more pieces re-adds the 2m - 1 planes
+            // its window carries over each cut), each sweeping the run pieces
+            // it covers; single
             // lines hold short runs and take one run per task.
             const int r_lo = uni(find_run(run_soff, nr, cs));
             const int r_hi = uni(find_run(run_soff, nr, cs + cnt - 1));
-            const int piece = max(16, (cnt + 2 * nwaves - 1) / (2 * nwaves));
+            const int piece = max(16, (cnt + nwaves - 1) / nwaves);
             const int ntask = (BW > 1 ? (cnt + piece - 1) / piece : r_hi - r_lo + 1) * NRG;
             for (int task = wave; task < ntask; task += nwaves) {
               const int rg = task % NRG;
@@ -412,13 +436,23 @@ __global__ __launch_bounds__(spread_max_threads(sizeof(R), M2)) void k_spread(co
                 // add slot s (plane q) of the lane's rows into the LDS tile
                 auto flush = [&](int s, int q) __attribute__((always_inline)) {
                     const int o = (q + qshift) * plane;
+                    if constexpr (COMP) {
+                        unsigned long long *c[2 * NW];
+                        float v[2 * NW];
+                        bool ok[2 * NW];
 #pragma unroll
-                    for (int w = 0; w < NW; ++w) {
-                        if (row_ok[w]) {
-                            if (COMP) {
-                                lds_add_comp2(&pairs[o + lrow[w]], &pairs[o + lrow[w] + im_off], (float)wr[w][s],
-                                              (float)wi[w][s]);
-                            } else {
+                        for (int w = 0; w < NW; ++w) {
+                            c[2 * w] = row_ok[w] ? &pairs[o + lrow[w]] : still;
+                            c[2 * w + 1] = row_ok[w] ? &pairs[o + lrow[w] + im_off] : still;
+                            v[2 * w] = (float)wr[w][s];
+                            v[2 * w + 1] = (float)wi[w][s];
+                            ok[2 * w] = ok[2 * w + 1] = row_ok[w];
+                        }
+                        lds_add_comp<2 * NW>(c, v, ok);
+                    } else {
+#pragma unroll
+                        for (int w = 0; w < NW; ++w) {
+                            if (row_ok[w]) {
                                 atomicAdd(&acc[o + lrow[w]], wr[w][s]);
                                 atomicAdd(&acc[o + lrow[w] + im_off], wi[w][s]);
                             }
@@ -433,8 +467,10 @@ __global__ __launch_bounds__(spread_max_threads(sizeof(R), M2)) void k_spread(co
                 // is retired (after that, their slot is reused for p + 2m).
                 // Only planes f_lo .. f_lo + nf - 1 lie in the slab; the
                 // others are dropped.
-                const int B0 = plane_of(stage, a, ST16, OFF_PZ, m);
+                const int2 h0 = head_of(stage, a, ST16, OFF_PZ);
+                const int B0 = uni(h0.x) + m + 1;
                 const int Blast = plane_of(stage, b - 1, ST16, OFF_PZ, m);
+                int jn = uni(h0.y);
                 const int f_lo = max(B0, -qshift);
                 const int nf = max(min(Blast + M2 - 1, g.zs - 1 - qshift) - f_lo + 1, 0);
                 const int p_end = max(Blast, f_lo + nf - 1);
@@ -445,9 +481,11 @@ __global__ __launch_bounds__(spread_max_threads(sizeof(R), M2)) void k_spread(co
                     for (int k = 0; k < M2; ++k) {
                         while (Bn == p) {
                             const R *ps = reinterpret_cast<const R *>(stage + sl * ST16);
+                            // the next point's header loads while this one is added
+                            const int2 hx = head_of(stage, min(sl + 1, b - 1), ST16, OFF_PZ);
                             R sr[NW], si[NW];
                             if constexpr (NW > 1) {
-                                const int j = uni(reinterpret_cast<const int *>(ps)[OFF_XR]);
+                                const int j = jn;
                                 const bool hi = xm < j;
                                 const int dx = hi ? xm + BW - j : xm - j;
                                 const R w12 = ps[M2 + dy] * ps[2 * M2 + dx];
@@ -472,7 +510,8 @@ __global__ __launch_bounds__(spread_max_threads(sizeof(R), M2)) void k_spread(co
                             }
                             last = p;
                             ++sl;
-                            Bn = sl < b ? plane_of(stage, sl, ST16, OFF_PZ, m) : kNoPlane;
+                            Bn = sl < b ? uni(hx.x) + m + 1 : kNoPlane;
+                            jn = uni(hx.y);
                         }
                         if ((unsigned)(p - f_lo) < (unsigned)nf) flush(k, p);
 #pragma unroll
@@ -530,7 +569,8 @@ __global__ __launch_bounds__(interp_max_threads(sizeof(R), M2, GRAD)) void k_int
     constexpr int ST16 = (int)(rec_size(M2, sizeof(R), GRAD) / 16);
     constexpr int OFF_PZ = (int)(rec_off_pz(M2, sizeof(R)) / 4);
     constexpr int OFF_D = (int)(rec_prefix(M2, sizeof(R)) / sizeof(R));
-    constexpr int OFF_XR = (int)(rec_off_xr(M2, sizeof(R)) / 4);
+    static_assert(rec_off_xr(M2, sizeof(R)) == rec_off_pz(M2, sizeof(R)) + 4 && rec_off_pz(M2, sizeof(R)) % 8 == 0,
+                  "head_of reads the plane index and line offset as one int2");
     constexpr int BW = block_w(M2);
     constexpr int NW = BW > 1 ? 2 : 1;  // tile rows per lane
     extern __shared__ uint4 smem16[];
@@ -596,7 +636,7 @@ __global__ __launch_bounds__(interp_max_threads(sizeof(R), M2, GRAD)) void k_int
             // of each point, so every slot has exactly one writer.
             const int r_lo = uni(find_run(run_soff, nr, cs));
             const int r_hi = uni(find_run(run_soff, nr, cs + cnt - 1));
-            const int piece = max(16, (cnt + 2 * nwaves - 1) / (2 * nwaves));
+            const int piece = max(16, (cnt + nwaves - 1) / nwaves);
             const int ntask = BW > 1 ? (cnt + piece - 1) / piece : r_hi - r_lo + 1;
             for (int task = wave; task < ntask; task += nwaves) {
               int lo = cs, hi = cs + cnt, rf = r_lo + task;
@@ -688,7 +728,9 @@ __global__ __launch_bounds__(interp_max_threads(sizeof(R), M2, GRAD)) void k_int
                             }
                         };
                         int sl = c0;
-                        int Bn = plane_of(stage, c0, ST16, OFF_PZ, m);
+                        const int2 h0 = head_of(stage, c0, ST16, OFF_PZ);
+                        int Bn = uni(h0.x) + m + 1;
+                        int jn = uni(h0.y);
                         int p = Bn - Bn % M2;
 #pragma unroll
                         for (int s = 0; s < M2 - 1; ++s)
@@ -699,13 +741,14 @@ __global__ __launch_bounds__(interp_max_threads(sizeof(R), M2, GRAD)) void k_int
                                 if (Bn <= p + M2 - 1) load((k + M2 - 1) % M2, p + M2 - 1);
                                 while (Bn == p) {
                                     const R *ps = reinterpret_cast<const R *>(stage + sl * ST16);
+                                    const int2 hx = head_of(stage, min(sl + 1, c1 - 1), ST16, OFF_PZ);
                                     // the lane's row for this point: single
                                     // lines use row 0; in a block, row 1 when
                                     // the point's line lies right of column xm
                                     int dx = xm;
                                     bool hi = false;
                                     if constexpr (NW > 1) {
-                                        const int j = uni(reinterpret_cast<const int *>(ps)[OFF_XR]);
+                                        const int j = jn;
                                         hi = xm < j;
                                         dx = hi ? xm + BW - j : xm - j;
                                     }
@@ -758,7 +801,8 @@ __global__ __launch_bounds__(interp_max_threads(sizeof(R), M2, GRAD)) void k_int
                                     }
                                     feed(sl - c0, v);
                                     ++sl;
-                                    Bn = sl < c1 ? plane_of(stage, sl, ST16, OFF_PZ, m) : kNoPlane;
+                                    Bn = sl < c1 ? uni(hx.x) + m + 1 : kNoPlane;
+                                    jn = uni(hx.y);
                                 }
                                 ++p;
                             }
