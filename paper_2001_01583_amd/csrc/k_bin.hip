@@ -179,71 +179,134 @@ __global__ __launch_bounds__(256) void k_bin_scatter(const double *__restrict__ 
 }
 
 // ---------------------------------------------------------------------------
-// Exclusive prefix sum (in place) over int counts: per-block reduce, scan of
-// the block sums (recursively), then a per-block scan with the block offset.
+// Exclusive prefix sum (in place) over int counts, in blocks of 4096: a
+// reduce pass writes each block's total; the scan pass then scans each block
+// from the sum of the totals before it.  Up to kScanDirect blocks, each block
+// adds those totals itself (at most 32 loads per thread), so the scan is two
+// launches; longer arrays scan the totals recursively first.
 constexpr int kScanThreads = 256;
-constexpr int kScanPer = 16;
+constexpr int kScanPer = 16;                         // 4 int4 per thread
 constexpr int kScanBlock = kScanThreads * kScanPer;  // 4096 elements
+constexpr long long kScanDirect = 8192;
 
-__device__ inline int block_exclusive_scan(int v, int *sh, int *total)
+// Exclusive scan of one int per thread over the 256-thread block; *total =
+// the block's sum.  sh: 4 ints of LDS.
+__device__ inline int scan_block256(int v, int *sh, int *total)
 {
-    // Hillis-Steele over the block's 256 thread sums in LDS.
-    int tid = threadIdx.x;
-    sh[tid] = v;
-    __syncthreads();
-    for (int off = 1; off < kScanThreads; off <<= 1) {
-        int add = tid >= off ? sh[tid - off] : 0;
-        __syncthreads();
-        sh[tid] += add;
-        __syncthreads();
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
     }
-    int incl = sh[tid];
-    *total = sh[kScanThreads - 1];
+    if (lane == 63) sh[w] = x;
     __syncthreads();
-    return incl - v;
+    int pre = 0, tot = 0;
+#pragma unroll
+    for (int k = 0; k < kScanThreads / 64; ++k) {
+        const int t = sh[k];
+        pre += k < w ? t : 0;
+        tot += t;
+    }
+    __syncthreads();
+    *total = tot;
+    return pre + x - v;
 }
 
-__global__ void k_scan_reduce(const int *__restrict__ data, long long n, int *__restrict__ sums)
+__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const int *__restrict__ data, long long n,
+                                                              int *__restrict__ sums)
 {
-    __shared__ int sh[kScanThreads];
-    long long base = (long long)blockIdx.x * kScanBlock + (long long)threadIdx.x * kScanPer;
+    __shared__ int sh[kScanThreads / 64];
+    const int4 *d4 = reinterpret_cast<const int4 *>(data);
+    const long long n4 = n / 4;
     int s = 0;
-    for (int i = 0; i < kScanPer; ++i)
-        if (base + i < n) s += data[base + i];
+#pragma unroll
+    for (int k = 0; k < kScanPer / 4; ++k) {
+        const long long i4 = (long long)blockIdx.x * (kScanBlock / 4) + k * kScanThreads + threadIdx.x;
+        if (i4 < n4) {
+            const int4 v = d4[i4];
+            s += v.x + v.y + v.z + v.w;
+        } else if (i4 == n4) {
+            for (long long e = n4 * 4; e < n; ++e) s += data[e];
+        }
+    }
     int total;
-    block_exclusive_scan(s, sh, &total);
+    scan_block256(s, sh, &total);
     if (threadIdx.x == 0) sums[blockIdx.x] = total;
 }
 
-__global__ void k_scan_apply(int *__restrict__ data, long long n, const int *__restrict__ offs)
+// offs: block totals (direct: their prefix is summed here) or, when
+// !direct, already-scanned block offsets; null for a single block.
+__global__ __launch_bounds__(kScanThreads) void k_scan_apply(int *__restrict__ data, long long n,
+                                                             const int *__restrict__ offs, int direct)
 {
-    __shared__ int sh[kScanThreads];
-    long long base = (long long)blockIdx.x * kScanBlock + (long long)threadIdx.x * kScanPer;
-    int v[kScanPer];
-    int s = 0;
-    for (int i = 0; i < kScanPer; ++i) {
-        v[i] = base + i < n ? data[base + i] : 0;
-        s += v[i];
+    __shared__ int sh[kScanThreads / 64];
+    int base = 0;
+    if (offs) {
+        if (direct) {
+            int o = 0;
+            for (int i = threadIdx.x; i < (int)blockIdx.x; i += kScanThreads) o += offs[i];
+            scan_block256(o, sh, &base);
+        } else {
+            base = offs[blockIdx.x];
+        }
     }
+    const long long e0 = (long long)blockIdx.x * kScanBlock + (long long)threadIdx.x * kScanPer;
+    int v[kScanPer];
+    const bool full = e0 + kScanPer <= n;
+    if (full) {
+#pragma unroll
+        for (int k = 0; k < kScanPer / 4; ++k) {
+            const int4 q = reinterpret_cast<const int4 *>(data + e0)[k];
+            v[4 * k] = q.x;
+            v[4 * k + 1] = q.y;
+            v[4 * k + 2] = q.z;
+            v[4 * k + 3] = q.w;
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < kScanPer; ++i) v[i] = e0 + i < n ? data[e0 + i] : 0;
+    }
+    int s = 0;
+#pragma unroll
+    for (int i = 0; i < kScanPer; ++i) s += v[i];
     int total;
-    int run = block_exclusive_scan(s, sh, &total) + (offs ? offs[blockIdx.x] : 0);
+    int run = base + scan_block256(s, sh, &total);
+#pragma unroll
     for (int i = 0; i < kScanPer; ++i) {
-        if (base + i < n) data[base + i] = run;
-        run += v[i];
+        const int c = v[i];
+        v[i] = run;
+        run += c;
+    }
+    if (full) {
+#pragma unroll
+        for (int k = 0; k < kScanPer / 4; ++k)
+            reinterpret_cast<int4 *>(data + e0)[k] = make_int4(v[4 * k], v[4 * k + 1], v[4 * k + 2], v[4 * k + 3]);
+    } else {
+#pragma unroll
+        for (int i = 0; i < kScanPer; ++i)
+            if (e0 + i < n) data[e0 + i] = v[i];
     }
 }
 
+// data must be 16-byte aligned; tmp holds nb + nb / 2048 + 64 ints.
 hipError_t launch_scan(int *data, long long n, int *tmp, hipStream_t s)
 {
-    long long nb = (n + kScanBlock - 1) / kScanBlock;
+    if (n <= 0) return hipSuccess;
+    const long long nb = (n + kScanBlock - 1) / kScanBlock;
     if (nb <= 1) {
-        hipLaunchKernelGGL(k_scan_apply, dim3(1), dim3(kScanThreads), 0, s, data, n, (const int *)nullptr);
+        hipLaunchKernelGGL(k_scan_apply, dim3(1), dim3(kScanThreads), 0, s, data, n, (const int *)nullptr, 0);
         return hipGetLastError();
     }
     hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0, s, data, n, tmp);
-    hipError_t e = launch_scan(tmp, nb, tmp + nb, s);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(kScanThreads), 0, s, data, n, tmp);
+    const bool direct = nb <= kScanDirect;
+    if (!direct) {
+        hipError_t e = launch_scan(tmp, nb, tmp + nb, s);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(kScanThreads), 0, s, data, n, (const int *)tmp,
+                       direct ? 1 : 0);
     return hipGetLastError();
 }
 

@@ -283,3 +283,21 @@ def test_blocked_runs_tilings(H, oracle_mod, prec, tiles):
     err_f = oracle_mod.rel_l2(back[jidx], ref_f)
     print("blocked %s tiles=%s adjoint %.3e forward %.3e" % (prec, tiles, err, err_f))
     assert err <= tol and err_f <= tol
+
+
+def test_large_grid_key_table(H, oracle_mod):
+    """N = 256^3 (n = 512^3): the sort's cell table then has 2^27 entries,
+    more than the prefix scan adds up directly, so the block totals are
+    scanned recursively.  2^17 uniform points, m = 4, float32 adjoint on 64
+    sampled frequencies."""
+    g = W.rng(612)
+    N = (256, 256, 256)
+    M = 1 << 17
+    x = W.uniform_points(M, 3, g)
+    f = W.complex_normal(M, g)
+    got, plan = run_adjoint(H, N, x, f, 4, "f32")
+    kidx = W.sample_indices(256 ** 3, 64, g)
+    ref = oracle_mod.ndft_adjoint(N, x, f_used(f, "f32"), kidx=kidx)
+    err = oracle_mod.rel_l2(got.reshape(-1)[kidx], ref)
+    print("N=256^3 f32 m=4 adjoint %.3e" % err)
+    assert err <= 1e-5
