@@ -52,6 +52,13 @@ struct Tiling {
 
 __host__ __device__ constexpr size_t align16(size_t v) { return (v + 15) & ~(size_t)15; }
 
+// Pointers read from a descriptor in memory (the Xform fields) are generic to
+// the compiler, which then emits flat memory instructions.  A flat access also
+// counts against the LDS wait counter, so every LDS wait after it would wait
+// for the HBM access too.  as_global restores global addressing.
+template <typename T> using gptr = __attribute__((address_space(1))) T *;
+template <typename T> __device__ __forceinline__ gptr<T> as_global(T *p) { return (gptr<T>)p; }
+
 // Record of one sorted point (16-byte aligned, contiguous per run):
 //   [psi: 3 x 2m window values (dim 0 rotated, dims 1, 2 natural)]
 //   [f: the point's value, complex]  [plane index c0 (int)]
@@ -154,18 +161,17 @@ hipError_t launch_scan(int *data, long long n, int *tmp, hipStream_t s);
 template <typename R>
 hipError_t launch_bin_scatter(const double *x, const float *xf32, long long M, const Xform &X, int T, int m,
                               double b, double inv_peak, const double *poly, const int *cell_start, const int *rank, int *perm,
-                              unsigned char *rec, size_t rec_bytes, bool grad, hipStream_t s);
+                              int *ipos, unsigned char *rec, size_t rec_bytes, bool grad, hipStream_t s);
 template <typename R>
-hipError_t launch_gather(const void *f, const int *perm, long long total, unsigned char *rec,
-                         size_t rec_bytes, size_t off_f, hipStream_t s);
+hipError_t launch_gather(const void *f, const int *perm, long long total, R *fs, hipStream_t s);
 template <typename R>
-hipError_t launch_scatter(const R *outs, const int *perm, long long total, void *f, hipStream_t s);
+hipError_t launch_scatter(const R *outs, const int *ipos, long long total, void *f, hipStream_t s);
 template <typename R>
-hipError_t launch_grad_finish(const R *outs4, const void *f, const int *perm, long long total,
+hipError_t launch_grad_finish(const R *outs4, const void *f, const int *ipos, long long total,
                               void *grad_f, void *grad_x, hipStream_t s);
 template <typename R>
 hipError_t launch_spread(int m, const Xform *dxf, const SItem *items, int nitems, int *queue,
-                         Tiling t, const unsigned char *rec, size_t rec_bytes, const int *cell_start,
+                         Tiling t, const unsigned char *rec, size_t rec_bytes, const R *fs, const int *cell_start,
                          hipStream_t s);
 template <typename R>
 hipError_t launch_interp(int m, bool grad, const Xform *dxf, const SItem *items, int nitems, int *queue,

@@ -119,7 +119,8 @@ __global__ __launch_bounds__(256) void k_bin_scatter(const double *__restrict__ 
                                                      long long M, long long poff, int n0, int n1, int n2, int T,
                                                      int ntx, const int *__restrict__ cell_start,
                                                      const int *__restrict__ rank, int *__restrict__ perm,
-                                                     unsigned char *__restrict__ rec, size_t rec_bytes, double b,
+                                                     int *__restrict__ ipos, unsigned char *__restrict__ rec,
+                                                     size_t rec_bytes, double b,
                                                      double inv_peak, const double *__restrict__ poly)
 {
     constexpr int m = M2 / 2;
@@ -138,6 +139,7 @@ __global__ __launch_bounds__(256) void k_bin_scatter(const double *__restrict__ 
     }
     const long long pos = poff + cell_start[sort_key(c, T, ntx, n0, block_w(M2))] + rank[j];
     perm[pos] = (int)(poff + j);
+    ipos[poff + j] = (int)pos;
     unsigned char *rp = rec + pos * rec_bytes;
 
     int rot = (c[0] - m + 1) % M2;
@@ -327,24 +329,24 @@ hipError_t launch_bin_count(const double *x, const float *xf32, long long M, con
 
 template <typename R, int M2>
 static void scatter_m(const double *x, const float *xf32, long long M, const Xform &X, int T,
-                      const int *cell_start, const int *rank, int *perm, unsigned char *rec, size_t rec_bytes,
-                      double b, double inv_peak, const double *poly, bool grad, hipStream_t s)
+                      const int *cell_start, const int *rank, int *perm, int *ipos, unsigned char *rec,
+                      size_t rec_bytes, double b, double inv_peak, const double *poly, bool grad, hipStream_t s)
 {
     const unsigned nb = (unsigned)((M + 255) / 256);
     auto k = grad ? k_bin_scatter<R, M2, true> : k_bin_scatter<R, M2, false>;
     hipLaunchKernelGGL(k, dim3(nb), dim3(256), 0, s, x, xf32, M, X.poff, X.n[0], X.n[1], X.n[2], T, X.ntx,
-                       cell_start, rank, perm, rec, rec_bytes, b, inv_peak, poly);
+                       cell_start, rank, perm, ipos, rec, rec_bytes, b, inv_peak, poly);
 }
 
 template <typename R>
 hipError_t launch_bin_scatter(const double *x, const float *xf32, long long M, const Xform &X, int T, int m,
                               double b, double inv_peak, const double *poly, const int *cell_start, const int *rank,
-                              int *perm, unsigned char *rec, size_t rec_bytes, bool grad, hipStream_t s)
+                              int *perm, int *ipos, unsigned char *rec, size_t rec_bytes, bool grad, hipStream_t s)
 {
     if (M <= 0) return hipSuccess;
     switch (m) {
 #define HPNFFT_SCATTER_CASE(MM) \
-    case MM: scatter_m<R, 2 * MM>(x, xf32, M, X, T, cell_start, rank, perm, rec, rec_bytes, b, inv_peak, poly, grad, s); break;
+    case MM: scatter_m<R, 2 * MM>(x, xf32, M, X, T, cell_start, rank, perm, ipos, rec, rec_bytes, b, inv_peak, poly, grad, s); break;
         HPNFFT_SCATTER_CASE(1)
         HPNFFT_SCATTER_CASE(2)
         HPNFFT_SCATTER_CASE(3)
@@ -360,10 +362,10 @@ hipError_t launch_bin_scatter(const double *x, const float *xf32, long long M, c
 }
 
 template hipError_t launch_bin_scatter<double>(const double *, const float *, long long, const Xform &, int, int,
-                                               double, double, const double *, const int *, const int *, int *,
+                                               double, double, const double *, const int *, const int *, int *, int *,
                                                unsigned char *, size_t, bool, hipStream_t);
 template hipError_t launch_bin_scatter<float>(const double *, const float *, long long, const Xform &, int, int,
-                                              double, double, const double *, const int *, const int *, int *,
+                                              double, double, const double *, const int *, const int *, int *, int *,
                                               unsigned char *, size_t, bool, hipStream_t);
 
 }  // namespace hpnfft

@@ -24,6 +24,14 @@ constexpr int kFftCap = 2112;  // complex elements per LDS buffer
 constexpr int kLoadU = 8;      // loads in flight per thread
 
 template <typename R> struct C2 { R x, y; };
+// loads and stores through global pointers, member by member (the compiler
+// merges them into one 8- or 16-byte access)
+template <typename R> __device__ inline C2<R> gload(gptr<const C2<R>> p) { return C2<R>{p->x, p->y}; }
+template <typename R> __device__ inline void gstore(gptr<C2<R>> p, C2<R> v)
+{
+    p->x = v.x;
+    p->y = v.y;
+}
 
 template <typename R> __device__ inline C2<R> cmul(C2<R> a, C2<R> b)
 {
@@ -153,22 +161,25 @@ __global__ __launch_bounds__(kFftThreads) void k_fft(int pass, const Xform *__re
     const int n = g.n, ld = n + 1, cnt = W.count;
     const int tid = threadIdx.x, nthr = blockDim.x;
 
-    const C2<R> *src;
-    C2<R> *dst;
-    C2<R> *fh = reinterpret_cast<C2<R> *>(fhat_base) + X.foff;
+    // global addressing for the descriptor's pointers (see as_global)
+    gptr<const C2<R>> src;
+    gptr<C2<R>> dst;
+    gptr<C2<R>> fh = as_global(reinterpret_cast<C2<R> *>(fhat_base)) + X.foff;
     switch (pass) {
-    case P_ADJ0: src = (const C2<R> *)X.grid; dst = (C2<R> *)X.tmpA; break;
-    case P_ADJ1: src = (const C2<R> *)X.tmpA; dst = (C2<R> *)X.tmpB; break;
-    case P_ADJ2: src = (const C2<R> *)X.tmpB; dst = fh; break;
-    case P_FWD0: src = fh; dst = (C2<R> *)X.tmpB; break;
-    case P_FWD1: src = (const C2<R> *)X.tmpB; dst = (C2<R> *)X.tmpA; break;
-    default:     src = (const C2<R> *)X.tmpA; dst = (C2<R> *)X.grid; break;
+    case P_ADJ0: src = as_global((const C2<R> *)X.grid); dst = as_global((C2<R> *)X.tmpA); break;
+    case P_ADJ1: src = as_global((const C2<R> *)X.tmpA); dst = as_global((C2<R> *)X.tmpB); break;
+    case P_ADJ2: src = as_global((const C2<R> *)X.tmpB); dst = fh; break;
+    case P_FWD0: src = fh; dst = as_global((C2<R> *)X.tmpB); break;
+    case P_FWD1: src = as_global((const C2<R> *)X.tmpB); dst = as_global((C2<R> *)X.tmpA); break;
+    default:     src = as_global((const C2<R> *)X.tmpA); dst = as_global((C2<R> *)X.grid); break;
     }
+    const gptr<const double> roll0 = as_global(X.roll[0]), roll1 = as_global(X.roll[1]),
+                             roll2 = as_global(X.roll[2]);
 
     // twiddles exp(S 2 pi i j / n), table holds exp(-2 pi i j / n)
-    const C2<R> *twg = reinterpret_cast<const C2<R> *>(X.tw[g.dim]);
+    const gptr<const C2<R>> twg = as_global(reinterpret_cast<const C2<R> *>(X.tw[g.dim]));
     for (int j = tid; j < n; j += nthr) {
-        C2<R> w = twg[j];
+        C2<R> w = gload<R>(twg + j);
         if (S > 0) w.y = -w.y;
         tw[j] = w;
     }
@@ -196,7 +207,7 @@ __global__ __launch_bounds__(kFftThreads) void k_fft(int pass, const Xform *__re
                 int p, j;
                 if (inner == 1) { p = ec / n; j = ec - p * n; }
                 else { j = ec / cnt; p = ec - j * cnt; }
-                C2<R> w = src[addr(p, j, n)];
+                C2<R> w = gload<R>(src + addr(p, j, n));
                 vx[u] = w.x;
                 vy[u] = w.y;
                 if (e < tot) at[u] = p * ld + j;
@@ -223,10 +234,10 @@ __global__ __launch_bounds__(kFftThreads) void k_fft(int pass, const Xform *__re
                 int p, i;
                 if (inner == 1) { p = ec / N; i = ec - p * N; }
                 else { i = ec / cnt; p = ec - i * cnt; }
-                C2<R> w = src[addr(p, i, N)];
+                C2<R> w = gload<R>(src + addr(p, i, N));
                 if (g.roll_in) {
                     int ii = W.inner0 + p;
-                    double f = X.roll[0][i] * X.roll[1][ii / X.N[2]] * X.roll[2][ii % X.N[2]];
+                    double f = roll0[i] * roll1[ii / X.N[2]] * roll2[ii % X.N[2]];
                     w.x = (R)(w.x * f);
                     w.y = (R)(w.y * f);
                 }
@@ -276,11 +287,11 @@ __global__ __launch_bounds__(kFftThreads) void k_fft(int pass, const Xform *__re
         C2<R> v = cur[p * ld + bin];
         if (g.roll_out) {
             int ii = W.inner0 + p;
-            double f = X.roll[0][o] * X.roll[1][ii / X.N[2]] * X.roll[2][ii % X.N[2]];
+            double f = roll0[o] * roll1[ii / X.N[2]] * roll2[ii % X.N[2]];
             v.x = (R)(v.x * f);
             v.y = (R)(v.y * f);
         }
-        dst[addr(p, o, Lout)] = v;
+        gstore<R>(dst + addr(p, o, Lout), v);
     }
 }
 

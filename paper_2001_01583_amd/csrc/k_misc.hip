@@ -33,39 +33,40 @@ template <typename R> struct Cplx;
 template <> struct Cplx<float> { typedef float T __attribute__((ext_vector_type(2))); };
 template <> struct Cplx<double> { typedef double T __attribute__((ext_vector_type(2))); };
 
+// Values in sorted order for the spread: fs[i] = f[perm[i]] (dense stores;
+// the reads gather from f).
 template <typename R>
 __global__ void k_gather(const R *__restrict__ f, const int *__restrict__ perm, long long total,
-                         unsigned char *__restrict__ rec, size_t rec_bytes, size_t off_f)
+                         R *__restrict__ fs)
 {
-    long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= total) return;
-    const long long j = perm[p];
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= total) return;
     // one complex value: a single 8- or 16-byte load and store
     using C = typename Cplx<R>::T;
-    *reinterpret_cast<C *>(rec + p * rec_bytes + off_f) = reinterpret_cast<const C *>(f)[j];
+    reinterpret_cast<C *>(fs)[i] = reinterpret_cast<const C *>(f)[perm[i]];
 }
 
+// Interpolation outputs back to the caller's order: f[j] = outs[ipos[j]],
+// ipos[j] = sorted position of point j (dense stores).
 template <typename R>
-__global__ void k_scatter(const R *__restrict__ outs, const int *__restrict__ perm, long long total,
+__global__ void k_scatter(const R *__restrict__ outs, const int *__restrict__ ipos, long long total,
                           R *__restrict__ f)
 {
-    long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= total) return;
-    const long long j = perm[p];
+    long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= total) return;
     using C = typename Cplx<R>::T;
-    reinterpret_cast<C *>(f)[j] = reinterpret_cast<const C *>(outs)[p];
+    reinterpret_cast<C *>(f)[j] = reinterpret_cast<const C *>(outs)[ipos[j]];
 }
 
 // outs4 per sorted point: p, d0 p, d1 p, d2 p (complex).  grad_x = Re(f conj(d p)).
 template <typename R>
 __global__ void k_grad_finish(const R *__restrict__ outs4, const R *__restrict__ f,
-                              const int *__restrict__ perm, long long total, R *__restrict__ grad_f,
+                              const int *__restrict__ ipos, long long total, R *__restrict__ grad_f,
                               R *__restrict__ grad_x)
 {
-    long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= total) return;
-    long long j = perm[p];
-    const R *o = outs4 + p * 8;
+    long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= total) return;
+    const R *o = outs4 + (long long)ipos[j] * 8;
     if (grad_f) {
         grad_f[2 * j] = o[0];
         grad_f[2 * j + 1] = o[1];
@@ -77,31 +78,30 @@ __global__ void k_grad_finish(const R *__restrict__ outs4, const R *__restrict__
 }
 
 template <typename R>
-hipError_t launch_gather(const void *f, const int *perm, long long total, unsigned char *rec,
-                         size_t rec_bytes, size_t off_f, hipStream_t s)
+hipError_t launch_gather(const void *f, const int *perm, long long total, R *fs, hipStream_t s)
 {
     if (total <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_gather<R>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s,
-                       (const R *)f, perm, total, rec, rec_bytes, off_f);
+    hipLaunchKernelGGL(k_gather<R>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, (const R *)f, perm,
+                       total, fs);
     return hipGetLastError();
 }
 
 template <typename R>
-hipError_t launch_scatter(const R *outs, const int *perm, long long total, void *f, hipStream_t s)
+hipError_t launch_scatter(const R *outs, const int *ipos, long long total, void *f, hipStream_t s)
 {
     if (total <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_scatter<R>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, outs, perm,
+    hipLaunchKernelGGL(k_scatter<R>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, outs, ipos,
                        total, (R *)f);
     return hipGetLastError();
 }
 
 template <typename R>
-hipError_t launch_grad_finish(const R *outs4, const void *f, const int *perm, long long total,
+hipError_t launch_grad_finish(const R *outs4, const void *f, const int *ipos, long long total,
                               void *grad_f, void *grad_x, hipStream_t s)
 {
     if (total <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_grad_finish<R>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, outs4,
-                       (const R *)f, perm, total, (R *)grad_f, (R *)grad_x);
+                       (const R *)f, ipos, total, (R *)grad_f, (R *)grad_x);
     return hipGetLastError();
 }
 
@@ -242,8 +242,7 @@ hipError_t launch_ewald_real(const double *r, const double *q, long long M, doub
 }
 
 #define HPNFFT_INST(R)                                                                             \
-    template hipError_t launch_gather<R>(const void *, const int *, long long, unsigned char *,      \
-                                         size_t, size_t, hipStream_t);                             \
+    template hipError_t launch_gather<R>(const void *, const int *, long long, R *, hipStream_t);   \
     template hipError_t launch_scatter<R>(const R *, const int *, long long, void *, hipStream_t); \
     template hipError_t launch_grad_finish<R>(const R *, const void *, const int *, long long,     \
                                               void *, void *, hipStream_t);                        \

@@ -267,9 +267,34 @@ __device__ inline void chunk_slots(int cs, int cnt, int nr, const int *run_p0, c
     }
 }
 
-template <int PF>
+// The spread takes each point's value from the values in sorted order (fs,
+// written per call) rather than from its record: 16-byte unit uf of a staged
+// record receives it, at word wf (float: 2 words, double: the whole unit).
+struct ValueSlot {
+    const void *fs;  // null: stage the records as they are
+    int uf, wf;
+};
+template <typename R>
+__device__ inline v4u with_value(v4u v, const ValueSlot &vs, long long sp)
+{
+    if constexpr (sizeof(R) == 8) {
+        return reinterpret_cast<const v4u *>(vs.fs)[sp];
+    } else {
+        const uint2 q = reinterpret_cast<const uint2 *>(vs.fs)[sp];
+        if (vs.wf == 0) {
+            v.x = q.x;
+            v.y = q.y;
+        } else {
+            v.z = q.x;
+            v.w = q.y;
+        }
+        return v;
+    }
+}
+
+template <int PF, typename R>
 __device__ inline void chunk_fetch(int cnt, const int *slot_p, int st16, const v4u *__restrict__ rec, int rs16,
-                                   v4u (&reg)[PF])
+                                   const ValueSlot &vs, v4u (&reg)[PF])
 {
     // every thread loads PF units; indices past the chunk reload unit 0 (the
     // chunk is never empty), so the loads need no branch and the array stays
@@ -279,14 +304,17 @@ __device__ inline void chunk_fetch(int cnt, const int *slot_p, int st16, const v
     for (int k = 0; k < PF; ++k) {
         int e = threadIdx.x + k * blockDim.x;
         e = e < tot ? e : 0;
-        int sl = e / st16;
-        reg[k] = rec[(size_t)slot_p[sl] * rs16 + (e - sl * st16)];
+        const int sl = e / st16, u = e - sl * st16;
+        const long long sp = slot_p[sl];
+        v4u v = rec[sp * rs16 + u];
+        if (vs.fs && u == vs.uf) v = with_value<R>(v, vs, sp);
+        reg[k] = v;
     }
 }
 
-template <int PF>
+template <int PF, typename R>
 __device__ inline void chunk_store(int cnt, const int *slot_p, int st16, const v4u *__restrict__ rec, int rs16,
-                                   const v4u (&reg)[PF], v4u *stage)
+                                   const ValueSlot &vs, const v4u (&reg)[PF], v4u *stage)
 {
     const int tot = cnt * st16;
 #pragma unroll
@@ -295,8 +323,11 @@ __device__ inline void chunk_store(int cnt, const int *slot_p, int st16, const v
         if (e < tot) stage[e] = reg[k];
     }
     for (int e = threadIdx.x + PF * blockDim.x; e < tot; e += blockDim.x) {
-        int sl = e / st16;
-        stage[e] = rec[(size_t)slot_p[sl] * rs16 + (e - sl * st16)];
+        const int sl = e / st16, u = e - sl * st16;
+        const long long sp = slot_p[sl];
+        v4u v = rec[sp * rs16 + u];
+        if (vs.fs && u == vs.uf) v = with_value<R>(v, vs, sp);
+        stage[e] = v;
     }
 }
 
@@ -309,13 +340,16 @@ __global__ __launch_bounds__(spread_max_threads(sizeof(R), M2)) void k_spread(co
                                                  const SItem *__restrict__ items, int nitems,
                                                  int *__restrict__ queue, int T, int Zs, int cap,
                                                  const v4u *__restrict__ rec, int rs16,
-                                                 const int *__restrict__ cell_start)
+                                                 const R *__restrict__ fs, const int *__restrict__ cell_start)
 {
     constexpr int m = M2 / 2;
     constexpr int ROWS = M2 * M2;
     constexpr int NRG = (ROWS + 63) / 64;
     constexpr int ST16 = (int)(rec_prefix(M2, sizeof(R)) / 16);
     constexpr int OFF_F = (int)(rec_off_f(M2, sizeof(R)) / sizeof(R));
+    const ValueSlot vs{fs, (int)(rec_off_f(M2, sizeof(R)) / 16), (int)(rec_off_f(M2, sizeof(R)) % 16 / 4)};
+    static_assert(rec_off_f(M2, sizeof(R)) % 8 == 0 && rec_off_f(M2, sizeof(R)) % 16 + 2 * sizeof(R) <= 16,
+                  "the value lies within one 16-byte unit of the record");
     constexpr int OFF_PZ = (int)(rec_off_pz(M2, sizeof(R)) / 4);
     static_assert(rec_off_xr(M2, sizeof(R)) == rec_off_pz(M2, sizeof(R)) + 4 && rec_off_pz(M2, sizeof(R)) % 8 == 0,
                   "head_of reads the plane index and line offset as one int2");
@@ -368,8 +402,8 @@ __global__ __launch_bounds__(spread_max_threads(sizeof(R), M2)) void k_spread(co
             const int c0n = min(cap, S);
             chunk_slots(0, c0n, nr, run_p0, run_soff, slot_a);
             __syncthreads();
-            chunk_fetch<PF>(c0n, slot_a, ST16, rec, rs16, reg);
-            chunk_store<PF>(c0n, slot_a, ST16, rec, rs16, reg, stage);
+            chunk_fetch<PF, R>(c0n, slot_a, ST16, rec, rs16, vs, reg);
+            chunk_store<PF, R>(c0n, slot_a, ST16, rec, rs16, vs, reg, stage);
             __syncthreads();
         }
         for (int ch = 0; ch < nch; ++ch) {
@@ -381,7 +415,7 @@ __global__ __launch_bounds__(spread_max_threads(sizeof(R), M2)) void k_spread(co
             if (more) {
                 chunk_slots(cs + cap, cntn, nr, run_p0, run_soff, slot_n);
                 __syncthreads();
-                chunk_fetch<PF>(cntn, slot_n, ST16, rec, rs16, reg);
+                chunk_fetch<PF, R>(cntn, slot_n, ST16, rec, rs16, vs, reg);
             }
             // Tasks (times row groups): blocks of lines hold long runs, so
             // their tasks are equal ranges of the chunk's points (one per
@@ -530,12 +564,12 @@ __global__ __launch_bounds__(spread_max_threads(sizeof(R), M2)) void k_spread(co
             }
             __syncthreads();
             if (more) {
-                chunk_store<PF>(cntn, slot_n, ST16, rec, rs16, reg, stage);
+                chunk_store<PF, R>(cntn, slot_n, ST16, rec, rs16, vs, reg, stage);
                 __syncthreads();
             }
         }
 
-        R *grid = reinterpret_cast<R *>(xfs[items[it].xf].grid);
+        const gptr<R> grid = as_global(reinterpret_cast<R *>(xfs[items[it].xf].grid));
         for (int i = tid; i < nz; i += nthr) {
             int z = i / (g.nrows * P), rem = i - z * g.nrows * P;
             int y = g.ry0 + rem / P, xx = rem % P;
@@ -551,8 +585,8 @@ __global__ __launch_bounds__(spread_max_threads(sizeof(R), M2)) void k_spread(co
             }
             int gy = wrapn(g.Y0 + y - m + 1, g.n1), gx = wrapn(g.X0 + xx - m + 1, g.n2);
             size_t gi = (((size_t)(g.z0 + z) * g.n1 + gy) * g.n2 + gx) * 2;
-            if (vr != R(0)) atomicAdd(&grid[gi], vr);
-            if (vi != R(0)) atomicAdd(&grid[gi + 1], vi);
+            if (vr != R(0)) __hip_atomic_fetch_add(&grid[gi], vr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (vi != R(0)) __hip_atomic_fetch_add(&grid[gi + 1], vi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
 }
@@ -571,6 +605,7 @@ __global__ __launch_bounds__(interp_max_threads(sizeof(R), M2, GRAD)) void k_int
     constexpr int ROWS = M2 * M2;
     constexpr int NRG = (ROWS + 63) / 64;
     constexpr int NO = GRAD ? 4 : 1;
+    const ValueSlot vs{nullptr, 0, 0};  // interpolation does not read the values
     constexpr int ST16 = (int)(rec_size(M2, sizeof(R), GRAD) / 16);
     constexpr int OFF_PZ = (int)(rec_off_pz(M2, sizeof(R)) / 4);
     constexpr int OFF_D = (int)(rec_prefix(M2, sizeof(R)) / sizeof(R));
@@ -600,7 +635,7 @@ __global__ __launch_bounds__(interp_max_threads(sizeof(R), M2, GRAD)) void k_int
     for (int it = next_item(queue, &s_item); it < nitems; it = next_item(queue, &s_item)) {
         const ItemGeom g = item_geom(items[it], xfs[items[it].xf], T, Zs, M2);
         const int nz = g.zs * g.nrows * P;
-        const R *grid = reinterpret_cast<const R *>(xfs[items[it].xf].grid);
+        const gptr<const R> grid = as_global(reinterpret_cast<const R *>(xfs[items[it].xf].grid));
         for (int i = tid; i < nz; i += nthr) {
             int z = i / (g.nrows * P), rem = i - z * g.nrows * P;
             int y = g.ry0 + rem / P, xx = rem % P;
@@ -619,8 +654,8 @@ __global__ __launch_bounds__(interp_max_threads(sizeof(R), M2, GRAD)) void k_int
             const int c0n = min(cap, S);
             chunk_slots(0, c0n, nr, run_p0, run_soff, slot_a);
             __syncthreads();
-            chunk_fetch<PF>(c0n, slot_a, ST16, rec, rs16, reg);
-            chunk_store<PF>(c0n, slot_a, ST16, rec, rs16, reg, stage);
+            chunk_fetch<PF, R>(c0n, slot_a, ST16, rec, rs16, vs, reg);
+            chunk_store<PF, R>(c0n, slot_a, ST16, rec, rs16, vs, reg, stage);
             __syncthreads();
         }
         for (int ch = 0; ch < nch; ++ch) {
@@ -633,7 +668,7 @@ __global__ __launch_bounds__(interp_max_threads(sizeof(R), M2, GRAD)) void k_int
             if (more) {
                 chunk_slots(cs + cap, cntn, nr, run_p0, run_soff, slot_n);
                 __syncthreads();
-                chunk_fetch<PF>(cntn, slot_n, ST16, rec, rs16, reg);
+                chunk_fetch<PF, R>(cntn, slot_n, ST16, rec, rs16, vs, reg);
             }
             // Tasks as in the spread (ranges for blocks of lines, one run for
             // single lines); a task evaluates each run piece it covers (all
@@ -851,7 +886,7 @@ __global__ __launch_bounds__(interp_max_threads(sizeof(R), M2, GRAD)) void k_int
             }
             __syncthreads();
             if (more) {
-                chunk_store<PF>(cntn, slot_n, ST16, rec, rs16, reg, stage);
+                chunk_store<PF, R>(cntn, slot_n, ST16, rec, rs16, vs, reg, stage);
                 __syncthreads();
             }
         }
@@ -888,7 +923,7 @@ static void shrink_for_sparse(LdsLayout &LL, const Tiling &t, int M2, size_t R, 
 
 template <typename R, int M2>
 static hipError_t spread_m(const Xform *dxf, const SItem *items, int nitems, int *queue, Tiling t,
-                           const unsigned char *rec, size_t rec_bytes, const int *cs, hipStream_t s)
+                           const unsigned char *rec, size_t rec_bytes, const R *fs, const int *cs, hipStream_t s)
 {
     constexpr bool COMP = sizeof(R) == 4;
     LdsLayout LL = lds_fit(t.T, t.Zs, M2, sizeof(R), 0, COMP);
@@ -904,7 +939,7 @@ static hipError_t spread_m(const Xform *dxf, const SItem *items, int nitems, int
     int grid = std::min(cu_count() * per_cu, nitems);
     if (grid < 1) return hipSuccess;
     hipLaunchKernelGGL(kern, dim3(grid), dim3(threads), LL.total, s, dxf, items, nitems, queue, t.T, t.Zs,
-                       LL.cap, (const v4u *)rec, (int)(rec_bytes / 16), cs);
+                       LL.cap, (const v4u *)rec, (int)(rec_bytes / 16), fs, cs);
     return hipGetLastError();
 }
 
@@ -931,10 +966,11 @@ static hipError_t interp_m(const Xform *dxf, const SItem *items, int nitems, int
 
 template <typename R>
 hipError_t launch_spread(int m, const Xform *dxf, const SItem *items, int nitems, int *queue, Tiling t,
-                         const unsigned char *rec, size_t rec_bytes, const int *cell_start, hipStream_t s)
+                         const unsigned char *rec, size_t rec_bytes, const R *fs, const int *cell_start,
+                         hipStream_t s)
 {
 #define HPNFFT_SPREAD_CASE(MM) \
-    case MM: return spread_m<R, 2 * MM>(dxf, items, nitems, queue, t, rec, rec_bytes, cell_start, s);
+    case MM: return spread_m<R, 2 * MM>(dxf, items, nitems, queue, t, rec, rec_bytes, fs, cell_start, s);
     switch (m) {
         HPNFFT_SPREAD_CASE(1)
         HPNFFT_SPREAD_CASE(2)
@@ -973,9 +1009,9 @@ hipError_t launch_interp(int m, bool grad, const Xform *dxf, const SItem *items,
 }
 
 template hipError_t launch_spread<double>(int, const Xform *, const SItem *, int, int *, Tiling,
-                                          const unsigned char *, size_t, const int *, hipStream_t);
+                                          const unsigned char *, size_t, const double *, const int *, hipStream_t);
 template hipError_t launch_spread<float>(int, const Xform *, const SItem *, int, int *, Tiling,
-                                         const unsigned char *, size_t, const int *, hipStream_t);
+                                         const unsigned char *, size_t, const float *, const int *, hipStream_t);
 template hipError_t launch_interp<double>(int, bool, const Xform *, const SItem *, int, int *, Tiling,
                                           const unsigned char *, size_t, const int *, double *, hipStream_t);
 template hipError_t launch_interp<float>(int, bool, const Xform *, const SItem *, int, int *, Tiling,

@@ -54,7 +54,7 @@ int fft_count(int n)
 }
 
 struct Layout {
-    size_t counters, setp, grids, tmpA, tmpB, cell_start, scan_tmp, rank, perm, xs, rec, outs, tcost, poly,
+    size_t counters, setp, grids, tmpA, tmpB, cell_start, scan_tmp, rank, perm, ipos, fs, xs, rec, outs, tcost, poly,
         items, fit[3], ewald, roll, tw, xf, total;
     size_t rec_bytes = 0;
     std::vector<size_t> grid_off, tmpA_off, tmpB_off, key_off, tcost_off, roll_off;
@@ -199,6 +199,8 @@ void build_layout(hpnfft_plan_s *p)
     L.scan_tmp = take((size_t)(nb + nb / 2048 + 64) * 4);
     L.rank = take((size_t)maxM * 4);
     L.perm = take((size_t)p->Mtot * 4);
+    L.ipos = take((size_t)p->Mtot * 4);
+    L.fs = take((size_t)p->Mtot * C);
     L.xs = take((size_t)p->Mtot * 24);
     L.rec_bytes = rec_size(p->M2(), p->rbytes(), p->grad());
     L.rec = take((size_t)p->Mtot * L.rec_bytes);
@@ -444,12 +446,12 @@ int bin_points(hpnfft_plan_s *p, const double *x = nullptr, const float *x32 = n
         if (p->prec == HPNFFT_F32)
             HCHECK(launch_bin_scatter<float>(xb, nullptr, X.M, X, p->til.T, p->m, p->b, p->inv_peak,
                                              p->poly_ok ? p->at<double>(L.poly) : nullptr, cs,
-                                             p->at<int>(L.rank), p->at<int>(L.perm), p->at<unsigned char>(L.rec),
-                                             L.rec_bytes, p->grad(), s));
+                                             p->at<int>(L.rank), p->at<int>(L.perm), p->at<int>(L.ipos),
+                                             p->at<unsigned char>(L.rec), L.rec_bytes, p->grad(), s));
         else
             HCHECK(launch_bin_scatter<double>(xb, nullptr, X.M, X, p->til.T, p->m, p->b, p->inv_peak,
                                               p->poly_ok ? p->at<double>(L.poly) : nullptr, cs,
-                                              p->at<int>(L.rank), p->at<int>(L.perm),
+                                              p->at<int>(L.rank), p->at<int>(L.perm), p->at<int>(L.ipos),
                                               p->at<unsigned char>(L.rec), L.rec_bytes, p->grad(), s));
         HCHECK(launch_tile_cost(cs, X, p->til.T, p->til.Zs, p->m, p->at<int>(L.tcost_off[b]), total, s));
     }
@@ -485,13 +487,13 @@ template <typename R> int run_adjoint(hpnfft_plan_s *p, const void *f, void *fha
     }
     {
         PhaseTimer t(p, HPNFFT_PH_GATHER);
-        HCHECK(launch_gather<R>(f, p->at<int>(L.perm), p->Mtot, p->at<unsigned char>(L.rec), L.rec_bytes,
-                                rec_off_f(p->M2(), sizeof(R)), s));
+        HCHECK(launch_gather<R>(f, p->at<int>(L.perm), p->Mtot, p->at<R>(L.fs), s));
     }
     {
         PhaseTimer t(p, HPNFFT_PH_SPREAD);
         HCHECK(launch_spread<R>(p->m, dxf, p->at<SItem>(L.items), p->nitems, p->at<int>(L.counters), p->til,
-                                p->at<unsigned char>(L.rec), L.rec_bytes, p->at<int>(L.cell_start), s));
+                                p->at<unsigned char>(L.rec), L.rec_bytes, p->at<R>(L.fs), p->at<int>(L.cell_start),
+                                s));
     }
     for (int pass = P_ADJ0; pass <= P_ADJ2; ++pass) {
         int d = pass == P_ADJ0 ? 2 : (pass == P_ADJ1 ? 1 : 0);
@@ -535,7 +537,7 @@ template <typename R> int run_forward(hpnfft_plan_s *p, const void *fhat, void *
     }
     {
         PhaseTimer t(p, HPNFFT_PH_SCATTER);
-        HCHECK(launch_scatter<R>(p->at<R>(L.outs), p->at<int>(L.perm), p->Mtot, f, s));
+        HCHECK(launch_scatter<R>(p->at<R>(L.outs), p->at<int>(L.ipos), p->Mtot, f, s));
     }
     return HPNFFT_OK;
 }
@@ -561,7 +563,7 @@ int run_backward(hpnfft_plan_s *p, const void *f, const void *gfhat, void *grad_
     }
     {
         PhaseTimer t(p, HPNFFT_PH_GRAD_FIN);
-        HCHECK(launch_grad_finish<R>(p->at<R>(L.outs), f, p->at<int>(L.perm), p->Mtot, grad_f, grad_x, s));
+        HCHECK(launch_grad_finish<R>(p->at<R>(L.outs), f, p->at<int>(L.ipos), p->Mtot, grad_f, grad_x, s));
     }
     return HPNFFT_OK;
 }
