@@ -31,11 +31,15 @@ __device__ inline int line_cost(const int *cs_line, int n0, int z0, int zs, int 
 
 // One thread per (tile, slab, run): the run's cost goes to
 // lcost[(tile * nslab + slab) * nl + run] (consecutive threads, consecutive
-// words) and into the grand total (one atomic per wavefront).
-__global__ __launch_bounds__(256) void k_tile_cost(const int *__restrict__ cell_start, int n0, int T, int Zs,
-                                                   int m, int BW, int nslab, long long n,
-                                                   int *__restrict__ lcost, unsigned long long *__restrict__ total)
+// words) and into the grand total (one atomic per workgroup: atomics on one
+// address serialise).
+constexpr int kCostThreads = 1024;
+__global__ __launch_bounds__(kCostThreads) void k_tile_cost(const int *__restrict__ cell_start, int n0, int T,
+                                                            int Zs, int m, int BW, int nslab, long long n,
+                                                            int *__restrict__ lcost,
+                                                            unsigned long long *__restrict__ total)
 {
+    __shared__ int wsum[kCostThreads / 64];
     const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const int nl = T * T / BW;
     int c = 0;
@@ -49,23 +53,31 @@ __global__ __launch_bounds__(256) void k_tile_cost(const int *__restrict__ cell_
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
-    if ((threadIdx.x & 63) == 0 && c) atomicAdd(total, (unsigned long long)c);
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += (unsigned long long)wsum[w];
+        if (t) atomicAdd(total, t);
+    }
 }
 
-// One wavefront per (tile, slab), four per workgroup: the run costs (from
-// k_tile_cost) are prefix-summed across the lanes and the pair is cut wherever
-// the running cost crosses a multiple of the cap (a pair within the cap
-// becomes one item).  The workgroup counts its items first and reserves their
-// slots in the list with one atomic.
-__global__ __launch_bounds__(256) void k_make_items(const int *__restrict__ lcost, int xf, int T, int BW, int ntiles,
-                                                    int nslab, const unsigned long long *__restrict__ total,
-                                                    int cap_div, int min_cap, int max_items,
-                                                    SItem *__restrict__ items, int *__restrict__ nitems,
-                                                    int *__restrict__ overflow)
+// One wavefront per (tile, slab), kItemWaves per workgroup: the run costs
+// (from k_tile_cost) are prefix-summed across the lanes and the pair is cut
+// wherever the running cost crosses a multiple of the cap (a pair within the
+// cap becomes one item).  The workgroup counts its items first and reserves
+// their slots in the list with one atomic.
+constexpr int kItemWaves = 16;
+__global__ __launch_bounds__(kItemWaves * 64) void k_make_items(const int *__restrict__ lcost, int xf, int T, int BW,
+                                                                int ntiles, int nslab,
+                                                                const unsigned long long *__restrict__ total,
+                                                                int cap_div, int min_cap, int max_items,
+                                                                SItem *__restrict__ items, int *__restrict__ nitems,
+                                                                int *__restrict__ overflow)
 {
-    __shared__ int wcount[4], wbase[4];
+    __shared__ int wcount[kItemWaves], wbase[kItemWaves];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int g = blockIdx.x * 4 + w;
+    const int g = blockIdx.x * kItemWaves + w;
     const bool valid = g < ntiles * nslab;
     const int tile = valid ? g / nslab : 0, slab = valid ? g % nslab : 0;
     const long long capl = (long long)(*total / (unsigned long long)cap_div);
@@ -118,12 +130,12 @@ __global__ __launch_bounds__(256) void k_make_items(const int *__restrict__ lcos
     __syncthreads();
     if (threadIdx.x == 0) {
         int t = 0;
-        for (int k = 0; k < 4; ++k) {
+        for (int k = 0; k < kItemWaves; ++k) {
             wbase[k] = t;
             t += wcount[k];
         }
         const int base = t ? atomicAdd(nitems, t) : 0;
-        for (int k = 0; k < 4; ++k) wbase[k] += base;
+        for (int k = 0; k < kItemWaves; ++k) wbase[k] += base;
     }
     __syncthreads();
     int idx = wbase[w];
@@ -152,8 +164,8 @@ hipError_t launch_tile_cost(const int *cell_start, const Xform &X, int T, int Zs
     const int BW = block_w(2 * m);
     const long long n = (long long)X.ntx * X.nty * X.nslab * (T * T / BW);
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_tile_cost, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, cell_start, X.n[0], T, Zs,
-                       m, BW, X.nslab, n, lcost, total);
+    hipLaunchKernelGGL(k_tile_cost, dim3((unsigned)((n + kCostThreads - 1) / kCostThreads)), dim3(kCostThreads), 0, s,
+                       cell_start, X.n[0], T, Zs, m, BW, X.nslab, n, lcost, total);
     return hipGetLastError();
 }
 
@@ -163,7 +175,8 @@ hipError_t launch_make_items(const int *lcost, int xf, const Xform &X, int T, in
 {
     const long long pairs = (long long)X.ntx * X.nty * X.nslab;  // one wavefront per pair
     if (pairs <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_make_items, dim3((unsigned)((pairs + 3) / 4)), dim3(256), 0, s, lcost, xf, T,
+    hipLaunchKernelGGL(k_make_items, dim3((unsigned)((pairs + kItemWaves - 1) / kItemWaves)), dim3(kItemWaves * 64), 0, s,
+                       lcost, xf, T,
                        block_w(2 * m), X.ntx * X.nty, X.nslab, total, cap_div, min_cap, max_items, items, nitems,
                        overflow);
     return hipGetLastError();
