@@ -906,18 +906,20 @@ static int cu_count()
     return cus;
 }
 
-// Sparse point sets: when the work items hold few points (cap_hint, from
-// the binning), a staging area sized for them leaves LDS for a second
-// workgroup on the compute unit; workgroups then take half the threads, so
-// two independent items (each with its own barriers) share the unit.
-static void shrink_for_sparse(LdsLayout &LL, const Tiling &t, int M2, size_t R, int kind, bool comp, int &threads)
+// Two workgroups per compute unit, each with half the LDS and at most 512
+// threads, when the tile leaves both a staging area worth having: kTwoWgCap
+// points, or fewer when the work items hold fewer (cap_hint, from the
+// binning).  One workgroup's list, staging and flush phases (barriers and
+// HBM latency) then overlap the other's sweep.
+constexpr int kTwoWgCap = 256;
+static void two_per_cu(LdsLayout &LL, const Tiling &t, int M2, size_t R, int kind, bool comp, int &threads)
 {
-    if (t.cap_hint <= 0 || t.cap_hint >= LL.cap) return;
-    const int cap = std::max(64, ((t.cap_hint + 63) / 64) * 64);
-    if (cap >= LL.cap) return;
-    const LdsLayout small = lds_layout(t.T, t.Zs, M2, R, kind, comp, cap);
-    if (2 * (small.total + 1024) > 160 * 1024) return;  // still one workgroup per unit
-    LL = small;
+    int need = kTwoWgCap;
+    if (t.cap_hint > 0) need = std::min(need, std::max(64, t.cap_hint));
+    int cap = LL.cap;
+    while (cap >= need && 2 * (lds_layout(t.T, t.Zs, M2, R, kind, comp, cap).total + 1024) > 160 * 1024) cap -= 16;
+    if (cap < need || cap < 16) return;
+    LL = lds_layout(t.T, t.Zs, M2, R, kind, comp, cap);
     threads = std::max(64, std::min(threads, 512));
 }
 
@@ -929,7 +931,7 @@ static hipError_t spread_m(const Xform *dxf, const SItem *items, int nitems, int
     LdsLayout LL = lds_fit(t.T, t.Zs, M2, sizeof(R), 0, COMP);
     if (!LL.cap) return hipErrorInvalidValue;
     int threads = std::min(t.threads, spread_max_threads(sizeof(R), M2));
-    shrink_for_sparse(LL, t, M2, sizeof(R), 0, COMP, threads);
+    two_per_cu(LL, t, M2, sizeof(R), 0, COMP, threads);
     auto kern = k_spread<R, M2, COMP>;
     hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)LL.total);
@@ -950,7 +952,7 @@ static hipError_t interp_m(const Xform *dxf, const SItem *items, int nitems, int
     LdsLayout LL = lds_fit(t.T, t.Zs, M2, sizeof(R), GRAD ? 2 : 1, false);
     if (!LL.cap) return hipErrorInvalidValue;
     int threads = std::min(t.threads, interp_max_threads(sizeof(R), M2, GRAD));
-    shrink_for_sparse(LL, t, M2, sizeof(R), GRAD ? 2 : 1, false, threads);
+    two_per_cu(LL, t, M2, sizeof(R), GRAD ? 2 : 1, false, threads);
     auto kern = k_interp<R, M2, GRAD>;
     hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)LL.total);

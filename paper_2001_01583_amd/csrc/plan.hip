@@ -134,7 +134,10 @@ Tiling default_tiling(const hpnfft_plan_s *p)
     std::vector<int> Ts = {4, 6, 8, 12, 16, 24, 32};
     std::stable_sort(Ts.begin(), Ts.end(),
                      [&](int a, int b) { return std::abs(a - target) < std::abs(b - target); });
-    for (int Zs : {16, 12, 8})
+    // float32 blocked sweeps: 12-plane slabs leave room for two workgroups
+    // per compute unit (see two_per_cu), measured faster than 16
+    const bool two = p->prec == HPNFFT_F32 && block_w(M2) > 1;
+    for (int Zs : {two ? 12 : 16, two ? 16 : 12, 8})
         for (int T : Ts) {
             Tiling t{T, Zs, 1024};
             if (tiling_fits(p, t)) return t;
