@@ -212,6 +212,11 @@ int hpnfft_batch_offsets(hpnfft_batch batch, int b, int64_t *point_offset,
 /* Enable (1) or disable (0) timing; either way previous records are dropped.
  * While enabled every transform call records two events per phase. */
 int hpnfft_profile(hpnfft_plan plan, int enable);
+/* Time only the phases whose bit (1u << phase) is set in mask (0: off);
+ * previous records are dropped.  Each timed phase costs two events per call,
+ * and an event between two kernels delays the second by a few microseconds,
+ * so a throughput measurement times only the phase it needs. */
+int hpnfft_profile_phases(hpnfft_plan plan, unsigned mask);
 /* Wait for the recorded events, add their elapsed milliseconds per phase to
  * ms[HPNFFT_NPHASES] and the number of launches to counts[HPNFFT_NPHASES]
  * (either may be NULL), then drop the records. */

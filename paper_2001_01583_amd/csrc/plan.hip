@@ -89,7 +89,7 @@ struct hpnfft_plan_s {
         int phase;
         hipEvent_t a, b;
     };
-    bool prof = false;
+    unsigned prof = 0;  // phases timed (bit 1 << phase)
     std::vector<Rec> recs;
     std::vector<hipEvent_t> pool;
 
@@ -402,7 +402,7 @@ struct PhaseTimer {
     hipEvent_t a = nullptr;
     PhaseTimer(hpnfft_plan_s *pl, int ph) : p(pl), phase(ph)
     {
-        if (!p->prof) return;
+        if (!((p->prof >> phase) & 1u)) return;
         a = take_event(p);
         if (a) hipEventRecord(a, p->stream);
     }
@@ -826,8 +826,8 @@ int hpnfft_batch_capture(hpnfft_batch p, const void *f, void *fhat)
     }
     // attribute setup outside the capture: one eager run; no timing events
     // inside the graph
-    bool prof = p->prof;
-    p->prof = false;
+    const unsigned prof = p->prof;
+    p->prof = 0;
     int rc = hpnfft_adjoint(p, f, fhat);
     if (rc) {
         p->prof = prof;
@@ -925,10 +925,15 @@ int hpnfft_autotune(hpnfft_plan p, void *scratch_f, void *scratch_fhat, int *til
 
 int hpnfft_profile(hpnfft_plan p, int enable)
 {
+    return hpnfft_profile_phases(p, enable ? (1u << HPNFFT_NPHASES) - 1u : 0u);
+}
+
+int hpnfft_profile_phases(hpnfft_plan p, unsigned mask)
+{
     if (!p) return HPNFFT_EINVAL;
     if (!p->recs.empty()) HCHECK(hipStreamSynchronize(p->stream));
     drop_records(p);
-    p->prof = enable != 0;
+    p->prof = mask & ((1u << HPNFFT_NPHASES) - 1u);
     return HPNFFT_OK;
 }
 

@@ -74,6 +74,7 @@ def _load():
         "hpnfft_batch_launch": (ctypes.c_int, [P]),
         "hpnfft_batch_offsets": (ctypes.c_int, [P, ctypes.c_int, i64p, i64p]),
         "hpnfft_profile": (ctypes.c_int, [P, ctypes.c_int]),
+        "hpnfft_profile_phases": (ctypes.c_int, [P, ctypes.c_uint]),
         "hpnfft_profile_read": (ctypes.c_int, [P, P, P]),
         "hpnfft_phase_name": (ctypes.c_char_p, [ctypes.c_int]),
         "hpnfft_window_eval": (ctypes.c_int, [ctypes.c_int, ctypes.c_double, ctypes.c_int64, P, P, P]),
@@ -305,10 +306,21 @@ class Plan:
     # live timing ------------------------------------------------------------
     NPHASES = 14
 
-    def profile(self, enable: bool = True):
-        """Record HIP events around every kernel group on the plan's stream."""
+    def profile(self, enable: bool = True, phases=None):
+        """Record HIP events around every kernel group on the plan's stream
+        (or, with phases = a list of phase names, around those only)."""
         self._sync_stream()
-        _check(_load().hpnfft_profile(self._h, 1 if enable else 0), "profile")
+        if phases is None:
+            _check(_load().hpnfft_profile(self._h, 1 if enable else 0), "profile")
+            return
+        lib = _load()
+        names = {lib.hpnfft_phase_name(i).decode(): i for i in range(self.NPHASES)}
+        mask = 0
+        for ph in phases:
+            if ph not in names:
+                raise ValueError("unknown phase %r" % ph)
+            mask |= 1 << names[ph]
+        _check(lib.hpnfft_profile_phases(self._h, ctypes.c_uint(mask if enable else 0)), "profile_phases")
 
     def profile_read(self) -> dict:
         """{phase: (total_ms, launches)} for the calls since the last read."""

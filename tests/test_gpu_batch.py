@@ -154,3 +154,35 @@ def test_autotuner_keeps_results(H, oracle_mod):
     ref = oracle_mod.ndft_adjoint(N, x, f.astype(np.complex128), kidx=kidx)
     for out in (before, after):
         assert oracle_mod.rel_l2(out.reshape(-1)[kidx].astype(np.complex128), ref) <= 1e-5
+
+
+def test_phase_profiling_mask(H):
+    """Timing a subset of phases records events for those phases only, and
+    the transforms' results do not depend on what is timed."""
+    g = W.rng(77)
+    N = (16, 12, 24)
+    M = 3000
+    x = torch.from_numpy(W.uniform_points(M, 3, g)).cuda()
+    f = torch.from_numpy(W.complex_normal(M, g).astype(np.complex64)).cuda()
+    fh = torch.from_numpy(W.complex_normal(int(np.prod(N)), g).reshape(N).astype(np.complex64)).cuda()
+    plan = H.Plan(N, M, m=4, precision="f32")
+    plan.set_points(x)
+    ref_a = plan.adjoint(f).clone()
+    ref_f = plan.forward(fh).clone()
+    plan.profile(True, phases=["spread", "interp"])
+    for _ in range(3):
+        a = plan.adjoint(f)
+        b = plan.forward(fh)
+    ph = plan.profile_read()
+    plan.profile(False)
+    assert set(ph) == {"spread", "interp"}
+    assert ph["spread"][1] == 3 and ph["interp"][1] == 3 and ph["spread"][0] > 0
+    # the sums are atomic, so their order (and the last bits) may vary
+    assert (a - ref_a).abs().max() <= 1e-5 * ref_a.abs().max()
+    assert (b - ref_f).abs().max() <= 1e-5 * ref_f.abs().max()
+    plan.profile(True)
+    plan.adjoint(f)
+    assert {"gather", "spread", "fft_a0", "fft_a1", "fft_a2"} <= set(plan.profile_read())
+    plan.profile(False)
+    with pytest.raises(ValueError):
+        plan.profile(True, phases=["no_such_phase"])
