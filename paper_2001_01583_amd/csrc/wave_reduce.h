@@ -1,13 +1,12 @@
 // Cross-lane sums over a 64-lane wavefront for gfx950.
 //
-// group_reduce<G> sums G per-lane values (one per point) over the wavefront
-// at once by recursive halving: each exchange step sends half of the
-// remaining values to the partner lanes and adds the other half, so G values
-// cost about G - 1 exchange-adds in total instead of G full 6-step
+// The interpolation feeds the per-lane partials of consecutive points through
+// halving steps: each exchange sends half of the pending values to the
+// partner lanes and adds the other half, so 8 points cost about 7
+// exchange-adds per component plus one 8-lane sum, instead of 8 full 6-step
 // reductions.  Exchanges across 32- and 16-lane halves use gfx950's
 // v_permlane32_swap / v_permlane16_swap; exchanges within a 16-lane row use
-// DPP.  After the call, lanes [g * 64/G, (g + 1) * 64/G) all hold the total
-// of value g.
+// DPP.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -90,8 +89,8 @@ __device__ inline void swap16(R &a, R &b)
     b = Words<R>::join(wb);
 }
 
-// Sum within aligned groups of 8, 16 (a row) lanes; every lane of the group
-// receives the group total.
+// Sum within aligned groups of 8 lanes; every lane of the group receives the
+// group total.
 template <typename R>
 __device__ inline R sum8(R v)
 {
@@ -100,14 +99,6 @@ __device__ inline R sum8(R v)
     v += dpp<0x141>(v);  // row_half_mirror
     return v;
 }
-template <typename R>
-__device__ inline R sum16(R v)
-{
-    v = sum8(v);
-    v += dpp<0x140>(v);  // row_mirror
-    return v;
-}
-
 // Halving steps for a stream of per-lane partials, one value per point.
 // halve32(a, b): lanes 0-31 hold a summed over lanes l and l^32, lanes 32-63
 // the same for b.
@@ -136,53 +127,6 @@ __device__ inline R halve8_sum(R a, R b)
     R u = hi ? a : b;
     t += dpp<0x128>(u);  // row_ror:8
     return sum8(t);
-}
-
-// Reduce G values (G in {1, 2, 4, 8}); see the header comment for where
-// value g ends up.
-template <int G, typename R>
-__device__ inline R group_reduce(R (&v)[G])
-{
-    if constexpr (G == 1) {
-        R a = v[0], b = v[0];
-        swap32(a, b);
-        a += b;
-        R c = a;
-        swap16(a, c);
-        return sum16(a + c);
-    } else if constexpr (G == 2) {
-        R a = v[0], b = v[1];
-        swap32(a, b);
-        a += b;  // lanes 0-31: value 0, 32-63: value 1
-        R c = a;
-        swap16(a, c);
-        return sum16(a + c);
-    } else if constexpr (G == 4) {
-        R a0 = v[0], a1 = v[1], b0 = v[2], b1 = v[3];
-        swap32(a0, b0);
-        swap32(a1, b1);
-        R q0 = a0 + b0, q1 = a1 + b1;  // q0 = [v0 | v2], q1 = [v1 | v3]
-        swap16(q0, q1);
-        return sum16(q0 + q1);  // row g: value g
-    } else {
-        static_assert(G == 8, "group size");
-        R a0 = v[0], a1 = v[1], a2 = v[2], a3 = v[3];
-        R b0 = v[4], b1 = v[5], b2 = v[6], b3 = v[7];
-        swap32(a0, b0);
-        swap32(a1, b1);
-        swap32(a2, b2);
-        swap32(a3, b3);
-        R q0 = a0 + b0, q1 = a1 + b1, q2 = a2 + b2, q3 = a3 + b3;  // qi = [vi | vi+4]
-        swap16(q0, q2);
-        swap16(q1, q3);
-        R r0 = q0 + q2, r1 = q1 + q3;  // rows of r0: v0 v2 v4 v6; of r1: v1 v3 v5 v7
-        // within each row, lanes 0-7 keep r0's value, lanes 8-15 r1's
-        const bool hi = (threadIdx.x & 8) != 0;
-        R t = hi ? r1 : r0;
-        R u = hi ? r0 : r1;
-        t += dpp<0x128>(u);  // row_ror:8
-        return sum8(t);      // 8-lane group g: value g
-    }
 }
 
 }  // namespace hpnfft
