@@ -84,6 +84,10 @@ struct hpnfft_plan_s {
     int maxn = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
+    // set_points' readback: pinned host words and the event that marks them
+    // copied (created at the first set_points, which runs on a GPU)
+    int *hres = nullptr;
+    hipEvent_t res_ev = nullptr;
     // live timing
     struct Rec {
         int phase;
@@ -120,12 +124,14 @@ bool tiling_fits(const hpnfft_plan_s *p, Tiling t)
     return true;
 }
 
-// Default tiling.  Measured on MI355X at 0.5 points per grid cell, the
-// sweeps run fastest with slabs of 16 planes and tiles whose LDS footprint
-// side P = T + 2m - 1 is about 20-21 cells (float32 m = 4: T = 12; float64
-// m = 8: T = 6): larger tiles cut the halo traffic but leave too little LDS
-// for staging points, smaller ones re-read more halo.  The first candidate
-// (in order of distance from that target) that fits is taken.
+// Default tiling.  Measured on MI355X at 0.5 points per grid cell: single-
+// line sweeps run fastest with slabs of 16 planes and tiles whose LDS
+// footprint side P = T + 2m - 1 is about 20-21 cells (float64 m = 8: T = 6);
+// larger tiles cut the halo traffic but leave too little LDS for staging
+// points, smaller ones re-read more halo.  Blocked sweeps (2m = 8) take one
+// block of lines per tile row (T = 8); in float32 with 12-plane slabs, which
+// lets two workgroups share a compute unit.  The first candidate (in order of
+// distance from the target) that fits is taken.
 Tiling default_tiling(const hpnfft_plan_s *p)
 {
     const int M2 = p->M2();
@@ -464,9 +470,21 @@ int bin_points(hpnfft_plan_s *p, const double *x = nullptr, const float *x32 = n
         HCHECK(launch_make_items(p->at<int>(L.tcost_off[b]), b, X, p->til.T, p->m, total, cap_div, kMinCap,
                                  L.max_items, p->at<SItem>(L.items), setp + 1, setp + 2, s));
     }
-    int host[6] = {0, 0, 0, 0, 0, 0};  // err, nitems, overflow, pad, total cost (u64)
-    HCHECK(hipMemcpyAsync(host, setp, sizeof(host), hipMemcpyDeviceToHost, s));
-    HCHECK(hipStreamSynchronize(s));
+    // err, nitems, overflow, pad, total cost (u64).  The copy goes to pinned
+    // memory and the host polls its event: a blocking wait would leave the
+    // GPU idle for the wake-up latency as well.
+    if (!p->hres) {
+        HCHECK(hipHostMalloc((void **)&p->hres, 64, hipHostMallocDefault));
+        HCHECK(hipEventCreateWithFlags(&p->res_ev, hipEventDisableTiming));
+    }
+    HCHECK(hipMemcpyAsync(p->hres, setp, 6 * sizeof(int), hipMemcpyDeviceToHost, s));
+    HCHECK(hipEventRecord(p->res_ev, s));
+    hipError_t q;
+    while ((q = hipEventQuery(p->res_ev)) == hipErrorNotReady) {
+    }
+    HCHECK(q);
+    int host[6];
+    std::memcpy(host, p->hres, sizeof(host));
     if (host[0]) return HPNFFT_EDOMAIN;
     if (host[2]) return HPNFFT_ENOMEM;
     p->nitems = std::min(host[1], L.max_items);
@@ -670,6 +688,11 @@ int hpnfft_plan_destroy(hpnfft_plan p)
     for (hipEvent_t e : p->pool) hipEventDestroy(e);
     if (p->gexec) hipGraphExecDestroy(p->gexec);
     if (p->graph) hipGraphDestroy(p->graph);
+    if (p->res_ev) {
+        hipEventSynchronize(p->res_ev);
+        hipEventDestroy(p->res_ev);
+    }
+    if (p->hres) hipHostFree(p->hres);
     delete p;
     return HPNFFT_OK;
 }
