@@ -159,6 +159,22 @@ __device__ inline int next_item(int *queue, int *s_item)
     return *s_item;
 }
 
+// The work-queue counter clears itself: the last workgroup to finish resets
+// it (and the finish count two words on) to zero, so the next launch needs
+// no clearing, and a captured graph no memset.  Call from all threads after
+// the item loop (whose last next_item ends with a barrier): by then this
+// workgroup has taken its last item.
+__device__ inline void release_queue(int *queue)
+{
+    if (threadIdx.x == 0) {
+        const int done = atomicAdd(queue + 2, 1);
+        if (done == (int)gridDim.x - 1) {
+            atomicExch(queue, 0);
+            atomicExch(queue + 2, 0);
+        }
+    }
+}
+
 // Geometry of one work item.
 struct ItemGeom {
     int n0, n1, n2, X0, Y0, z0, zs, ry0, nrows, lb, le, tile;
@@ -589,6 +605,7 @@ __global__ __launch_bounds__(spread_max_threads(sizeof(R), M2)) void k_spread(co
             if (vi != R(0)) __hip_atomic_fetch_add(&grid[gi + 1], vi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
+    release_queue(queue);
 }
 
 // ---------------------------------------------------------------------------
@@ -891,6 +908,7 @@ __global__ __launch_bounds__(interp_max_threads(sizeof(R), M2, GRAD)) void k_int
             }
         }
     }
+    release_queue(queue);
 }
 
 // ---------------------------------------------------------------------------

@@ -440,7 +440,9 @@ int bin_points(hpnfft_plan_s *p, const double *x = nullptr, const float *x32 = n
     const Layout &L = p->L;
     hipStream_t s = p->stream;
     int *setp = p->at<int>(L.setp);  // [0] err, [1] nitems, [2] overflow, [4..5] total (u64)
-    HCHECK(launch_zero(setp, 256, s));
+    // the status words and the sweeps' work-queue counters (adjacent; the
+    // sweeps reset their counters themselves after every launch)
+    HCHECK(launch_zero(p->ws + L.counters, L.setp + 256 - L.counters, s));
     double *xs = p->at<double>(L.xs);
     const bool stored = !x && !x32;
     unsigned long long *total = reinterpret_cast<unsigned long long *>(setp + 4);
@@ -503,7 +505,6 @@ template <typename R> int run_adjoint(hpnfft_plan_s *p, const void *f, void *fha
     const Xform *dxf = p->at<Xform>(L.xf);
     {
         PhaseTimer t(p, HPNFFT_PH_ZERO);
-        HCHECK(launch_zero(p->ws + L.counters, 256, s));
         HCHECK(launch_zero(p->ws + L.grids, L.grids_bytes, s));
     }
     {
@@ -545,7 +546,6 @@ template <typename R> int run_forward(hpnfft_plan_s *p, const void *fhat, void *
     const Xform *dxf = p->at<Xform>(L.xf);
     {
         PhaseTimer t(p, HPNFFT_PH_ZERO);
-        HCHECK(launch_zero(p->ws + L.counters, 256, s));
         HCHECK(launch_zero(p->ws + L.outs, (size_t)p->Mtot * 2 * sizeof(R), s));
     }
     int rc = run_to_grid<R>(p, fhat);
@@ -571,7 +571,6 @@ int run_backward(hpnfft_plan_s *p, const void *f, const void *gfhat, void *grad_
     const Xform *dxf = p->at<Xform>(L.xf);
     {
         PhaseTimer t(p, HPNFFT_PH_ZERO);
-        HCHECK(launch_zero(p->ws + L.counters, 256, s));
         HCHECK(launch_zero(p->ws + L.outs, L.outs_bytes, s));
     }
     int rc = run_to_grid<R>(p, gfhat);
