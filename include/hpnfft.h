@@ -24,7 +24,9 @@
  *          stored at index k_t + N_t/2
  * Streams: all transform calls are asynchronous on the plan's HIP stream.
  * The library never allocates device memory: the caller provides one
- * workspace buffer of hpnfft_workspace_size() bytes.
+ * workspace buffer of hpnfft_workspace_size() bytes.  The only allocation
+ * is 64 bytes of pinned host memory per plan (at its first set_points), the
+ * target of set_points' status readback.
  */
 #ifndef HPNFFT_H
 #define HPNFFT_H
@@ -108,9 +110,10 @@ int hpnfft_set_workspace(hpnfft_plan plan, void *dev_ptr, size_t bytes);
  * and tabulates the window values (the paper's CUNFFT evaluates the window on
  * the fly, Section 1; here it is tabulated once per point set because the
  * same points serve adjoint, forward and gradient).  The caller may free x
- * afterwards.  Synchronises the plan's stream once, to check the domain:
- * returns EDOMAIN if any coordinate is outside [-1/2,1/2) or not finite, and
- * the plan then has no points.  ESTATE if no workspace is attached. */
+ * afterwards.  Waits once for the plan's stream (polling the readback of
+ * its status words), to check the domain: returns EDOMAIN if any coordinate
+ * is outside [-1/2,1/2) or not finite, and the plan then has no points.
+ * ESTATE if no workspace is attached. */
 int hpnfft_set_points(hpnfft_plan plan, const double *x);
 /* Same, for float32 coordinates (promoted exactly to float64). */
 int hpnfft_set_points_f32(hpnfft_plan plan, const float *x);
