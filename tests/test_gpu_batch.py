@@ -186,3 +186,29 @@ def test_phase_profiling_mask(H):
     plan.profile(False)
     with pytest.raises(ValueError):
         plan.profile(True, phases=["no_such_phase"])
+
+
+@pytest.mark.parametrize("M", [1, 37, 20000])
+def test_repeated_calls_reuse_work_queues(H, M):
+    """The sweeps' work-queue counters reset themselves at the end of every
+    launch: many adjoint / forward calls in a row (few points, so fewer work
+    items than workgroup slots, and many) keep giving the first call's
+    results (up to the order of the atomic sums)."""
+    g = W.rng(78 + M)
+    N = (16, 16, 16)
+    x = torch.from_numpy(W.uniform_points(M, 3, g)).cuda()
+    f = torch.from_numpy(W.complex_normal(M, g).astype(np.complex64)).cuda()
+    fh = torch.from_numpy(W.complex_normal(16 ** 3, g).reshape(N).astype(np.complex64)).cuda()
+    plan = H.Plan(N, M, m=4, precision="f32")
+    plan.set_points(x)
+    a0 = plan.adjoint(f).clone()
+    b0 = plan.forward(fh).clone()
+    for _ in range(10):
+        a = plan.adjoint(f)
+        b = plan.forward(fh)
+    torch.cuda.synchronize()
+    assert (a - a0).abs().max() <= 1e-5 * a0.abs().max()
+    assert (b - b0).abs().max() <= 1e-5 * b0.abs().max()
+    plan.set_points(x)  # re-binning keeps them valid too
+    a = plan.adjoint(f)
+    assert (a - a0).abs().max() <= 1e-5 * a0.abs().max()
