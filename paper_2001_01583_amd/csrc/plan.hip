@@ -918,15 +918,19 @@ int hpnfft_autotune(hpnfft_plan p, void *scratch_f, void *scratch_fhat, int *til
     hipEvent_t e0, e1;
     HCHECK(hipEventCreate(&e0));
     HCHECK(hipEventCreate(&e1));
+    // one round: adjoint and forward, and for gradient plans the backward
+    // (its gradient interpolation is timed; grad_f lands in scratch_f)
+    auto round = [&]() {
+        return hpnfft_adjoint(p, scratch_f, scratch_fhat) == 0 && hpnfft_forward(p, scratch_fhat, scratch_f) == 0 &&
+               (!p->grad() || hpnfft_adjoint_backward(p, scratch_f, scratch_fhat, scratch_f, nullptr) == 0);
+    };
     for (const Tiling &t : cand) {
         if (install(t)) continue;
         bool ok = true;
-        for (int w = 0; w < 2 && ok; ++w)
-            ok = hpnfft_adjoint(p, scratch_f, scratch_fhat) == 0 && hpnfft_forward(p, scratch_fhat, scratch_f) == 0;
+        for (int w = 0; w < 2 && ok; ++w) ok = round();
         if (!ok) continue;
         hipEventRecord(e0, p->stream);
-        for (int r = 0; r < 3 && ok; ++r)
-            ok = hpnfft_adjoint(p, scratch_f, scratch_fhat) == 0 && hpnfft_forward(p, scratch_fhat, scratch_f) == 0;
+        for (int r = 0; r < 3 && ok; ++r) ok = round();
         hipEventRecord(e1, p->stream);
         hipEventSynchronize(e1);
         float ms = 0;

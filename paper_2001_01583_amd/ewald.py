@@ -49,6 +49,12 @@ class Ewald:
         self.device = self.plan.device
         self._scratch = torch.empty((self.M + 255) // 256 + 8, dtype=torch.float64, device=self.device)
 
+    def autotune(self, r: torch.Tensor):
+        """Pick the plan's tiling on these positions (once per lattice; the
+        timing covers the forward pass and the gradient used for forces)."""
+        self.plan.set_points(self._unit(r.to(torch.float64)))
+        return self.plan.autotune()
+
     def _unit(self, r: torch.Tensor) -> torch.Tensor:
         x = r / self.L
         x = x - torch.floor(x + 0.5)

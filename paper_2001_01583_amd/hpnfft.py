@@ -296,8 +296,10 @@ class Plan:
         self._sync_stream()
         _check(lib.hpnfft_set_workspace(self._h, ctypes.c_void_p(self._ws_ptr), need), "set_workspace")
         self.set_points(x_keep)
-        f = torch.zeros(self.Mtot, dtype=self.cdtype, device=self.device)
-        fh = torch.zeros(self.Ftot, dtype=self.cdtype, device=self.device)
+        # nonzero values: the spread skips the grid atomics of cells that sum
+        # to zero, so zeros would time every candidate without its flush
+        f = torch.ones(self.Mtot, dtype=self.cdtype, device=self.device)
+        fh = torch.ones(self.Ftot, dtype=self.cdtype, device=self.device)
         a, b, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
         _check(lib.hpnfft_autotune(self._h, _ptr(f), _ptr(fh), ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)),
                "autotune")
