@@ -169,3 +169,22 @@ def test_autograd_forces_equal_backward_kernel(E):
     Fa = -ra.grad
     assert abs(Ua.item() - U.item()) <= 1e-12 * abs(U.item())
     assert (Fa - F).abs().max().item() <= 1e-10 * F.abs().max().item()
+
+
+@pytest.mark.parametrize("prec,m,tol_u,tol_f", [("f64", 8, 1e-12, 1e-10), ("f32", 4, 1e-5, 1e-3)])
+def test_autotuned_ewald_keeps_energy_and_forces(E, oracle_mod, prec, m, tol_u, tol_f):
+    """Ewald.autotune re-tiles a gradient plan (timing the backward too); the
+    reciprocal energy and forces then still match the direct oracle."""
+    rt, qt, L, r, q = _fluorite_gpu(3, 0.02, 407)
+    alpha = 1.4
+    ew = E.Ewald(r.shape[0], L, alpha, N=(48, 48, 48), m=m, precision=prec)
+    tiles = ew.autotune(rt)
+    assert tuple(ew.plan.tiles) == tuple(tiles)
+    U, F = ew.reciprocal(rt, qt)
+    kmax = 23
+    Uk = oracle_mod.ewald_recip(r, q, L, alpha, kmax)  # Eq. (12) including the self term
+    Fk = oracle_mod.ewald_recip_forces(r, q, L, alpha, kmax)
+    eu = abs(U.item() - Uk) / abs(Uk)
+    ef = np.max(np.abs(F.cpu().numpy() - Fk)) / np.max(np.abs(Fk))
+    print("autotuned %s tiles=%s: energy %.3e forces %.3e" % (prec, tiles, eu, ef))
+    assert eu <= tol_u and ef <= tol_f
