@@ -163,9 +163,9 @@ int hpnfft_ewald_real(const double *r, const double *q, int64_t M, double L, dou
                       double rcut, double *energy_dev, double *forces_dev,
                       double *scratch_dev, void *stream);
 
-/* Tiling autotuner: times the adjoint and forward (and, for gradient plans,
- * the backward) for each candidate tiling on the current points and keeps
- * the fastest.  scratch_f / scratch_fhat are overwritten; give them nonzero
+/* Tiling autotuner: times the adjoint and the forward (for gradient plans:
+ * the adjoint and the backward) for each candidate tiling on the current
+ * points and keeps the fastest.  scratch_f / scratch_fhat are overwritten; give them nonzero
  * values (the spread skips the grid atomics of cells that sum to zero).
  * Needs points and a workspace at least as large as the largest candidate
  * needs (query with hpnfft_workspace_size after hpnfft_set_tiles).  Writes

@@ -918,11 +918,16 @@ int hpnfft_autotune(hpnfft_plan p, void *scratch_f, void *scratch_fhat, int *til
     hipEvent_t e0, e1;
     HCHECK(hipEventCreate(&e0));
     HCHECK(hipEventCreate(&e1));
-    // one round: adjoint and forward, and for gradient plans the backward
-    // (its gradient interpolation is timed; grad_f lands in scratch_f)
+    // one round: the adjoint, then the forward, or for gradient plans the
+    // backward that their users run instead.  Their point outputs go to the
+    // workspace's sorted-values array (the next adjoint's gather rewrites
+    // it), never back into scratch_f: fed back, the values would grow round
+    // by round to inf and NaN.
     auto round = [&]() {
-        return hpnfft_adjoint(p, scratch_f, scratch_fhat) == 0 && hpnfft_forward(p, scratch_fhat, scratch_f) == 0 &&
-               (!p->grad() || hpnfft_adjoint_backward(p, scratch_f, scratch_fhat, scratch_f, nullptr) == 0);
+        void *outp = p->ws + p->L.fs;
+        return hpnfft_adjoint(p, scratch_f, scratch_fhat) == 0 &&
+               (p->grad() ? hpnfft_adjoint_backward(p, scratch_f, scratch_fhat, outp, nullptr) == 0
+                          : hpnfft_forward(p, scratch_fhat, outp) == 0);
     };
     for (const Tiling &t : cand) {
         if (install(t)) continue;

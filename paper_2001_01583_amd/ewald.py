@@ -51,7 +51,7 @@ class Ewald:
 
     def autotune(self, r: torch.Tensor):
         """Pick the plan's tiling on these positions (once per lattice; the
-        timing covers the forward pass and the gradient used for forces)."""
+        timing covers the adjoint and the gradient used for forces)."""
         self.plan.set_points(self._unit(r.to(torch.float64)))
         return self.plan.autotune()
 
