@@ -419,13 +419,7 @@ def bench_c5(H, torch, W, args):
     for prec, m in (("f64", 8), ("f32", 4)):
         ew = E.Ewald(r.shape[0], L_box, alpha, N=(128, 128, 128), m=m, precision=prec, device=dev)
         t_tune = time.perf_counter()
-        if prec == "f32":
-            tiles = ew.autotune(r)  # once per lattice: tiling timed on these ions, gradient included
-        else:
-            # float64 gradient plans keep the default tiling: inside the
-            # autotuner their sweep kernels were measured running 3-20x
-            # slower than the same launches outside it, so its choice misleads
-            tiles = ew.plan.tiles
+        tiles = ew.autotune(r)  # once per lattice: tiling timed on these ions, gradient included
         t_tune = time.perf_counter() - t_tune
         t = _time(torch, lambda: ew.reciprocal(r, q, forces=True), args.steps, args.warmup)
         ew.plan.profile(True)

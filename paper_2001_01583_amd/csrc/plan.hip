@@ -882,6 +882,13 @@ int hpnfft_autotune(hpnfft_plan p, void *scratch_f, void *scratch_fhat, int *til
 {
     if (!p || !scratch_f || !scratch_fhat) return HPNFFT_EINVAL;
     if (!p->have_points) return HPNFFT_ESTATE;
+    // the stored float64 points survive re-layouts only if their offset is
+    // unchanged; keep a host copy instead (read before any candidate layout
+    // is built: p->L must still be the layout the points were stored with)
+    std::vector<double> hx((size_t)p->Mtot * 3);
+    HCHECK(hipMemcpyAsync(hx.data(), p->at<double>(p->L.xs), hx.size() * 8, hipMemcpyDeviceToHost,
+                          p->stream));
+    HCHECK(hipStreamSynchronize(p->stream));
     // candidates that fit the attached workspace
     std::vector<Tiling> cand;
     for (int T : {4, 6, 8, 12, 16})
@@ -896,12 +903,6 @@ int hpnfft_autotune(hpnfft_plan p, void *scratch_f, void *scratch_fhat, int *til
                 p->til = keep;
                 if (need <= p->ws_bytes) cand.push_back(t);
             }
-    // the stored float64 points survive re-layouts only if their offset is
-    // unchanged; keep a host copy instead
-    std::vector<double> hx((size_t)p->Mtot * 3);
-    HCHECK(hipMemcpyAsync(hx.data(), p->at<double>(p->L.xs), hx.size() * 8, hipMemcpyDeviceToHost,
-                          p->stream));
-    HCHECK(hipStreamSynchronize(p->stream));
     auto install = [&](Tiling t) -> int {
         p->til = t;
         build_layout(p);

@@ -212,3 +212,25 @@ def test_repeated_calls_reuse_work_queues(H, M):
     plan.set_points(x)  # re-binning keeps them valid too
     a = plan.adjoint(f)
     assert (a - a0).abs().max() <= 1e-5 * a0.abs().max()
+
+
+@pytest.mark.parametrize("prec,m,tol", [("f64", 8, 1e-12), ("f32", 4, 1e-5)])
+def test_autotune_keeps_the_points(H, prec, m, tol):
+    """After autotuning, the plan still holds its own points: an adjoint
+    without a new set_points equals the one before.  The grid (n = 48 x 36 x
+    64) makes the stored points' offset in the workspace depend on the tile
+    edge, so a copy read from a candidate's layout would be wrong."""
+    g = W.rng(79)
+    N = (24, 18, 32)
+    M = 6000
+    x = torch.from_numpy(W.uniform_points(M, 3, g)).cuda()
+    cd = torch.complex128 if prec == "f64" else torch.complex64
+    f = torch.from_numpy(W.complex_normal(M, g)).cuda().to(cd)
+    plan = H.Plan(N, M, m=m, precision=prec)
+    plan.set_points(x)
+    ref = plan.adjoint(f).clone()
+    plan.autotune()
+    got = plan.adjoint(f)
+    err = ((got - ref).abs().norm() / ref.abs().norm()).item()
+    print("autotune %s m=%d tiles=%s: rel change %.3e" % (prec, m, plan.tiles, err))
+    assert err <= tol
