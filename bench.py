@@ -59,11 +59,31 @@ def phase_work(prec: str, m: int, n: int, Nb: int, Mp: int):
     }
 
 
-def spread_bytes(prec: str, m: int, n: int, Mp: int) -> float:
-    """Spread algorithmic HBM bytes: per point its value, plane index and
-    3 x 2m window weights in; the grid written once."""
+def spread_bytes(prec: str, m: int, n: int, Mp: int, d: int = 3) -> float:
+    """Spread algorithmic HBM bytes of the method itself: per point its d
+    coordinates and its complex value read (M (d + 2) s), the grid written
+    once (n^d 2 s).  Implementation-specific tables (the per-point window
+    records) are not counted."""
     r = 8 if prec == "f64" else 4
-    return Mp * (2 * r + 4 + 3 * 2 * m * r) + n ** 3 * 2 * r
+    return Mp * (d + 2) * r + n ** d * 2 * r
+
+
+def hbm_copy_gbs(torch, H, nbytes: int = 1 << 30, reps: int = 10) -> float:
+    """Achievable HBM rate: the library's streaming copy kernel over nbytes
+    (read + write counted), best of reps launches timed with HIP events."""
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    best = 1e30
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        H.device_copy(b, a)
+        e1.record()
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1) * 1e-3)
+    del a, b
+    torch.cuda.empty_cache()
+    return 2.0 * nbytes / best / 1e9
 
 
 def src_hash() -> str:
@@ -202,7 +222,7 @@ def run_path(H, torch, W, data, prec: str, m: int, steps: int, warmup: int):
                 fhat=fh_out.cpu().numpy(), fout=f_out.cpu().numpy(), tiles=plan.tiles)
 
 
-def summarize(res, prec, m):
+def summarize(res, prec, m, copy_gbs=None):
     n = 2 * N[0]
     work = phase_work(prec, m, n, N[0], M)
     table = {}
@@ -214,7 +234,11 @@ def summarize(res, prec, m):
             if kind == "alu":
                 row["tflops"] = round(amount / (per * 1e-3) / 1e12, 3)
             else:
-                row["gbs"] = round(amount / (per * 1e-3) / 1e9, 1)
+                gbs = amount / (per * 1e-3) / 1e9
+                row["gbs"] = round(gbs, 1)
+                row["hbm_frac"] = round(gbs / PEAK_HBM_GBS, 4)
+                if copy_gbs:
+                    row["hbm_frac_of_copy"] = round(gbs / copy_gbs, 4)
         table[name] = row
     dom = res["dom"]
     kind, amount = work[dom]
@@ -227,6 +251,12 @@ def summarize(res, prec, m):
     traffic = measured_traffic(dom, prec)
     roof = {"bound": kind, "kernel": dom, "achieved": round(ach, 3), "peak": peak, "unit": unit,
             "frac": round(ach / peak, 4), "traffic": traffic}
+    if kind == "alu":
+        # the library is built without packed FP32 instructions: one FMA per
+        # lane per cycle, 78.6 TFLOP/s in either precision
+        roof["peak_note"] = ("vector %s peak; without packed FP32 the reachable rate is 78.6 TFLOP/s"
+                             % prec)
+        roof["frac_of_unpacked"] = round(ach / 78.6, 4)
     sp_ms, sp_cnt = res["phases"].get("spread", (0.0, 0))
     spread_gbs = spread_bytes(prec, m, n, M) / (sp_ms / max(sp_cnt, 1) * 1e-3) / 1e9 if sp_cnt else None
     return table, roof, spread_gbs
@@ -266,19 +296,22 @@ def cpu_baseline(data, gpu):
     t0 = time.perf_counter()
     ref_f = oracle.ndft_forward(N, x, fhat, jidx=jidx)
     tf = time.perf_counter() - t0
+    # the float32 runs received the same draws rounded: their oracle values
+    # on the same (full) sample, outside the timed baseline
+    fa = f.astype(np.complex64).astype(np.complex128)
+    fb = fhat.astype(np.complex64).astype(np.complex128)
+    ref32 = None
     for key, res in gpu.items():
         prec = key.split("_")[0]
         if prec == "f32":
-            fa = f.astype(np.complex64).astype(np.complex128)
-            fb = fhat.astype(np.complex64).astype(np.complex128)
-            ra = oracle.ndft_adjoint(N, x, fa, kidx=kidx[:64])
-            rf = oracle.ndft_forward(N, x, fb, jidx=jidx[:64])
-            ea = oracle.rel_l2(res["fhat"].reshape(-1)[kidx[:64]].astype(np.complex128), ra)
-            ef = oracle.rel_l2(res["fout"][jidx[:64]].astype(np.complex128), rf)
+            if ref32 is None:
+                ref32 = (oracle.ndft_adjoint(N, x, fa, kidx=kidx), oracle.ndft_forward(N, x, fb, jidx=jidx))
+            ra, rf = ref32
         else:
-            ea = oracle.rel_l2(res["fhat"].reshape(-1)[kidx], ref_a)
-            ef = oracle.rel_l2(res["fout"][jidx], ref_f)
-        errs[key] = {"adjoint": float("%.3e" % ea), "forward": float("%.3e" % ef)}
+            ra, rf = ref_a, ref_f
+        ea = oracle.rel_l2(res["fhat"].reshape(-1)[kidx].astype(np.complex128), ra)
+        ef = oracle.rel_l2(res["fout"][jidx].astype(np.complex128), rf)
+        errs[key] = {"adjoint": float("%.3e" % ea), "forward": float("%.3e" % ef), "k": int(nk), "j": int(nj)}
     t_adj_full = ta * nall / nk
     t_fwd_full = tf * M / nj
     cores = oracle.threads()
@@ -304,7 +337,7 @@ def _time(torch, fn, steps, warmup):
     return (time.perf_counter() - t0) / steps
 
 
-def bench_c3(H, torch, W, args):
+def bench_c3(H, torch, W, args, summary=False):
     """Precision workload: N = 128^3, M = 2^23 (half uniform, half in 64
     Gaussian clusters), m = 4; step = set_points + adjoint.  float32 against
     the float64 GPU path over all of I_N, and both against the oracle on
@@ -344,7 +377,15 @@ def bench_c3(H, torch, W, args):
     e64 = oracle.rel_l2(res["f64"]["out"].reshape(-1)[kidx], ref64)
     e32_64 = oracle.rel_l2(res["f32"]["out"].reshape(-1), res["f64"]["out"].reshape(-1))
     r32 = res["f32"]
-    sp_ms = r32["phases"].get("spread", 0.0)
+    if summary:
+        return {"workload": "N=128^3, M=2^23 (half in 64 Gaussian clusters), m=4; step = set_points + adjoint",
+                "f32_ms_per_step": round(r32["ms"], 4), "f64_ms_per_step": round(res["f64"]["ms"], 4),
+                "f32_points_per_s": round(Mp / (r32["ms"] * 1e-3), 1),
+                "fp32_speedup_over_fp64_equal_m": round(res["f64"]["ms"] / r32["ms"], 3),
+                "rel_l2_f32_vs_f64_gpu_all_IN": float("%.3e" % e32_64),
+                "rel_l2_vs_oracle_sampled": {"f32": float("%.3e" % e32), "f64": float("%.3e" % e64), "k": 64},
+                "phases_f32_ms": {k: round(v, 4) for k, v in r32["phases"].items()},
+                "phases_f64_ms": {k: round(v, 4) for k, v in res["f64"]["phases"].items()}}
     return {
         "metric": METRIC, "value": round(Mp / (r32["ms"] * 1e-3), 1), "unit": "points/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(r32["ms"], 4), "higher_is_better": True,
@@ -360,7 +401,7 @@ def bench_c3(H, torch, W, args):
     }
 
 
-def bench_c4(H, torch, W, args):
+def bench_c4(H, torch, W, args, summary=False):
     """Batching workload: 256 independent adjoints (M log-uniform in
     [1e3, 1e6], N in {32, 48, 64, 96}^3), float32, m = 4, one launch per
     phase; the adjoint captured in a HIP graph and replayed."""
@@ -377,6 +418,11 @@ def bench_c4(H, torch, W, args):
         t_tune = time.perf_counter()
         plan.autotune()  # bin sizes (tile, slab, threads) chosen on these points
         t_tune = time.perf_counter() - t_tune
+        # the choice is in the tuning cache now: a second tuning of the same
+        # batch shape reads it instead of timing the candidates
+        t_cached = time.perf_counter()
+        plan.autotune()
+        t_cached = time.perf_counter() - t_cached
         t_sp = _time(torch, lambda: plan.set_points(x), max(2, args.steps // 4), 1)
         out = plan.adjoint(f)
         t_eager = _time(torch, lambda: plan.adjoint(f, out=out), args.steps, args.warmup)
@@ -390,6 +436,14 @@ def bench_c4(H, torch, W, args):
         t_graph = _time(torch, plan.replay, args.steps, args.warmup)
         diff = (gout - out).abs().max().item() / max(out.abs().max().item(), 1e-30)
     Mt = int(sum(Ms))
+    if summary:
+        return {"workload": "256 adjoints, M log-uniform in [1e3, 1e6], N in {32,48,64,96}^3, f32, m=4; "
+                            "step = one graph-replayed batched adjoint",
+                "ms_per_step": round(t_graph * 1e3, 4), "points_per_s": round(Mt / t_graph, 1),
+                "M_total": Mt, "eager_ms_per_step": round(t_eager * 1e3, 4),
+                "set_points_ms": round(t_sp * 1e3, 4), "tiles": list(plan.tiles),
+                "autotune_s": round(t_tune, 2), "autotune_cached_s": round(t_cached, 3),
+                "graph_vs_eager_max_rel_diff": float("%.3e" % diff), "phases_ms": phases}
     return {
         "metric": METRIC, "value": round(Mt / t_graph, 1), "unit": "points/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(t_graph * 1e3, 4),
@@ -398,12 +452,12 @@ def bench_c4(H, torch, W, args):
                                "complex64, m=4, autotuned tiling; step = one graph-replayed batched adjoint (points already set)",
                    "B": 256, "M_total": Mt, "tiles": list(plan.tiles)},
         "eager_ms_per_step": round(t_eager * 1e3, 4), "set_points_ms": round(t_sp * 1e3, 4),
-        "autotune_s": round(t_tune, 2),
+        "autotune_s": round(t_tune, 2), "autotune_cached_s": round(t_cached, 3),
         "graph_vs_eager_max_rel_diff": float("%.3e" % diff), "phases_ms": phases,
     }
 
 
-def bench_c5(H, torch, W, args):
+def bench_c5(H, torch, W, args, summary=False):
     """Differentiation workload: reciprocal Ewald energy and forces of a
     fluorite lattice of 24^3 cells (165,888 ions, displacements std 0.01 r0),
     N = 128^3; step = set_points + adjoint (S) + energy/gbar + backward."""
@@ -433,6 +487,15 @@ def bench_c5(H, torch, W, args):
         torch.cuda.empty_cache()
     fdiff = np.abs(out["f32"]["F"] - out["f64"]["F"]).max() / np.abs(out["f64"]["F"]).max()
     nion = int(r.shape[0])
+    if summary:
+        return {"workload": "Ewald reciprocal energy + forces, fluorite 24^3 cells (165,888 ions), N=128^3; "
+                            "step = set_points + adjoint + Eq. (12) + backward",
+                "f64_m8_ms_per_step": round(out["f64"]["ms"], 4), "f32_m4_ms_per_step": round(out["f32"]["ms"], 4),
+                "f64_ions_per_s": round(nion / (out["f64"]["ms"] * 1e-3), 1),
+                "tiles_f64": out["f64"]["tiles"], "tiles_f32": out["f32"]["tiles"],
+                "autotune_s": {"f64": out["f64"]["tune_s"], "f32": out["f32"]["tune_s"]},
+                "forces_f32_vs_f64_max_rel": float("%.3e" % fdiff),
+                "phases_f64_ms": out["f64"]["phases"], "phases_f32_ms": out["f32"]["phases"]}
     return {
         "metric": METRIC, "value": round(nion / (out["f64"]["ms"] * 1e-3), 1), "unit": "ions/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(out["f64"]["ms"], 4),
@@ -456,6 +519,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-secondary", action="store_true",
+                    help="skip the precision, batching and Ewald summaries of the default line")
     ap.add_argument("--copy-calib", action="store_true",
                     help="run a 1 GiB device copy first (counter calibration for rocprofv3 --pmc runs)")
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -476,6 +541,7 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    import numpy as np  # noqa: F401
     import torch
 
     import workloads as W
@@ -484,6 +550,11 @@ def main():
     if not torch.cuda.is_available():
         log("no GPU visible")
         sys.exit(1)
+    if not os.environ.get("HPNFFT_TUNE_CACHE"):
+        # the autotuner's cache for this run (a fresh file: every choice is
+        # timed once, then read back by later tunings of the same shape)
+        import tempfile
+        os.environ["HPNFFT_TUNE_CACHE"] = os.path.join(tempfile.mkdtemp(prefix="hpnfft_"), "tune.json")
     if args.workload != "c2":
         fn = {"c3": bench_c3, "c4": bench_c4, "c5": bench_c5}[args.workload]
         print(json.dumps(fn(H, torch, W, args)), flush=True)
@@ -492,15 +563,19 @@ def main():
     log("workload ready: N=%s M=%d" % (N, M))
     if args.copy_calib:
         copy_calibration(torch)
+    copy_gbs = hbm_copy_gbs(torch, H)
+    log("streaming copy: %.1f GB/s" % copy_gbs)
     gpu = {}
     gpu["f32_m4"] = run_path(H, torch, W, data, "f32", 4, args.steps, args.warmup)
     log("f32 m=4: %.3f ms/step" % gpu["f32_m4"]["ms_per_step"])
     if not args.no_fp64:
+        gpu["f64_m4"] = run_path(H, torch, W, data, "f64", 4, max(3, args.steps // 2), args.warmup)
+        log("f64 m=4: %.3f ms/step" % gpu["f64_m4"]["ms_per_step"])
         gpu["f64_m8"] = run_path(H, torch, W, data, "f64", 8, max(3, args.steps // 2), args.warmup)
         log("f64 m=8: %.3f ms/step" % gpu["f64_m8"]["ms_per_step"])
 
     main_res = gpu["f32_m4"]
-    table, roof, spread_gbs = summarize(main_res, "f32", 4)
+    table, roof, spread_gbs = summarize(main_res, "f32", 4, copy_gbs)
     out = {
         "metric": METRIC,
         "value": round(M / (main_res["ms_per_step"] * 1e-3), 1),
@@ -518,18 +593,36 @@ def main():
                                "Kaiser-Bessel m=4; step = set_points + adjoint (Eq. 5) + forward (Eq. 6)",
                    "N": list(N), "M": M, "m": 4, "sigma": 2.0, "tiles": list(main_res["tiles"])},
         "roofline": roof,
+        "hbm_copy_gbs": round(copy_gbs, 1),
         "spread_gbs_algorithmic": None if spread_gbs is None else round(spread_gbs, 1),
+        "spread_hbm_frac": None if spread_gbs is None else round(spread_gbs / PEAK_HBM_GBS, 4),
+        "spread_hbm_frac_of_copy": None if spread_gbs is None else round(spread_gbs / copy_gbs, 4),
+        "spread_bytes_note": "M (d+2) s + n^3 2 s per launch (points and values in, grid out once)",
         "phases": table,
     }
     if "f64_m8" in gpu:
-        r64 = gpu["f64_m8"]
-        t64, roof64, sp64 = summarize(r64, "f64", 8)
-        out["fp64_m8"] = {"value": round(M / (r64["ms_per_step"] * 1e-3), 1), "unit": "points/s",
-                          "ms_per_step": round(r64["ms_per_step"], 4), "dtype": "f64",
-                          "tiles": list(r64["tiles"]), "roofline": roof64,
-                          "spread_gbs_algorithmic": None if sp64 is None else round(sp64, 1),
-                          "phases": t64}
-        out["fp32_speedup_over_fp64"] = round(r64["ms_per_step"] / main_res["ms_per_step"], 3)
+        for key in ("f64_m8", "f64_m4"):
+            r64 = gpu[key]
+            mm = int(key[-1])
+            t64, roof64, sp64 = summarize(r64, "f64", mm, copy_gbs)
+            out["fp64_m%d" % mm] = {"value": round(M / (r64["ms_per_step"] * 1e-3), 1), "unit": "points/s",
+                                    "ms_per_step": round(r64["ms_per_step"], 4), "dtype": "f64", "m": mm,
+                                    "tiles": list(r64["tiles"]), "roofline": roof64,
+                                    "spread_gbs_algorithmic": None if sp64 is None else round(sp64, 1),
+                                    "phases": t64}
+        # E1 speed-up at equal M, N and m; the m = 8 ratio is the 1e-12 path's
+        out["fp32_speedup_over_fp64_equal_m"] = round(gpu["f64_m4"]["ms_per_step"] / main_res["ms_per_step"], 3)
+        out["f32_m4_over_f64_m8"] = round(gpu["f64_m8"]["ms_per_step"] / main_res["ms_per_step"], 3)
+        a32 = main_res["fhat"].reshape(-1).astype(np.complex128)
+        o32 = main_res["fout"].astype(np.complex128)
+        out["rel_l2_f32_vs_f64m8_gpu_all"] = {
+            "adjoint_all_IN": float("%.3e" % rel(a32, gpu["f64_m8"]["fhat"].reshape(-1))),
+            "forward_all_points": float("%.3e" % rel(o32, gpu["f64_m8"]["fout"]))}
+    if not args.no_secondary:
+        for name, fn in (("c3", bench_c3), ("c4", bench_c4), ("c5", bench_c5)):
+            t0 = time.perf_counter()
+            out[name] = fn(H, torch, W, args, summary=True)
+            log("%s: %.1f s" % (name, time.perf_counter() - t0))
     if not args.no_cpu_baseline:
         base, errs = cpu_baseline(data, gpu)
         out["cpu_baseline"] = base
@@ -537,6 +630,12 @@ def main():
     else:
         out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)
+
+
+def rel(a, b) -> float:
+    """Eq. (9) relative l2 of a against b (host arrays)."""
+    import numpy as np
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
 if __name__ == "__main__":

@@ -46,8 +46,22 @@ extern "C" {
 #define HPNFFT_EHIP     (-4)  /* a HIP runtime call failed                           */
 #define HPNFFT_ESTATE   (-5)  /* call out of order (e.g. transform before set_points)*/
 
-/* ---- window (Section 2: a window well localised in space and frequency) */
+/* ---- window (Section 2: a window well localised in space and frequency;
+ * Section 4 compares these four).  In grid units t = n x - l, each
+ * normalised to phi(0) = 1 and truncated to |t| <= m, with the Scaling
+ * step's divisor D(k) = its Fourier transform at k/n cycles per cell
+ * (NFFT literature: Potts, Steidl, Tasche 2001; Keiner, Kunis, Potts 2009):
+ *   KAISER_BESSEL  sinh(b r)/r, r = sqrt(m^2 - t^2), b = pi (2 - 1/sigma);
+ *                  D ~ I0(m sqrt(b^2 - (2 pi k/n)^2))
+ *   GAUSSIAN       exp(-t^2/g), g = 2 sigma m / ((2 sigma - 1) pi);
+ *                  D = sqrt(pi g) exp(-g (pi k/n)^2)
+ *   BSPLINE        centred cardinal B-spline of order 2m;  D ~ sinc(pi k/n)^2m
+ *   SINC_POWER     sinc(beta t)^2m, beta = pi (2 sigma - 1)/(2 m sigma);
+ *                  D = (pi/beta) M_2m(pi k/(n beta)), M_2m the B-spline */
 #define HPNFFT_KAISER_BESSEL 0
+#define HPNFFT_GAUSSIAN      1
+#define HPNFFT_BSPLINE       2
+#define HPNFFT_SINC_POWER    3
 
 /* ---- arithmetic precision of the transform -------------------------- */
 #define HPNFFT_F64 0          /* complex128 values, FP64 grid, FFT and sums     */
@@ -69,9 +83,10 @@ const char *hpnfft_strerror(int status);
  *   N[d]       bandwidth, each N_t even and >= 2 (Section 1)
  *   M          number of points, >= 1
  *   sigma      oversampling factor; n_t = sigma * N_t must be an even integer
- *              of the form 2^a 3^b with 2m <= n_t <= 1024
- *   m          window cut-off: 2m grid cells per dimension, 1 <= m <= 8
- *   window     HPNFFT_KAISER_BESSEL
+ *              of the form 2^a 3^b 5^c 7^d with 2m <= n_t <= 1024
+ *   m          window cut-off: 2m grid cells per dimension, 1 <= m <= 15
+ *   window     HPNFFT_KAISER_BESSEL, HPNFFT_GAUSSIAN, HPNFFT_BSPLINE or
+ *              HPNFFT_SINC_POWER
  *   precision  HPNFFT_F64 or HPNFFT_F32
  *   flags      0 or HPNFFT_WITH_GRADIENT
  * The plan starts without a workspace and without points.
@@ -174,6 +189,19 @@ int hpnfft_ewald_real(const double *r, const double *q, int64_t M, double L, dou
 int hpnfft_autotune(hpnfft_plan plan, void *scratch_f, void *scratch_fhat,
                     int *tile, int *slab, int *threads);
 
+/* Host-side domain check (no GPU needed): x is HOST memory, M x d float64
+ * row-major.  Returns EDOMAIN if any coordinate lies outside [-1/2, 1/2) or
+ * is not finite (Section 1 defines the points on that half-open box), and
+ * writes the first offending point's index to *first_bad (-1 if none; may be
+ * NULL).  EINVAL for d outside 1..3, M < 0 or a NULL x with M > 0. */
+int hpnfft_check_points(const double *x, int64_t M, int d, int64_t *first_bad);
+
+/* Streaming device-to-device copy of `bytes` bytes on `stream` (a
+ * hipStream_t), for measuring the achievable HBM rate that the transform
+ * kernels are compared against.  Both pointers must be 16-byte aligned
+ * (else EINVAL); the ranges must not overlap.  Asynchronous. */
+int hpnfft_copy(void *dst, const void *src, size_t bytes, void *stream);
+
 /* Oversampled grid size n (d values) and points count. */
 int hpnfft_plan_info(hpnfft_plan plan, int64_t *n_out, int64_t *M_out);
 
@@ -231,15 +259,17 @@ int hpnfft_profile_read(hpnfft_plan plan, double *ms, int64_t *counts);
 const char *hpnfft_phase_name(int phase);
 
 /* ---- host-only helpers (no GPU needed) ------------------------------ */
-/* Kaiser-Bessel window in grid units t = n x - l, normalised to phi(0) = 1:
- *   phi(t) = sinh(b r) / (r sinh(b m) / m), r = sqrt(m^2 - t^2), b = pi(2 - 1/sigma),
- * and its derivative dphi/dt, for |t| <= m (0 beyond).  dphi may be NULL. */
-int hpnfft_window_eval(int m, double sigma, int64_t count, const double *t,
+/* Window `window` (HPNFFT_KAISER_BESSEL .. HPNFFT_SINC_POWER) with cut-off
+ * m (1..15) in grid units t = n x - l, normalised to phi(0) = 1 and
+ * truncated to |t| <= m (see the window list above), and its derivative
+ * dphi/dt, at `count` points t (host arrays).  dphi may be NULL. */
+int hpnfft_window_eval(int window, int m, double sigma, int64_t count, const double *t,
                        double *phi, double *dphi);
-/* Roll-off factors 1/c_k for k = -N/2 .. N/2-1 (N values) of one dimension
- * with grid size n: c_k = n * phihat(k), the Fourier coefficient of the
- * periodised window scaled as above (Section 2, "Scaling"). */
-int hpnfft_window_rolloff(int m, double sigma, int64_t n, int64_t N, double *out);
+/* Roll-off factors 1/D(k) for k = -N/2 .. N/2-1 (N values; N = 1: k = 0) of
+ * one dimension with grid size n, D(k) being the Fourier transform of the
+ * normalised window at k/n cycles per cell: the divisor of the Scaling step
+ * (Section 2). */
+int hpnfft_window_rolloff(int window, int m, double sigma, int64_t n, int64_t N, double *out);
 
 #ifdef __cplusplus
 }

@@ -60,6 +60,10 @@ def _load():
             lib.oracle_ewald_recip_forces.argtypes = [ctypes.c_int64, _f64p, _f64p, ctypes.c_double,
                                                       ctypes.c_double, ctypes.c_int, _f64p, _f64p]
             lib.oracle_ewald_recip_forces.restype = ctypes.c_int
+            lib.oracle_ewald_recip_sel.argtypes = [ctypes.c_int64, _f64p, _f64p, ctypes.c_double,
+                                                   ctypes.c_double, ctypes.c_int, ctypes.c_int64, _i64p,
+                                                   _f64p, _f64p]
+            lib.oracle_ewald_recip_sel.restype = ctypes.c_double
             lib.oracle_rel_l2.argtypes = [ctypes.c_int64, _f64p, _f64p]
             lib.oracle_rel_l2.restype = ctypes.c_double
             lib.oracle_threads.argtypes = []
@@ -191,6 +195,21 @@ def ewald_recip_forces(r, q, L, alpha, kmax):
     _load().oracle_ewald_recip_forces(q.size, _p(r), _p(q), float(L), float(alpha), int(kmax),
                                       _p(S), _p(F))
     return F
+
+
+def ewald_recip_selected(r, q, L, alpha, kmax, sel):
+    """Eq. (12) energy (self term included) and the forces of the ions listed
+    in ``sel`` only.  Returns (U, F[len(sel), 3], S) with S the structure
+    factors over the cube |n_t| <= kmax (complex, n_0 slowest)."""
+    r = np.ascontiguousarray(np.asarray(r, dtype=np.float64))
+    q = np.ascontiguousarray(np.asarray(q, dtype=np.float64))
+    sel = np.ascontiguousarray(np.asarray(sel, dtype=np.int64))
+    side = 2 * int(kmax) + 1
+    S = np.empty(2 * side ** 3, dtype=np.float64)
+    F = np.empty((sel.size, 3), dtype=np.float64)
+    U = _load().oracle_ewald_recip_sel(q.size, _p(r), _p(q), float(L), float(alpha), int(kmax), sel.size,
+                                       _p(sel, _i64p), _p(S), _p(F))
+    return U, F, S.view(np.complex128)
 
 
 def threads() -> int:

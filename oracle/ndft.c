@@ -338,6 +338,72 @@ int oracle_ewald_recip_forces(int64_t M, const double *r, const double *q,
     return 0;
 }
 
+/* Eq. (12) energy and the forces of selected ions only, for lattices whose */
+/* full force set is too costly to evaluate directly.  Same sums as the two  */
+/* functions above: S(n) over the cube |n_t| <= kmax from all M ions (stored */
+/* in S, 2 (2 kmax + 1)^3 doubles), the energy of Eq. (12) including the     */
+/* self term, and F for the nsel ions listed in sel (forces: nsel x 3).      */
+double oracle_ewald_recip_sel(int64_t M, const double *r, const double *q,
+                              double L, double alpha, int kmax,
+                              int64_t nsel, const int64_t *sel,
+                              double *S, double *forces)
+{
+    int64_t side = 2 * (int64_t)kmax + 1;
+    int64_t nk = side * side * side;
+    double total = 0.0;
+#pragma omp parallel for schedule(dynamic, 16) reduction(+:total)
+    for (int64_t lin = 0; lin < nk; ++lin) {
+        int64_t n0 = lin / (side * side) - kmax;
+        int64_t n1 = (lin / side) % side - kmax;
+        int64_t n2 = lin % side - kmax;
+        nsum sr = {0, 0}, si = {0, 0};
+        for (int64_t i = 0; i < M; ++i) {
+            double ph = frac_prod((double)n0, r[3 * i] / L)
+                      + frac_prod((double)n1, r[3 * i + 1] / L)
+                      + frac_prod((double)n2, r[3 * i + 2] / L);
+            double c, s;
+            cis_cycles(ph, -1.0, &c, &s);
+            nsum_add(&sr, q[i] * c);
+            nsum_add(&si, q[i] * s);
+        }
+        double Sr = nsum_get(&sr), Si = nsum_get(&si);
+        S[2 * lin] = Sr;
+        S[2 * lin + 1] = Si;
+        if (n0 == 0 && n1 == 0 && n2 == 0) continue;
+        double n2sum = (double)(n0 * n0 + n1 * n1 + n2 * n2);
+        double w = exp(-M_PI * M_PI * n2sum / (alpha * L * alpha * L)) / n2sum;
+        total += w * (Sr * Sr + Si * Si) / (2.0 * M_PI * L);
+    }
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t a = 0; a < nsel; ++a) {
+        int64_t i = sel[a];
+        nsum fx[3] = {{0, 0}, {0, 0}, {0, 0}};
+        for (int64_t lin = 0; lin < nk; ++lin) {
+            int64_t nv[3];
+            nv[0] = lin / (side * side) - kmax;
+            nv[1] = (lin / side) % side - kmax;
+            nv[2] = lin % side - kmax;
+            if (nv[0] == 0 && nv[1] == 0 && nv[2] == 0) continue;
+            double n2sum = (double)(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
+            double w = exp(-M_PI * M_PI * n2sum / (alpha * L * alpha * L)) / n2sum;
+            double ph = frac_prod((double)nv[0], r[3 * i] / L)
+                      + frac_prod((double)nv[1], r[3 * i + 1] / L)
+                      + frac_prod((double)nv[2], r[3 * i + 2] / L);
+            double c, s;
+            cis_cycles(ph, -1.0, &c, &s);
+            double pim = S[2 * lin] * s - S[2 * lin + 1] * c;
+            for (int t = 0; t < 3; ++t) {
+                double dre = 2.0 * M_PI * (double)nv[t] * q[i] * pim / L;
+                nsum_add(&fx[t], -w * 2.0 * dre / (2.0 * M_PI * L));
+            }
+        }
+        for (int t = 0; t < 3; ++t) forces[3 * a + t] = nsum_get(&fx[t]);
+    }
+    double self = 0.0;
+    for (int64_t i = 0; i < M; ++i) self += q[i] * q[i];
+    return total - alpha / sqrt(M_PI) * self;
+}
+
 /* Eq. (9): relative l2 error ||a - s|| / ||s|| over n complex values. */
 double oracle_rel_l2(int64_t n, const double *a, const double *s)
 {

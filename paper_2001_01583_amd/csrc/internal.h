@@ -4,10 +4,12 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "window.h"
+
 namespace hpnfft {
 
 constexpr int kWave = 64;          // CDNA wavefront width
-constexpr int kMaxM2 = 16;         // 2m <= 16  (m <= 8)
+constexpr int kMaxM2 = 30;         // 2m <= 30  (m <= 15)
 constexpr int kMaxN = 1024;        // largest oversampled grid edge
 constexpr int kLdsBytes = 160 * 1024;  // gfx950 local data share per CU
 
@@ -155,12 +157,13 @@ enum Pass { P_ADJ0 = 0, P_ADJ1, P_ADJ2, P_FWD0, P_FWD1, P_FWD2, P_COUNT };
 template <typename R> struct Launch;
 
 hipError_t launch_zero(void *p, size_t bytes, hipStream_t s);
+hipError_t launch_copy(void *dst, const void *src, size_t bytes, int cus, hipStream_t s);
 hipError_t launch_bin_count(const double *x, const float *xf32, long long M, const Xform &X, int T, int BW,
                             int *counts, int *rank, int *err, double *xs_out, hipStream_t s);
 hipError_t launch_scan(int *data, long long n, int *tmp, hipStream_t s);
 template <typename R>
 hipError_t launch_bin_scatter(const double *x, const float *xf32, long long M, const Xform &X, int T, int m,
-                              double b, double inv_peak, const double *poly, const int *cell_start, const int *rank, int *perm,
+                              const WindowParams &wp, const double *poly, const int *cell_start, const int *rank, int *perm,
                               int *ipos, unsigned char *rec, size_t rec_bytes, bool grad, hipStream_t s);
 template <typename R>
 hipError_t launch_gather(const void *f, const int *perm, long long total, R *fs, hipStream_t s);

@@ -120,8 +120,8 @@ __global__ __launch_bounds__(256) void k_bin_scatter(const double *__restrict__ 
                                                      int ntx, const int *__restrict__ cell_start,
                                                      const int *__restrict__ rank, int *__restrict__ perm,
                                                      int *__restrict__ ipos, unsigned char *__restrict__ rec,
-                                                     size_t rec_bytes, double b,
-                                                     double inv_peak, const double *__restrict__ poly)
+                                                     size_t rec_bytes, WindowParams wp,
+                                                     const double *__restrict__ poly)
 {
     constexpr int m = M2 / 2;
     constexpr int NW = 3 * M2;
@@ -153,8 +153,10 @@ __global__ __launch_bounds__(256) void k_bin_scatter(const double *__restrict__ 
 #pragma unroll
         for (int t = 0; t < M2; ++t) {
             const double dist = u[dim] + (double)(m - 1 - t);
-            w[dim * M2 + t] = (R)(poly ? horner<NC>(poly + t * NC, 2.0 * u[dim] - 1.0) : kb_phi(dist, m, b, inv_peak));
-            if constexpr (GRAD) dw[dim * M2 + t] = (R)((double)n[dim] * kb_dphi(dist, m, b, inv_peak));
+            double ph = 0.0, dph = 0.0;
+            if (!poly || GRAD) win_eval(wp, dist, &ph, GRAD ? &dph : nullptr);
+            w[dim * M2 + t] = (R)(poly ? horner<NC>(poly + t * NC, 2.0 * u[dim] - 1.0) : ph);
+            if constexpr (GRAD) dw[dim * M2 + t] = (R)((double)n[dim] * dph);
         }
     }
     // dim 0 into slot order, slot s = (tap + rot) mod 2m: a rotation by rot
@@ -330,23 +332,23 @@ hipError_t launch_bin_count(const double *x, const float *xf32, long long M, con
 template <typename R, int M2>
 static void scatter_m(const double *x, const float *xf32, long long M, const Xform &X, int T,
                       const int *cell_start, const int *rank, int *perm, int *ipos, unsigned char *rec,
-                      size_t rec_bytes, double b, double inv_peak, const double *poly, bool grad, hipStream_t s)
+                      size_t rec_bytes, const WindowParams &wp, const double *poly, bool grad, hipStream_t s)
 {
     const unsigned nb = (unsigned)((M + 255) / 256);
     auto k = grad ? k_bin_scatter<R, M2, true> : k_bin_scatter<R, M2, false>;
     hipLaunchKernelGGL(k, dim3(nb), dim3(256), 0, s, x, xf32, M, X.poff, X.n[0], X.n[1], X.n[2], T, X.ntx,
-                       cell_start, rank, perm, ipos, rec, rec_bytes, b, inv_peak, poly);
+                       cell_start, rank, perm, ipos, rec, rec_bytes, wp, poly);
 }
 
 template <typename R>
 hipError_t launch_bin_scatter(const double *x, const float *xf32, long long M, const Xform &X, int T, int m,
-                              double b, double inv_peak, const double *poly, const int *cell_start, const int *rank,
+                              const WindowParams &wp, const double *poly, const int *cell_start, const int *rank,
                               int *perm, int *ipos, unsigned char *rec, size_t rec_bytes, bool grad, hipStream_t s)
 {
     if (M <= 0) return hipSuccess;
     switch (m) {
 #define HPNFFT_SCATTER_CASE(MM) \
-    case MM: scatter_m<R, 2 * MM>(x, xf32, M, X, T, cell_start, rank, perm, ipos, rec, rec_bytes, b, inv_peak, poly, grad, s); break;
+    case MM: scatter_m<R, 2 * MM>(x, xf32, M, X, T, cell_start, rank, perm, ipos, rec, rec_bytes, wp, poly, grad, s); break;
         HPNFFT_SCATTER_CASE(1)
         HPNFFT_SCATTER_CASE(2)
         HPNFFT_SCATTER_CASE(3)
@@ -355,6 +357,13 @@ hipError_t launch_bin_scatter(const double *x, const float *xf32, long long M, c
         HPNFFT_SCATTER_CASE(6)
         HPNFFT_SCATTER_CASE(7)
         HPNFFT_SCATTER_CASE(8)
+        HPNFFT_SCATTER_CASE(9)
+        HPNFFT_SCATTER_CASE(10)
+        HPNFFT_SCATTER_CASE(11)
+        HPNFFT_SCATTER_CASE(12)
+        HPNFFT_SCATTER_CASE(13)
+        HPNFFT_SCATTER_CASE(14)
+        HPNFFT_SCATTER_CASE(15)
 #undef HPNFFT_SCATTER_CASE
     default: return hipErrorInvalidValue;
     }
@@ -362,10 +371,10 @@ hipError_t launch_bin_scatter(const double *x, const float *xf32, long long M, c
 }
 
 template hipError_t launch_bin_scatter<double>(const double *, const float *, long long, const Xform &, int, int,
-                                               double, double, const double *, const int *, const int *, int *, int *,
+                                               const WindowParams &, const double *, const int *, const int *, int *, int *,
                                                unsigned char *, size_t, bool, hipStream_t);
 template hipError_t launch_bin_scatter<float>(const double *, const float *, long long, const Xform &, int, int,
-                                              double, double, const double *, const int *, const int *, int *, int *,
+                                              const WindowParams &, const double *, const int *, const int *, int *, int *,
                                               unsigned char *, size_t, bool, hipStream_t);
 
 }  // namespace hpnfft

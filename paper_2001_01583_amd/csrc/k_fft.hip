@@ -5,7 +5,7 @@
 //
 // One pass transforms all pencils along one dimension.  A workgroup loads
 // `count` pencils (coalesced: a run of contiguous elements per pencil row),
-// runs a mixed-radix (8, 4, 2, 3) Stockham autosort FFT in LDS with FP64
+// runs a mixed-radix (8, 4, 2, 3, 5, 7) Stockham autosort FFT in LDS with FP64
 // twiddles (rounded once for the float path), and stores only the outputs the
 // next step needs.  The passes are HBM-bound; pruning keeps the traffic at
 // about 2.6 grid volumes per transform instead of 6.
@@ -89,6 +89,59 @@ template <int S, typename R> __device__ inline void dft3(C2<R> *v)
     v[2] = csub(a, b);
 }
 
+// Odd prime radix P (5 or 7) as a direct DFT: the P - 1 nontrivial outputs
+// pair up as k and P - k, which share the cosine sums of v[r] + v[P - r] and
+// the sine sums of v[r] - v[P - r] (cos and sin of 2 pi j / P below, j = 1 ..
+// (P - 1) / 2, to 20 digits).
+template <int P> struct RootsOf;
+template <> struct RootsOf<5> {
+    static constexpr double c[3] = {1.0, 0.30901699437494742410, -0.80901699437494742410};
+    static constexpr double s[3] = {0.0, 0.95105651629515357212, 0.58778525229247312917};
+};
+template <> struct RootsOf<7> {
+    static constexpr double c[4] = {1.0, 0.62348980185873353053, -0.22252093395631440429,
+                                    -0.90096886790241912624};
+    static constexpr double s[4] = {0.0, 0.78183148246802980871, 0.97492791218182360702,
+                                    0.43388373911755812048};
+};
+template <int P, int S, typename R> __device__ inline void dft_odd(C2<R> *v)
+{
+    constexpr int H = (P - 1) / 2;
+    C2<R> sp[H + 1], dm[H + 1];
+#pragma unroll
+    for (int r = 1; r <= H; ++r) {
+        sp[r] = cadd(v[r], v[P - r]);
+        dm[r] = csub(v[r], v[P - r]);
+    }
+    C2<R> out[P];
+    out[0] = v[0];
+#pragma unroll
+    for (int r = 1; r <= H; ++r) out[0] = cadd(out[0], sp[r]);
+#pragma unroll
+    for (int k = 1; k <= H; ++k) {
+        // exp(S 2 pi i r k / P) = cos(2 pi (rk mod P)/P) + i S sin(...)
+        C2<R> a = v[0], b = {R(0), R(0)};
+#pragma unroll
+        for (int r = 1; r <= H; ++r) {
+            int q = (r * k) % P;
+            const bool neg = q > H;     // sin(2 pi q / P) = -sin(2 pi (P - q) / P)
+            const int j = neg ? P - q : q;
+            const R cr = (R)RootsOf<P>::c[j];
+            const R sr = neg ? (R)(-RootsOf<P>::s[j]) : (R)RootsOf<P>::s[j];
+            a.x += cr * sp[r].x;
+            a.y += cr * sp[r].y;
+            b.x += sr * dm[r].x;
+            b.y += sr * dm[r].y;
+        }
+        // out[k] = a + i S b,  out[P - k] = a - i S b
+        const C2<R> ib = mul_is<S>(b);
+        out[k] = cadd(a, ib);
+        out[P - k] = csub(a, ib);
+    }
+#pragma unroll
+    for (int r = 0; r < P; ++r) v[r] = out[r];
+}
+
 // One Stockham stage of radix RAD for `count` pencils of length n.
 template <int RAD, int S, typename R>
 __device__ inline void stage(const C2<R> *__restrict__ src, C2<R> *__restrict__ dst, const C2<R> *tw,
@@ -112,6 +165,8 @@ __device__ inline void stage(const C2<R> *__restrict__ src, C2<R> *__restrict__ 
         if (RAD == 3) dft3<S>(v);
         if (RAD == 4) dft4<S>(v);
         if (RAD == 8) dft8<S>(v);
+        if (RAD == 5) dft_odd<5, S>(v);
+        if (RAD == 7) dft_odd<7, S>(v);
         int idx = (j / Ns) * Ns * RAD + k;
 #pragma unroll
         for (int r = 0; r < RAD; ++r) dp[idx + r * Ns] = v[r];
@@ -254,16 +309,19 @@ __global__ __launch_bounds__(kFftThreads) void k_fft(int pass, const Xform *__re
     }
     __syncthreads();
 
-    // ---- Stockham stages: radix 8 first, then 4, 2, 3 ----
+    // ---- Stockham stages: radix 8 first, then 4, 2, 3, 5, 7 ----
     C2<R> *cur = bufA, *nxt = bufB;
     int rem = n, Ns = 1;
     while (rem > 1) {
-        int rad = (rem % 8 == 0) ? 8 : (rem % 4 == 0) ? 4 : (rem % 2 == 0) ? 2 : 3;
+        int rad = (rem % 8 == 0) ? 8 : (rem % 4 == 0) ? 4 : (rem % 2 == 0) ? 2 : (rem % 3 == 0) ? 3
+                : (rem % 5 == 0) ? 5 : 7;
         switch (rad) {
         case 8: stage<8, S, R>(cur, nxt, tw, n, ld, cnt, Ns); break;
         case 4: stage<4, S, R>(cur, nxt, tw, n, ld, cnt, Ns); break;
         case 2: stage<2, S, R>(cur, nxt, tw, n, ld, cnt, Ns); break;
-        default: stage<3, S, R>(cur, nxt, tw, n, ld, cnt, Ns); break;
+        case 3: stage<3, S, R>(cur, nxt, tw, n, ld, cnt, Ns); break;
+        case 5: stage<5, S, R>(cur, nxt, tw, n, ld, cnt, Ns); break;
+        default: stage<7, S, R>(cur, nxt, tw, n, ld, cnt, Ns); break;
         }
         __syncthreads();
         C2<R> *t = cur;

@@ -27,6 +27,42 @@ hipError_t launch_zero(void *p, size_t bytes, hipStream_t s)
     return hipGetLastError();
 }
 
+// Streaming device copy (measurement helper: the achievable HBM rate of a
+// plain read + write, to set the other kernels' traffic against).  Each
+// thread moves four 16-byte units per round, all loads issued before the
+// stores; a grid of a few workgroups per compute unit strides over the
+// buffer.  A tail below 64 bytes is copied byte by byte by block 0.
+__global__ __launch_bounds__(256) void k_copy(const uint4 *__restrict__ src, uint4 *__restrict__ dst, size_t n16,
+                                              const unsigned char *__restrict__ stail,
+                                              unsigned char *__restrict__ dtail, size_t ntail)
+{
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i + 3 * stride < n16; i += 4 * stride) {
+        uint4 a = src[i], b = src[i + stride], c = src[i + 2 * stride], d = src[i + 3 * stride];
+        dst[i] = a;
+        dst[i + stride] = b;
+        dst[i + 2 * stride] = c;
+        dst[i + 3 * stride] = d;
+    }
+    for (; i < n16; i += stride) dst[i] = src[i];
+    if (blockIdx.x == 0)
+        for (size_t t = threadIdx.x; t < ntail; t += blockDim.x) dtail[t] = stail[t];
+}
+
+hipError_t launch_copy(void *dst, const void *src, size_t bytes, int cus, hipStream_t s)
+{
+    if (bytes == 0) return hipSuccess;
+    const size_t n16 = bytes / 16, ntail = bytes % 16;
+    size_t blocks = (n16 + 255) / 256;
+    const size_t cap = (size_t)(cus > 0 ? cus : 256) * 8;
+    if (blocks > cap) blocks = cap;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_copy, dim3((unsigned)blocks), dim3(256), 0, s, (const uint4 *)src, (uint4 *)dst, n16,
+                       (const unsigned char *)src + n16 * 16, (unsigned char *)dst + n16 * 16, ntail);
+    return hipGetLastError();
+}
+
 // Native two-component vector of a real type (one memory operation per
 // complex value).
 template <typename R> struct Cplx;

@@ -9,12 +9,18 @@
 // one launch over a combined work list (Section 3 decomposes one transform
 // into subcell transforms whose results add up, Eq. (8); independent
 // transforms batch the same way).
+#include <unistd.h>
+
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <new>
+#include <string>
 #include <vector>
 
 #include "hpnfft.h"
@@ -38,11 +44,12 @@ constexpr int kMinCap = 2048;
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
-bool is_2a3b(long v)
+// Grid edges the FFT passes factor: 2^a 3^b 5^c 7^d.
+bool is_smooth(long v)
 {
     if (v < 1) return false;
-    while (v % 2 == 0) v /= 2;
-    while (v % 3 == 0) v /= 3;
+    for (int p : {2, 3, 5, 7})
+        while (v % p == 0) v /= p;
     return v == 1;
 }
 
@@ -67,7 +74,8 @@ struct Layout {
 
 struct hpnfft_plan_s {
     int B = 0, m = 0, prec = 0, window = 0;
-    double sigma = 2.0, b = 0.0, inv_peak = 0.0;
+    double sigma = 2.0;
+    WindowParams wp{};
     unsigned flags = 0;
     std::vector<Xform> hx;
     std::vector<long long> keys;
@@ -79,8 +87,13 @@ struct hpnfft_plan_s {
     Layout L;
     bool have_ws = false, have_points = false;
     bool poly_ok = false;  // window polynomials uploaded (else direct evaluation)
+    // host tables (prepare_host_tables)
+    std::vector<double> h_roll, h_poly;
+    std::map<int, std::vector<unsigned char>> h_tw;
+    std::vector<FItem> h_fit[3];
     int nitems = 0;
     int cus = 256;
+    char arch[64] = "unknown";
     int maxn = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
@@ -106,11 +119,153 @@ struct hpnfft_plan_s {
 namespace {
 
 int hip_status(hipError_t e) { return e == hipSuccess ? HPNFFT_OK : HPNFFT_EHIP; }
+
+// Diagnostics on stderr when the environment variable HPNFFT_LOG is set to a
+// non-empty value other than "0" (read once).
+bool log_on()
+{
+    static int on = -1;
+    if (on < 0) {
+        const char *v = std::getenv("HPNFFT_LOG");
+        on = (v && *v && std::strcmp(v, "0") != 0) ? 1 : 0;
+    }
+    return on == 1;
+}
+void hlog(const char *fmt, ...)
+{
+    if (!log_on()) return;
+    va_list ap;
+    va_start(ap, fmt);
+    std::fputs("[hpnfft] ", stderr);
+    std::vfprintf(stderr, fmt, ap);
+    std::fputc('\n', stderr);
+    va_end(ap);
+}
+
+// ---- persistent autotuner cache -----------------------------------------
+// The file named by HPNFFT_TUNE_CACHE (none: no cache) is a small JSON
+// object, one entry per line:
+//   {"hpnfft_tune_cache": 1,
+//    "entries": {
+//     "<key>": [T, Zs, threads],
+//     ...
+//    }}
+// The key names everything the best tiling depends on: the device
+// architecture and compute-unit count, precision, cut-off, window, sigma,
+// the gradient flag, and per transform the grid edges and the point count
+// rounded down to a power of two (batches: a hash of that list).
+constexpr int kTuneCacheVersion = 1;
+
+const char *tune_cache_path()
+{
+    const char *v = std::getenv("HPNFFT_TUNE_CACHE");
+    return (v && *v) ? v : nullptr;
+}
+
+std::string tune_key(const hpnfft_plan_s *p)
+{
+    char head[256];
+    std::snprintf(head, sizeof(head), "v%d|%s|cu%d|%s|m%d|w%d|s%.6g|g%d|B%d", kTuneCacheVersion, p->arch,
+                  p->cus, p->prec == HPNFFT_F32 ? "f32" : "f64", p->m, p->window, p->sigma, p->grad() ? 1 : 0,
+                  p->B);
+    std::string list;
+    for (const Xform &X : p->hx) {
+        int mb = 0;
+        while ((2LL << mb) <= X.M) ++mb;
+        char e[96];
+        std::snprintf(e, sizeof(e), "|%dx%dx%d:M2^%d", X.n[0], X.n[1], X.n[2], mb);
+        list += e;
+    }
+    if (p->B == 1) return head + list;
+    unsigned long long h = 1469598103934665603ull;  // FNV-1a
+    for (unsigned char c : list) h = (h ^ c) * 1099511628211ull;
+    char e[40];
+    std::snprintf(e, sizeof(e), "|h%016llx", h);
+    return head + std::string(e);
+}
+
+// All entries of the cache file (empty if absent or unreadable).
+std::map<std::string, Tiling> tune_cache_read(const char *path)
+{
+    std::map<std::string, Tiling> out;
+    FILE *fp = std::fopen(path, "r");
+    if (!fp) return out;
+    char line[1024];
+    int version = -1;
+    while (std::fgets(line, sizeof(line), fp)) {
+        if (std::strstr(line, "\"hpnfft_tune_cache\"")) {
+            const char *c = std::strchr(line, ':');
+            if (c) version = std::atoi(c + 1);
+            continue;
+        }
+        const char *q0 = std::strchr(line, '"');
+        const char *q1 = q0 ? std::strchr(q0 + 1, '"') : nullptr;
+        const char *br = q1 ? std::strchr(q1, '[') : nullptr;
+        if (!br) continue;
+        Tiling t{};
+        if (std::sscanf(br, "[%d , %d , %d]", &t.T, &t.Zs, &t.threads) != 3) continue;
+        out[std::string(q0 + 1, q1)] = t;
+    }
+    std::fclose(fp);
+    if (version != kTuneCacheVersion) out.clear();
+    return out;
+}
+
+bool tune_cache_get(const std::string &key, Tiling *t)
+{
+    const char *path = tune_cache_path();
+    if (!path) return false;
+    auto all = tune_cache_read(path);
+    auto it = all.find(key);
+    if (it == all.end()) return false;
+    *t = it->second;
+    return true;
+}
+
+// Adds or replaces one entry; the file is rewritten through a temporary
+// file and a rename, so a concurrent reader sees the old or the new file.
+void tune_cache_put(const std::string &key, const Tiling &t)
+{
+    const char *path = tune_cache_path();
+    if (!path) return;
+    auto all = tune_cache_read(path);
+    all[key] = t;
+    std::string tmp = std::string(path) + ".tmp" + std::to_string((long long)getpid());
+    FILE *fp = std::fopen(tmp.c_str(), "w");
+    if (!fp) return;
+    std::fprintf(fp, "{\"hpnfft_tune_cache\": %d,\n \"entries\": {\n", kTuneCacheVersion);
+    size_t i = 0;
+    for (const auto &kv : all)
+        std::fprintf(fp, "  \"%s\": [%d, %d, %d]%s\n", kv.first.c_str(), kv.second.T, kv.second.Zs,
+                     kv.second.threads, ++i < all.size() ? "," : "");
+    std::fprintf(fp, " }}\n");
+    const bool ok = std::fclose(fp) == 0;
+    if (ok && std::rename(tmp.c_str(), path) == 0) {
+        hlog("autotune: cached %s -> T=%d Zs=%d threads=%d in %s", key.c_str(), t.T, t.Zs, t.threads, path);
+    } else {
+        std::remove(tmp.c_str());
+    }
+}
 #define HCHECK(x)                                                                                  \
     do {                                                                                           \
         hipError_t e_ = (x);                                                                       \
         if (e_ != hipSuccess) return HPNFFT_EHIP;                                                  \
     } while (0)
+
+// A captured graph holds the work-item count, grid sizes, LDS sizes and
+// workspace pointers of the moment it was recorded.  Every call that re-bins
+// the points or re-lays out the workspace drops it (after the stream has
+// finished any replay in flight); hpnfft_batch_launch then reports ESTATE
+// until the batch is captured again.
+void drop_graph(hpnfft_plan_s *p)
+{
+    if (!p->gexec && !p->graph) return;
+    hipStreamSynchronize(p->stream);
+    if (p->gexec) hipGraphExecDestroy(p->gexec);
+    if (p->graph) hipGraphDestroy(p->graph);
+    p->gexec = nullptr;
+    p->graph = nullptr;
+}
 
 bool tiling_fits(const hpnfft_plan_s *p, Tiling t)
 {
@@ -170,6 +325,9 @@ void build_layout(hpnfft_plan_s *p)
     };
     L.counters = take(256);
     L.setp = take(256);
+    // the float64 copy of the points sits at the same offset in every layout
+    // (it depends on the point count only), so a re-tiled plan keeps it
+    L.xs = take((size_t)p->Mtot * 24);
     size_t gbytes = 0;
     long long maxkeys = 0, maxM = 0, pairs = 0, maxF = 0;
     for (int b = 0; b < p->B; ++b) {
@@ -210,7 +368,6 @@ void build_layout(hpnfft_plan_s *p)
     L.perm = take((size_t)p->Mtot * 4);
     L.ipos = take((size_t)p->Mtot * 4);
     L.fs = take((size_t)p->Mtot * C);
-    L.xs = take((size_t)p->Mtot * 24);
     L.rec_bytes = rec_size(p->M2(), p->rbytes(), p->grad());
     L.rec = take((size_t)p->Mtot * L.rec_bytes);
     L.outs_bytes = (size_t)p->Mtot * C * (p->grad() ? 4 : 1);
@@ -259,16 +416,18 @@ void build_layout(hpnfft_plan_s *p)
 // v^k).  The window is analytic in t, so the interpolant converges fast: 10
 // coefficients reach ~1e-10 and 16-17 reach ~1e-14 of the peak.  The fit is
 // checked against direct evaluation on a fine grid; false if it misses tol.
-bool fit_window_poly(int m, double b, double ip, int nc, double tol, std::vector<double> &coef)
+bool fit_window_poly(const WindowParams &wp, int nc, double tol, std::vector<double> &coef)
 {
-    const int M2 = 2 * m, d = nc - 1;
+    const int m = wp.m, M2 = 2 * m, d = nc - 1;
     coef.assign((size_t)M2 * nc, 0.0);
     for (int t = 0; t < M2; ++t) {
         std::vector<long double> fv(nc), ch(nc), mono(nc, 0.0L), tkm1(nc, 0.0L), tk(nc, 0.0L), tn(nc);
         const long double pi = 3.141592653589793238462643383279502884L;
         for (int j = 0; j < nc; ++j) {
             const long double v = cosl(pi * (j + 0.5L) / nc);
-            fv[j] = kb_phi((double)((v + 1.0L) / 2.0L) + (m - 1 - t), m, b, ip);
+            double ph;
+            win_eval(wp, (double)((v + 1.0L) / 2.0L) + (m - 1 - t), &ph, nullptr);
+            fv[j] = ph;
         }
         for (int k = 0; k < nc; ++k) {
             long double a = 0.0L;
@@ -293,74 +452,59 @@ bool fit_window_poly(int m, double b, double ip, int nc, double tol, std::vector
             const double v = 2.0 * u - 1.0;
             double r = coef[(size_t)t * nc + d];
             for (int k = d - 1; k >= 0; --k) r = std::fma(r, v, coef[(size_t)t * nc + k]);
-            if (std::fabs(r - kb_phi(u + (m - 1 - t), m, b, ip)) > tol) return false;
+            double ph;
+            win_eval(wp, u + (m - 1 - t), &ph, nullptr);
+            if (std::fabs(r - ph) > tol) return false;
         }
     }
     return true;
 }
 
-int upload_tables(hpnfft_plan_s *p)
+// Host copies of the plan's constant tables, computed once at plan creation
+// (they depend on the sizes, the window and the precision, not on the tiling
+// or the workspace): roll-off factors, window polynomials, twiddles and the
+// FFT passes' work items.  upload_tables only copies them, so attaching a
+// workspace allocates nothing on the host.
+void prepare_host_tables(hpnfft_plan_s *p)
 {
-    const Layout &L = p->L;
-    // descriptors
-    for (int b = 0; b < p->B; ++b) {
-        Xform &X = p->hx[b];
-        X.grid = p->ws + L.grid_off[b];
-        X.tmpA = p->ws + L.tmpA_off[b];
-        X.tmpB = p->ws + L.tmpB_off[b];
-        double *r = p->at<double>(L.roll_off[b]);
-        X.roll[0] = r;
-        X.roll[1] = r + X.N[0];
-        X.roll[2] = r + X.N[0] + X.N[1];
-        for (int d = 0; d < 3; ++d) X.tw[d] = p->ws + L.tw_off.at(X.n[d]);
-        X.key_off = (long long)((L.key_off[b] - L.cell_start) / 4);
-    }
-    // roll-off factors 1/c_k (FP64)
+    p->h_roll.clear();
     for (int b = 0; b < p->B; ++b) {
         const Xform &X = p->hx[b];
-        std::vector<double> h;
         for (int d = 0; d < 3; ++d)
             for (int k = -X.N[d] / 2; k < X.N[d] / 2; ++k)
-                h.push_back(1.0 / kb_phihat(k, X.n[d], p->m, p->b, p->inv_peak));
-        HCHECK(hipMemcpyAsync(p->ws + L.roll_off[b], h.data(), h.size() * 8, hipMemcpyHostToDevice,
-                              p->stream));
-        HCHECK(hipStreamSynchronize(p->stream));
+                p->h_roll.push_back(1.0 / window_phihat(p->wp, k, X.n[d]));
     }
     // window polynomials for set_points (float32 tables: 10 coefficients;
     // float64: 17); without a good fit the tables are evaluated directly
-    {
-        const bool f32 = p->prec == HPNFFT_F32;
-        const int nc = f32 ? kPolyF32 : kPolyF64;
-        std::vector<double> coef;
-        p->poly_ok = fit_window_poly(p->m, p->b, p->inv_peak, nc, f32 ? 1e-9 : 5e-14, coef);
-        if (p->poly_ok) {
-            HCHECK(hipMemcpyAsync(p->ws + L.poly, coef.data(), coef.size() * 8, hipMemcpyHostToDevice, p->stream));
-            HCHECK(hipStreamSynchronize(p->stream));
-        }
-    }
+    const bool f32 = p->prec == HPNFFT_F32;
+    p->poly_ok = fit_window_poly(p->wp, f32 ? kPolyF32 : kPolyF64, f32 ? 1e-9 : 5e-14, p->h_poly);
     // twiddles exp(-2 pi i j / n), computed in FP64 (long double angle), rounded once for float
-    for (auto &kv : L.tw_off) {
-        int n = kv.first;
-        std::vector<double> w64(2 * (size_t)n);
-        for (int j = 0; j < n; ++j) {
-            long double a = -2.0L * 3.141592653589793238462643383279502884L * j / n;
-            w64[2 * j] = (double)cosl(a);
-            w64[2 * j + 1] = (double)sinl(a);
+    p->h_tw.clear();
+    for (int b = 0; b < p->B; ++b)
+        for (int d = 0; d < 3; ++d) {
+            const int n = p->hx[b].n[d];
+            if (p->h_tw.count(n)) continue;
+            std::vector<double> w64(2 * (size_t)n);
+            for (int j = 0; j < n; ++j) {
+                long double a = -2.0L * 3.141592653589793238462643383279502884L * j / n;
+                w64[2 * j] = (double)cosl(a);
+                w64[2 * j + 1] = (double)sinl(a);
+            }
+            std::vector<unsigned char> bytes;
+            if (f32) {
+                std::vector<float> w32(w64.begin(), w64.end());
+                bytes.assign(reinterpret_cast<unsigned char *>(w32.data()),
+                             reinterpret_cast<unsigned char *>(w32.data()) + w32.size() * 4);
+            } else {
+                bytes.assign(reinterpret_cast<unsigned char *>(w64.data()),
+                             reinterpret_cast<unsigned char *>(w64.data()) + w64.size() * 8);
+            }
+            p->h_tw[n] = std::move(bytes);
         }
-        if (p->prec == HPNFFT_F32) {
-            std::vector<float> w32(w64.begin(), w64.end());
-            HCHECK(hipMemcpyAsync(p->ws + kv.second, w32.data(), w32.size() * 4, hipMemcpyHostToDevice,
-                                  p->stream));
-        } else {
-            HCHECK(hipMemcpyAsync(p->ws + kv.second, w64.data(), w64.size() * 8, hipMemcpyHostToDevice,
-                                  p->stream));
-        }
-        HCHECK(hipStreamSynchronize(p->stream));
-    }
-    // FFT items
+    // FFT work items: `count` pencils per workgroup
     for (int d = 0; d < 3; ++d) {
-        std::vector<FItem> it;
-        it.reserve(L.nfit[d]);
+        std::vector<FItem> &it = p->h_fit[d];
+        it.clear();
         for (int b = 0; b < p->B; ++b) {
             const Xform &X = p->hx[b];
             int c = fft_count(X.n[d]);
@@ -376,13 +520,56 @@ int upload_tables(hpnfft_plan_s *p)
                 for (int i = 0; i < inner; i += c) it.push_back(FItem{b, 0, i, std::min(c, inner - i)});
             }
         }
-        if ((int)it.size() != L.nfit[d]) return HPNFFT_EINVAL;
-        HCHECK(hipMemcpyAsync(p->ws + L.fit[d], it.data(), it.size() * sizeof(FItem),
+    }
+}
+
+// Point the descriptors at the workspace p->ws (host copies only).
+void bind_descriptors(hpnfft_plan_s *p)
+{
+    const Layout &L = p->L;
+    for (int b = 0; b < p->B; ++b) {
+        Xform &X = p->hx[b];
+        X.grid = p->ws + L.grid_off[b];
+        X.tmpA = p->ws + L.tmpA_off[b];
+        X.tmpB = p->ws + L.tmpB_off[b];
+        double *r = p->at<double>(L.roll_off[b]);
+        X.roll[0] = r;
+        X.roll[1] = r + X.N[0];
+        X.roll[2] = r + X.N[0] + X.N[1];
+        for (int d = 0; d < 3; ++d) X.tw[d] = p->ws + L.tw_off.at(X.n[d]);
+        X.key_off = (long long)((L.key_off[b] - L.cell_start) / 4);
+    }
+}
+
+// Copy the tables and descriptors into the workspace p->ws.  No host or
+// device allocation: the host tables were prepared at plan creation.
+int upload_tables(hpnfft_plan_s *p)
+{
+    const Layout &L = p->L;
+    bind_descriptors(p);
+    size_t off = 0;
+    for (int b = 0; b < p->B; ++b) {
+        const Xform &X = p->hx[b];
+        const size_t cnt = (size_t)X.N[0] + X.N[1] + X.N[2];
+        HCHECK(hipMemcpyAsync(p->ws + L.roll_off[b], p->h_roll.data() + off, cnt * 8, hipMemcpyHostToDevice,
+                              p->stream));
+        off += cnt;
+    }
+    if (p->poly_ok)
+        HCHECK(hipMemcpyAsync(p->ws + L.poly, p->h_poly.data(), p->h_poly.size() * 8, hipMemcpyHostToDevice,
+                              p->stream));
+    for (auto &kv : L.tw_off) {
+        const std::vector<unsigned char> &t = p->h_tw.at(kv.first);
+        HCHECK(hipMemcpyAsync(p->ws + kv.second, t.data(), t.size(), hipMemcpyHostToDevice, p->stream));
+    }
+    for (int d = 0; d < 3; ++d) {
+        if ((int)p->h_fit[d].size() != L.nfit[d]) return HPNFFT_EINVAL;
+        HCHECK(hipMemcpyAsync(p->ws + L.fit[d], p->h_fit[d].data(), p->h_fit[d].size() * sizeof(FItem),
                               hipMemcpyHostToDevice, p->stream));
-        HCHECK(hipStreamSynchronize(p->stream));
     }
     HCHECK(hipMemcpyAsync(p->ws + L.xf, p->hx.data(), p->hx.size() * sizeof(Xform), hipMemcpyHostToDevice,
                           p->stream));
+    // the host sources must outlive the copies
     HCHECK(hipStreamSynchronize(p->stream));
     return HPNFFT_OK;
 }
@@ -455,12 +642,12 @@ int bin_points(hpnfft_plan_s *p, const double *x = nullptr, const float *x32 = n
                                 X.M, X, p->til.T, block_w(p->M2()), cs, p->at<int>(L.rank), setp, stored ? nullptr : xb, s));
         HCHECK(launch_scan(cs, p->keys[b], p->at<int>(L.scan_tmp), s));
         if (p->prec == HPNFFT_F32)
-            HCHECK(launch_bin_scatter<float>(xb, nullptr, X.M, X, p->til.T, p->m, p->b, p->inv_peak,
+            HCHECK(launch_bin_scatter<float>(xb, nullptr, X.M, X, p->til.T, p->m, p->wp,
                                              p->poly_ok ? p->at<double>(L.poly) : nullptr, cs,
                                              p->at<int>(L.rank), p->at<int>(L.perm), p->at<int>(L.ipos),
                                              p->at<unsigned char>(L.rec), L.rec_bytes, p->grad(), s));
         else
-            HCHECK(launch_bin_scatter<double>(xb, nullptr, X.M, X, p->til.T, p->m, p->b, p->inv_peak,
+            HCHECK(launch_bin_scatter<double>(xb, nullptr, X.M, X, p->til.T, p->m, p->wp,
                                               p->poly_ok ? p->at<double>(L.poly) : nullptr, cs,
                                               p->at<int>(L.rank), p->at<int>(L.perm), p->at<int>(L.ipos),
                                               p->at<unsigned char>(L.rec), L.rec_bytes, p->grad(), s));
@@ -593,9 +780,9 @@ int create_common(hpnfft_plan_s **out, int B, const int64_t *N, const int64_t *M
 {
     if (!out || B < 1 || !N || !M) return HPNFFT_EINVAL;
     *out = nullptr;
-    if (window != HPNFFT_KAISER_BESSEL) return HPNFFT_EINVAL;
+    if (window < HPNFFT_KAISER_BESSEL || window > HPNFFT_SINC_POWER) return HPNFFT_EINVAL;
     if (precision != HPNFFT_F64 && precision != HPNFFT_F32) return HPNFFT_EINVAL;
-    if (m < 1 || m > 8) return HPNFFT_EINVAL;
+    if (m < 1 || m > kMaxWindowM) return HPNFFT_EINVAL;
     if (flags & ~HPNFFT_WITH_GRADIENT) return HPNFFT_EINVAL;
     if (!(sigma >= 1.0) || !std::isfinite(sigma)) return HPNFFT_EINVAL;
     hpnfft_plan_s *p = new (std::nothrow) hpnfft_plan_s();
@@ -606,8 +793,7 @@ int create_common(hpnfft_plan_s **out, int B, const int64_t *N, const int64_t *M
     p->window = window;
     p->sigma = sigma;
     p->flags = flags;
-    p->b = kb_shape(sigma);
-    p->inv_peak = 1.0 / kb_peak(m, p->b);
+    p->wp = window_params(window, m, sigma);
     p->hx.resize(B);
     p->keys.resize(B);
     long long Mtot = 0, Ftot = 0;
@@ -620,7 +806,7 @@ int create_common(hpnfft_plan_s **out, int B, const int64_t *N, const int64_t *M
             if (Nt < 2 || Nt % 2 != 0 || Nt > kMaxN) { delete p; return HPNFFT_EINVAL; }
             double nv = sigma * (double)Nt;
             long nt = std::lround(nv);
-            if (std::fabs(nv - (double)nt) > 1e-9 * nv || nt % 2 != 0 || !is_2a3b(nt) || nt < 2 * m ||
+            if (std::fabs(nv - (double)nt) > 1e-9 * nv || nt % 2 != 0 || !is_smooth(nt) || nt < 2 * m ||
                 nt > kMaxN || nt < Nt) {
                 delete p;
                 return HPNFFT_EINVAL;
@@ -639,11 +825,26 @@ int create_common(hpnfft_plan_s **out, int B, const int64_t *N, const int64_t *M
     p->Mtot = Mtot;
     p->Ftot = Ftot;
     int dev = 0, cus = 0;
-    if (hipGetDevice(&dev) == hipSuccess &&
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
-        p->cus = cus;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+            p->cus = cus;
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+            // "gfx950:sramecc+:xnack-" -> "gfx950"
+            size_t k = 0;
+            while (k + 1 < sizeof(p->arch) && prop.gcnArchName[k] && prop.gcnArchName[k] != ':') {
+                p->arch[k] = prop.gcnArchName[k];
+                ++k;
+            }
+            p->arch[k] = 0;
+        }
+    }
     p->til = default_tiling(p);
     build_layout(p);
+    prepare_host_tables(p);
+    hlog("plan: B=%d m=%d %s sigma=%g first n=%dx%dx%d M=%lld tiles T=%d Zs=%d threads=%d workspace %zu B", B, m,
+         precision == HPNFFT_F32 ? "f32" : "f64", sigma, p->hx[0].n[0], p->hx[0].n[1], p->hx[0].n[2],
+         (long long)p->Mtot, p->til.T, p->til.Zs, p->til.threads, p->L.total);
     *out = p;
     return HPNFFT_OK;
 }
@@ -685,8 +886,7 @@ int hpnfft_plan_destroy(hpnfft_plan p)
     if (!p->recs.empty()) hipStreamSynchronize(p->stream);
     drop_records(p);
     for (hipEvent_t e : p->pool) hipEventDestroy(e);
-    if (p->gexec) hipGraphExecDestroy(p->gexec);
-    if (p->graph) hipGraphDestroy(p->graph);
+    drop_graph(p);
     if (p->res_ev) {
         hipEventSynchronize(p->res_ev);
         hipEventDestroy(p->res_ev);
@@ -711,6 +911,7 @@ int hpnfft_set_tiles(hpnfft_plan p, int tile, int slab, int threads)
     if (slab) t.Zs = slab;
     if (threads) t.threads = threads;
     if (!tiling_fits(p, t)) return HPNFFT_EINVAL;
+    drop_graph(p);
     p->til = t;
     build_layout(p);
     p->have_ws = false;
@@ -739,6 +940,7 @@ int hpnfft_set_workspace(hpnfft_plan p, void *dev_ptr, size_t bytes)
     if (!p || !dev_ptr) return HPNFFT_EINVAL;
     if (((uintptr_t)dev_ptr) % 256) return HPNFFT_EINVAL;
     if (bytes < p->L.total) return HPNFFT_ENOMEM;
+    drop_graph(p);
     p->ws = (char *)dev_ptr;
     p->ws_bytes = bytes;
     p->have_points = false;
@@ -751,6 +953,7 @@ static int set_points_any(hpnfft_plan p, const double *x, const float *x32)
 {
     if (!p || (!x && !x32)) return HPNFFT_EINVAL;
     if (!p->have_ws) return HPNFFT_ESTATE;
+    drop_graph(p);
     p->have_points = false;
     int rc;
     {
@@ -758,6 +961,7 @@ static int set_points_any(hpnfft_plan p, const double *x, const float *x32)
         rc = bin_points(p, x, x32);
     }
     p->have_points = rc == HPNFFT_OK;
+    hlog("set_points: status %d, %d work items, staging hint %d points", rc, p->nitems, p->til.cap_hint);
     return rc;
 }
 
@@ -816,6 +1020,31 @@ int hpnfft_ewald_real(const double *r, const double *q, int64_t M, double L, dou
                                         (hipStream_t)stream));
 }
 
+int hpnfft_check_points(const double *x, int64_t M, int d, int64_t *first_bad)
+{
+    if (first_bad) *first_bad = -1;
+    if (M < 0 || d < 1 || d > 3 || (M > 0 && !x)) return HPNFFT_EINVAL;
+    for (int64_t j = 0; j < M; ++j)
+        for (int t = 0; t < d; ++t) {
+            const double v = x[j * d + t];
+            if (!(v >= -0.5 && v < 0.5)) {  // NaN fails both comparisons
+                if (first_bad) *first_bad = j;
+                return HPNFFT_EDOMAIN;
+            }
+        }
+    return HPNFFT_OK;
+}
+
+int hpnfft_copy(void *dst, const void *src, size_t bytes, void *stream)
+{
+    if ((!dst || !src) && bytes) return HPNFFT_EINVAL;
+    if (((uintptr_t)dst | (uintptr_t)src) % 16) return HPNFFT_EINVAL;
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess)
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    return hip_status(launch_copy(dst, src, bytes, cus, (hipStream_t)stream));
+}
+
 int hpnfft_plan_info(hpnfft_plan p, int64_t *n_out, int64_t *M_out)
 {
     if (!p) return HPNFFT_EINVAL;
@@ -838,14 +1067,7 @@ int hpnfft_batch_capture(hpnfft_batch p, const void *f, void *fhat)
     if (!p || !f || !fhat) return HPNFFT_EINVAL;
     if (!p->have_points) return HPNFFT_ESTATE;
     if (!p->stream) return HPNFFT_EINVAL;  // capture needs a non-default stream
-    if (p->gexec) {
-        hipGraphExecDestroy(p->gexec);
-        p->gexec = nullptr;
-    }
-    if (p->graph) {
-        hipGraphDestroy(p->graph);
-        p->graph = nullptr;
-    }
+    drop_graph(p);
     // attribute setup outside the capture: one eager run; no timing events
     // inside the graph
     const unsigned prof = p->prof;
@@ -882,13 +1104,7 @@ int hpnfft_autotune(hpnfft_plan p, void *scratch_f, void *scratch_fhat, int *til
 {
     if (!p || !scratch_f || !scratch_fhat) return HPNFFT_EINVAL;
     if (!p->have_points) return HPNFFT_ESTATE;
-    // the stored float64 points survive re-layouts only if their offset is
-    // unchanged; keep a host copy instead (read before any candidate layout
-    // is built: p->L must still be the layout the points were stored with)
-    std::vector<double> hx((size_t)p->Mtot * 3);
-    HCHECK(hipMemcpyAsync(hx.data(), p->at<double>(p->L.xs), hx.size() * 8, hipMemcpyDeviceToHost,
-                          p->stream));
-    HCHECK(hipStreamSynchronize(p->stream));
+    drop_graph(p);
     // candidates that fit the attached workspace
     std::vector<Tiling> cand;
     for (int T : {4, 6, 8, 12, 16})
@@ -901,19 +1117,35 @@ int hpnfft_autotune(hpnfft_plan p, void *scratch_f, void *scratch_fhat, int *til
                 build_layout(p);
                 size_t need = p->L.total;
                 p->til = keep;
+                build_layout(p);
                 if (need <= p->ws_bytes) cand.push_back(t);
             }
+    // The stored float64 points sit at the same workspace offset in every
+    // layout (build_layout), so a candidate re-bins them where they are.
     auto install = [&](Tiling t) -> int {
         p->til = t;
         build_layout(p);
         int rc = upload_tables(p);
         if (rc) return rc;
-        HCHECK(hipMemcpyAsync(p->at<double>(p->L.xs), hx.data(), hx.size() * 8, hipMemcpyHostToDevice,
-                              p->stream));
         rc = bin_points(p, nullptr, nullptr);
         p->have_points = rc == HPNFFT_OK;
         return rc;
     };
+    const std::string key = tune_key(p);
+    Tiling cached{};
+    if (tune_cache_get(key, &cached)) {
+        bool ok = false;
+        for (const Tiling &t : cand) ok |= t.T == cached.T && t.Zs == cached.Zs && t.threads == cached.threads;
+        if (ok) {
+            hlog("autotune: cache hit %s -> T=%d Zs=%d threads=%d", key.c_str(), cached.T, cached.Zs,
+                 cached.threads);
+            int rc = install(cached);
+            if (tile) *tile = cached.T;
+            if (slab) *slab = cached.Zs;
+            if (threads) *threads = cached.threads;
+            return rc;
+        }
+    }
     Tiling best = p->til;
     double best_t = 1e30;
     hipEvent_t e0, e1;
@@ -941,6 +1173,7 @@ int hpnfft_autotune(hpnfft_plan p, void *scratch_f, void *scratch_fhat, int *til
         hipEventSynchronize(e1);
         float ms = 0;
         hipEventElapsedTime(&ms, e0, e1);
+        hlog("autotune: T=%d Zs=%d threads=%d %.4f ms per round", t.T, t.Zs, t.threads, ok ? ms / 3 : -1.0);
         if (ok && ms < best_t) {
             best_t = ms;
             best = t;
@@ -949,6 +1182,7 @@ int hpnfft_autotune(hpnfft_plan p, void *scratch_f, void *scratch_fhat, int *til
     hipEventDestroy(e0);
     hipEventDestroy(e1);
     int rc = install(best);
+    if (rc == HPNFFT_OK) tune_cache_put(key, best);
     if (tile) *tile = best.T;
     if (slab) *slab = best.Zs;
     if (threads) *threads = best.threads;
@@ -991,23 +1225,26 @@ const char *hpnfft_phase_name(int phase)
     return (phase >= 0 && phase < HPNFFT_NPHASES) ? names[phase] : "";
 }
 
-int hpnfft_window_eval(int m, double sigma, int64_t count, const double *t, double *phi, double *dphi)
+int hpnfft_window_eval(int window, int m, double sigma, int64_t count, const double *t, double *phi, double *dphi)
 {
-    if (m < 1 || m > 8 || !(sigma >= 1.0) || count < 0 || (count && (!t || !phi))) return HPNFFT_EINVAL;
-    double b = kb_shape(sigma), ip = 1.0 / kb_peak(m, b);
+    if (window < HPNFFT_KAISER_BESSEL || window > HPNFFT_SINC_POWER) return HPNFFT_EINVAL;
+    if (m < 1 || m > kMaxWindowM || !(sigma >= 1.0) || count < 0 || (count && (!t || !phi))) return HPNFFT_EINVAL;
+    const WindowParams w = window_params(window, m, sigma);
     for (int64_t i = 0; i < count; ++i) {
-        double a = std::fabs(t[i]);
-        phi[i] = a > m ? 0.0 : kb_phi(t[i], m, b, ip);
-        if (dphi) dphi[i] = a > m ? 0.0 : kb_dphi(t[i], m, b, ip);
+        double v, d;
+        win_eval(w, t[i], &v, &d);
+        phi[i] = v;
+        if (dphi) dphi[i] = d;
     }
     return HPNFFT_OK;
 }
 
-int hpnfft_window_rolloff(int m, double sigma, int64_t n, int64_t N, double *out)
+int hpnfft_window_rolloff(int window, int m, double sigma, int64_t n, int64_t N, double *out)
 {
-    if (m < 1 || m > 8 || !(sigma >= 1.0) || n < 2 || N < 2 || N > n || !out) return HPNFFT_EINVAL;
-    double b = kb_shape(sigma), ip = 1.0 / kb_peak(m, b);
-    for (int64_t k = -N / 2; k < N / 2; ++k) out[k + N / 2] = 1.0 / kb_phihat(k, n, m, b, ip);
+    if (window < HPNFFT_KAISER_BESSEL || window > HPNFFT_SINC_POWER) return HPNFFT_EINVAL;
+    if (m < 1 || m > kMaxWindowM || !(sigma >= 1.0) || n < 2 || N < 1 || N > n || !out) return HPNFFT_EINVAL;
+    const WindowParams w = window_params(window, m, sigma);
+    for (int64_t i = 0; i < N; ++i) out[i] = 1.0 / window_phihat(w, (long)(i - N / 2), (long)n);
     return HPNFFT_OK;
 }
 

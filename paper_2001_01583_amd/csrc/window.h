@@ -110,4 +110,142 @@ inline double kb_phihat(long k, long n, int m, double b, double inv_peak)
     return bessel_i0((double)m * sqrt(a)) * inv_peak;
 }
 
+// ---------------------------------------------------------------------------
+// The window family of the precision experiment (Section 4 names the
+// Gaussian, cardinal B-spline, sinc-power and Kaiser-Bessel windows).  Their
+// formulas follow the NFFT literature (Potts, Steidl and Tasche 2001; Keiner,
+// Kunis and Potts 2009), in grid units t = n x - l, each normalised to
+// phi(0) = 1, truncated to |t| <= m, with divisor D(k) = the continuous
+// Fourier transform of that normalised window at frequency k / n (cycles per
+// cell), which is what the Scaling step divides by:
+//   Gaussian     phi = exp(-t^2 / g),  g = 2 sigma m / ((2 sigma - 1) pi),
+//                D(k) = sqrt(pi g) exp(-g (pi k / n)^2)
+//   B-spline     phi = M_2m(t) / M_2m(0)  (centred cardinal B-spline of order
+//                2m, support [-m, m]),  D(k) = sinc(pi k / n)^2m / M_2m(0)
+//   sinc-power   phi = sinc(beta t)^2m,  beta = pi (2 sigma - 1) / (2 m sigma),
+//                D(k) = (pi / beta) M_2m(pi k / (n beta))
+//   Kaiser-Bessel  as above (kb_phi, kb_phihat).
+// sinc(x) = sin(x) / x.
+enum WindowKind { W_KAISER_BESSEL = 0, W_GAUSSIAN = 1, W_BSPLINE = 2, W_SINC_POWER = 3 };
+constexpr int kMaxWindowM = 15;
+
+struct WindowParams {
+    int kind, m;
+    double sigma;
+    double b;         // Kaiser-Bessel shape, Gaussian g, or sinc-power beta
+    double inv_peak;  // 1 / (unnormalised phi(0)): Kaiser-Bessel and B-spline
+};
+
+// Centred cardinal B-spline M_p(t) (support [-p/2, p/2]) and its derivative,
+// by the two-term recursion
+//   M_q(t) = ((q/2 + t) M_{q-1}(t + 1/2) + (q/2 - t) M_{q-1}(t - 1/2)) / (q - 1)
+// evaluated bottom-up on the half-integer shifts t + s/2 (no cancellation:
+// every term is non-negative).  p <= 2 kMaxWindowM.
+HPNFFT_HD void bspline_eval(int p, double t, double *val, double *der)
+{
+    // level q holds M_q(t + (p - q) / 2 - j) for j = 0 .. p - q
+    double a[2 * kMaxWindowM + 1];
+    for (int j = 0; j <= p - 1; ++j) {
+        const double u = t + 0.5 * (p - 1) - j;
+        a[j] = (u >= -0.5 && u < 0.5) ? 1.0 : 0.0;
+    }
+    double dlast = 0.0;
+    for (int q = 2; q <= p; ++q) {
+        if (q == p) dlast = a[0] - a[1];  // M_p' = M_{p-1}(t + 1/2) - M_{p-1}(t - 1/2)
+        for (int j = 0; j <= p - q; ++j) {
+            const double u = t + 0.5 * (p - q) - j;
+            a[j] = ((0.5 * q + u) * a[j] + (0.5 * q - u) * a[j + 1]) / (q - 1);
+        }
+    }
+    *val = a[0];
+    if (der) *der = p >= 2 ? dlast : 0.0;
+}
+
+HPNFFT_HD double sincd(double x) { return fabs(x) < 1e-8 ? 1.0 - x * x / 6.0 : sin(x) / x; }
+
+// Normalised window and its derivative d phi / dt at distance t (0 beyond m).
+HPNFFT_HD void win_eval(const WindowParams &w, double t, double *phi, double *dphi)
+{
+    const int m = w.m;
+    if (fabs(t) > (double)m * (1.0 + 1e-12)) {
+        *phi = 0.0;
+        if (dphi) *dphi = 0.0;
+        return;
+    }
+    switch (w.kind) {
+    case W_GAUSSIAN: {
+        const double v = exp(-t * t / w.b);
+        *phi = v;
+        if (dphi) *dphi = -2.0 * t / w.b * v;
+        return;
+    }
+    case W_BSPLINE: {
+        double v, d;
+        bspline_eval(2 * m, t, &v, &d);
+        *phi = v * w.inv_peak;
+        if (dphi) *dphi = d * w.inv_peak;
+        return;
+    }
+    case W_SINC_POWER: {
+        const double x = w.b * t;
+        const double sc = sincd(x);
+        double p1 = 1.0;  // sinc^(2m - 1)
+        for (int i = 0; i < 2 * m - 1; ++i) p1 *= sc;
+        *phi = p1 * sc;
+        if (dphi) {
+            // d/dx sinc(x) = (x cos x - sin x) / x^2, ~ -x/3 near 0
+            const double ds = fabs(x) < 1e-4 ? -x / 3.0 : (x * cos(x) - sin(x)) / (x * x);
+            *dphi = 2.0 * m * p1 * ds * w.b;
+        }
+        return;
+    }
+    default:
+        *phi = kb_phi(t, m, w.b, w.inv_peak);
+        if (dphi) *dphi = kb_dphi(t, m, w.b, w.inv_peak);
+        return;
+    }
+}
+
+// Parameters of a window of the family for cut-off m and oversampling sigma.
+inline WindowParams window_params(int kind, int m, double sigma)
+{
+    WindowParams w{kind, m, sigma, 0.0, 1.0};
+    switch (kind) {
+    case W_GAUSSIAN: w.b = 2.0 * sigma * m / ((2.0 * sigma - 1.0) * M_PI); break;
+    case W_BSPLINE: {
+        double v;
+        bspline_eval(2 * m, 0.0, &v, nullptr);
+        w.inv_peak = 1.0 / v;
+        break;
+    }
+    case W_SINC_POWER: w.b = M_PI * (2.0 * sigma - 1.0) / (2.0 * m * sigma); break;
+    default:
+        w.b = kb_shape(sigma);
+        w.inv_peak = 1.0 / kb_peak(m, w.b);
+        break;
+    }
+    return w;
+}
+
+// Divisor D(k) of the Scaling step on a grid of n cells (host only).
+inline double window_phihat(const WindowParams &w, long k, long n)
+{
+    const double x = M_PI * (double)k / (double)n;
+    switch (w.kind) {
+    case W_GAUSSIAN: return sqrt(M_PI * w.b) * exp(-w.b * x * x);
+    case W_BSPLINE: {
+        const double sc = sincd(x);
+        double v = w.inv_peak;
+        for (int i = 0; i < 2 * w.m; ++i) v *= sc;
+        return v;
+    }
+    case W_SINC_POWER: {
+        double v;
+        bspline_eval(2 * w.m, x / w.b, &v, nullptr);
+        return M_PI / w.b * v;
+    }
+    default: return kb_phihat(k, n, w.m, w.b, w.inv_peak);
+    }
+}
+
 }  // namespace hpnfft

@@ -19,7 +19,9 @@ LIB_PATH = os.path.join(_HERE, "libhpnfft.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "hpnfft.h")
 
 OK, EINVAL, EDOMAIN, ENOMEM, EHIP, ESTATE = 0, -1, -2, -3, -4, -5
-KAISER_BESSEL = 0
+KAISER_BESSEL, GAUSSIAN, BSPLINE, SINC_POWER = 0, 1, 2, 3
+WINDOWS = {"kaiser_bessel": KAISER_BESSEL, "kb": KAISER_BESSEL, "gaussian": GAUSSIAN,
+           "bspline": BSPLINE, "sinc_power": SINC_POWER}
 F64, F32 = 0, 1
 WITH_GRADIENT = 1
 
@@ -70,6 +72,8 @@ def _load():
         "hpnfft_ewald_real": (ctypes.c_int, [P, P, ctypes.c_int64, ctypes.c_double, ctypes.c_double,
                                              ctypes.c_double, P, P, P, P]),
         "hpnfft_plan_info": (ctypes.c_int, [P, i64p, i64p]),
+        "hpnfft_check_points": (ctypes.c_int, [P, ctypes.c_int64, ctypes.c_int, i64p]),
+        "hpnfft_copy": (ctypes.c_int, [P, P, ctypes.c_size_t, P]),
         "hpnfft_batch_capture": (ctypes.c_int, [P, P, P]),
         "hpnfft_batch_launch": (ctypes.c_int, [P]),
         "hpnfft_batch_offsets": (ctypes.c_int, [P, ctypes.c_int, i64p, i64p]),
@@ -77,8 +81,9 @@ def _load():
         "hpnfft_profile_phases": (ctypes.c_int, [P, ctypes.c_uint]),
         "hpnfft_profile_read": (ctypes.c_int, [P, P, P]),
         "hpnfft_phase_name": (ctypes.c_char_p, [ctypes.c_int]),
-        "hpnfft_window_eval": (ctypes.c_int, [ctypes.c_int, ctypes.c_double, ctypes.c_int64, P, P, P]),
-        "hpnfft_window_rolloff": (ctypes.c_int, [ctypes.c_int, ctypes.c_double, ctypes.c_int64,
+        "hpnfft_window_eval": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int64,
+                                              P, P, P]),
+        "hpnfft_window_rolloff": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int64,
                                                  ctypes.c_int64, P]),
     }
     for name, (res, args) in sig.items():
@@ -127,7 +132,8 @@ class Plan:
     """
 
     def __init__(self, N, M, sigma: float = 2.0, m: int = 8, precision: str = "f64",
-                 with_grad: bool = False, device="cuda", tiles: Optional[Sequence[int]] = None):
+                 with_grad: bool = False, device="cuda", tiles: Optional[Sequence[int]] = None,
+                 window: str = "kaiser_bessel"):
         lib = _load()
         self.device = _require_gpu(device)
         if isinstance(M, int):
@@ -139,6 +145,8 @@ class Plan:
         self.N, self.M = Ns, Ms
         self.B = len(Ms)
         self.m, self.sigma = int(m), float(sigma)
+        self.window = window
+        win = _window_code(window)
         self.precision = precision
         self.prec_code = {"f64": F64, "f32": F32}[precision]
         self.cdtype = torch.complex128 if precision == "f64" else torch.complex64
@@ -151,10 +159,10 @@ class Plan:
         with torch.cuda.device(self.device):
             if self.batched:
                 rc = lib.hpnfft_batch_create(ctypes.byref(self._h), self.B, Narr, Marr, self.sigma, self.m,
-                                             KAISER_BESSEL, self.prec_code, flags)
+                                             win, self.prec_code, flags)
             else:
                 rc = lib.hpnfft_plan_create(ctypes.byref(self._h), 3, Narr, Ms[0], self.sigma, self.m,
-                                            KAISER_BESSEL, self.prec_code, flags)
+                                            win, self.prec_code, flags)
         _check(rc, "plan_create")
         self.Mtot = sum(Ms)
         self.Ftot = sum(n[0] * n[1] * n[2] for n in Ns)
@@ -162,6 +170,9 @@ class Plan:
             _check(lib.hpnfft_set_tiles(self._h, *[int(v) for v in tiles]), "set_tiles")
         self._alloc_workspace()
         self.have_points = False
+        # incremented by every set_points: autograd's backward re-sets its
+        # forward's points when another call has replaced them since
+        self.points_generation = 0
 
     # -- internals ---------------------------------------------------------
     def _alloc_workspace(self):
@@ -214,6 +225,7 @@ class Plan:
         self._sync_stream()
         x = x.contiguous()
         self._points_copy = x
+        self.points_generation += 1
         if x.dtype == torch.float64:
             fn = lib.hpnfft_batch_set_points if self.batched else lib.hpnfft_set_points
             rc = fn(self._h, _ptr(x))
@@ -366,15 +378,22 @@ class NFFTAdjoint(torch.autograd.Function):
     def forward(ctx, x, f, plan: Plan):
         plan.set_points(x.detach())
         fhat = plan.adjoint(f.detach())
-        ctx.save_for_backward(f.detach())
+        ctx.save_for_backward(x.detach(), f.detach())
         ctx.plan = plan
+        ctx.generation = plan.points_generation
         return fhat
 
     @staticmethod
     def backward(ctx, grad_fhat):
-        (f,) = ctx.saved_tensors
+        x, f = ctx.saved_tensors
+        plan = ctx.plan
+        # the plan may hold other points by now (another transform or
+        # set_points on the same plan ran after this forward): restore ours
+        if plan.points_generation != ctx.generation:
+            plan.set_points(x)
+            ctx.generation = plan.points_generation
         need_x, need_f = ctx.needs_input_grad[0], ctx.needs_input_grad[1]
-        gf, gx = ctx.plan.adjoint_backward(f, grad_fhat.contiguous(), need_f=need_f, need_x=need_x)
+        gf, gx = plan.adjoint_backward(f, grad_fhat.contiguous(), need_f=need_f, need_x=need_x)
         if gx is not None and gx.dtype != torch.float64:
             gx = gx.to(torch.float64)
         return gx, gf, None
@@ -385,22 +404,56 @@ def nfft_adjoint(x: torch.Tensor, f: torch.Tensor, plan: Plan) -> torch.Tensor:
     return NFFTAdjoint.apply(x, f, plan)
 
 
-def window_eval(m: int, sigma: float, t):
-    """Host-only helper: normalised Kaiser-Bessel window and derivative."""
+def check_points(x) -> int:
+    """Host-side domain check of an (M, d) float64 array: -1 if every
+    coordinate lies in [-1/2, 1/2), else the index of the first point that
+    does not (no GPU needed)."""
+    import numpy as np
+    x = np.ascontiguousarray(np.asarray(x, dtype=np.float64))
+    if x.ndim != 2:
+        raise ValueError("x must be (M, d)")
+    bad = ctypes.c_int64()
+    rc = _load().hpnfft_check_points(x.ctypes.data_as(ctypes.c_void_p), x.shape[0], x.shape[1],
+                                     ctypes.byref(bad))
+    if rc not in (OK, EDOMAIN):
+        _check(rc, "check_points")
+    return int(bad.value)
+
+
+def device_copy(dst: torch.Tensor, src: torch.Tensor):
+    """dst <- src with the library's streaming copy kernel (same byte size,
+    contiguous, 16-byte aligned), on the current stream."""
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes or not (dst.is_contiguous() and src.is_contiguous()):
+        raise ValueError("dst and src must be contiguous with the same byte size")
+    _check(_load().hpnfft_copy(_ptr(dst), _ptr(src), nbytes, _stream_ptr(src.device)), "copy")
+
+
+def _window_code(window) -> int:
+    if isinstance(window, int):
+        return window
+    if window not in WINDOWS:
+        raise ValueError("window must be one of %s" % sorted(WINDOWS))
+    return WINDOWS[window]
+
+
+def window_eval(m: int, sigma: float, t, window="kaiser_bessel"):
+    """Host-only helper: a normalised window of the family and its derivative."""
     import numpy as np
     t = np.ascontiguousarray(np.asarray(t, dtype=np.float64))
     phi = np.empty_like(t)
     dphi = np.empty_like(t)
-    _check(_load().hpnfft_window_eval(int(m), float(sigma), t.size, t.ctypes.data_as(ctypes.c_void_p),
+    _check(_load().hpnfft_window_eval(_window_code(window), int(m), float(sigma), t.size,
+                                      t.ctypes.data_as(ctypes.c_void_p),
                                       phi.ctypes.data_as(ctypes.c_void_p), dphi.ctypes.data_as(ctypes.c_void_p)),
            "window_eval")
     return phi, dphi
 
 
-def window_rolloff(m: int, sigma: float, n: int, N: int):
-    """Host-only helper: roll-off factors 1/c_k for k = -N/2 .. N/2-1."""
+def window_rolloff(m: int, sigma: float, n: int, N: int, window="kaiser_bessel"):
+    """Host-only helper: roll-off factors 1/D(k) for k = -N/2 .. N/2-1."""
     import numpy as np
     out = np.empty(N, dtype=np.float64)
-    _check(_load().hpnfft_window_rolloff(int(m), float(sigma), int(n), int(N),
+    _check(_load().hpnfft_window_rolloff(_window_code(window), int(m), float(sigma), int(n), int(N),
                                          out.ctypes.data_as(ctypes.c_void_p)), "window_rolloff")
     return out

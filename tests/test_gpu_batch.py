@@ -116,25 +116,106 @@ def test_graph_replay_matches_eager(H):
 
 
 def test_c4_batch_sampled(H, oracle_mod):
-    """The 256-transform workload, 8 sampled frequencies per transform."""
+    """The 256-transform workload: every transform against the oracle on 64
+    sampled frequencies, each within 1e-5 (relative l2 over its sample)."""
     elems = W.c4(256)
     x, f = _pack(elems, "f32")
     plan = H.Plan([e["N"] for e in elems], [e["x"].shape[0] for e in elems], m=4, precision="f32")
     plan.set_points(torch.from_numpy(x).cuda())
     out = plan.adjoint(torch.from_numpy(f).cuda()).cpu().numpy().astype(np.complex128)
     g = W.rng(505)
-    worst = 0.0
-    for b in range(0, 256, 5):
+    errs = []
+    for b in range(256):
         e = elems[b]
         po, fo = plan.offsets(b)
         nb = int(np.prod(e["N"]))
-        kidx = W.sample_indices(nb, 8, g)
+        kidx = W.sample_indices(nb, 64, g)
         fu = f[po:po + e["x"].shape[0]].astype(np.complex128)
         ref = oracle_mod.ndft_adjoint(e["N"], e["x"], fu, kidx=kidx)
-        err = oracle_mod.rel_l2(out[fo:fo + nb][kidx], ref)
-        worst = max(worst, err)
-    print("C4 worst sampled rel-l2 %.3e" % worst)
-    assert worst <= 1e-5
+        errs.append(oracle_mod.rel_l2(out[fo:fo + nb][kidx], ref))
+    errs = np.array(errs)
+    print("C4 256 transforms x 64 k: median %.3e worst %.3e (b=%d)" % (np.median(errs), errs.max(), errs.argmax()))
+    assert errs.max() <= 1e-5
+
+
+def test_graph_dropped_by_set_points(H, oracle_mod):
+    """A captured batch graph holds the work list and workspace of the moment
+    it was recorded: set_points (and any re-tiling) drops it, replay then
+    reports ESTATE, and a new capture matches the eager result again."""
+    elems = _mixed(507, SIZES)
+    x, f = _pack(elems, "f32")
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        plan = H.Plan([e["N"] for e in elems], [e["x"].shape[0] for e in elems], m=4, precision="f32")
+        plan.set_points(torch.from_numpy(x).cuda())
+        ft = torch.from_numpy(f).cuda()
+        out = torch.empty(plan.Ftot, dtype=torch.complex64, device="cuda")
+        plan.capture(ft, out)
+        plan.replay()
+        # new points: half of the coordinates mirrored
+        x2 = x.copy()
+        x2[:, 0] = -x2[:, 0] - 1e-9
+        x2 = W.wrap_unit(x2)
+        plan.set_points(torch.from_numpy(x2).cuda())
+        with pytest.raises(H.HpnfftError) as ei:
+            plan.replay()
+        assert ei.value.code == H.ESTATE
+        eager = plan.adjoint(ft).clone()
+        plan.capture(ft, out)
+        out.zero_()
+        plan.replay()
+        torch.cuda.synchronize()
+        err = (out - eager).abs().max().item() / eager.abs().max().item()
+        assert err <= 1e-5
+        # the replayed result is the transform of the new points
+        po, fo = plan.offsets(5)
+        e = elems[5]
+        nb = int(np.prod(e["N"]))
+        kidx = W.sample_indices(nb, 64, W.rng(508))
+        ref = oracle_mod.ndft_adjoint(e["N"], x2[po:po + e["x"].shape[0]],
+                                      f[po:po + e["x"].shape[0]].astype(np.complex128), kidx=kidx)
+        got = out.cpu().numpy().astype(np.complex128)[fo:fo + nb][kidx]
+        assert oracle_mod.rel_l2(got, ref) <= 1e-5
+        # re-tiling drops it too
+        plan.set_tiles(8, 8, 512)
+        plan.set_points(torch.from_numpy(x2).cuda())
+        with pytest.raises(H.HpnfftError) as ei:
+            plan.replay()
+        assert ei.value.code == H.ESTATE
+    torch.cuda.synchronize()
+
+
+def test_autotune_cache(H, oracle_mod, tmp_path, monkeypatch):
+    """With HPNFFT_TUNE_CACHE set, the first autotune writes its choice to the
+    cache file and a second plan of the same shape takes it from there (no
+    candidate timing); the cached tiling reproduces the oracle result."""
+    path = tmp_path / "tune.json"
+    monkeypatch.setenv("HPNFFT_TUNE_CACHE", str(path))
+    g = W.rng(509)
+    N = (24, 24, 24)
+    M = 30000
+    x = W.uniform_points(M, 3, g)
+    f = W.complex_normal(M, g).astype(np.complex64)
+    import time
+    plan = H.Plan(N, M, m=4, precision="f32")
+    plan.set_points(torch.from_numpy(x).cuda())
+    t0 = time.perf_counter()
+    tiles = plan.autotune()
+    t_first = time.perf_counter() - t0
+    txt = path.read_text()
+    assert '"hpnfft_tune_cache": 1' in txt and "[%d, %d, %d]" % tiles in txt
+    plan2 = H.Plan(N, M, m=4, precision="f32")
+    plan2.set_points(torch.from_numpy(x).cuda())
+    t0 = time.perf_counter()
+    tiles2 = plan2.autotune()
+    t_second = time.perf_counter() - t0
+    print("autotune %.3f s, cached %.3f s, tiles %s" % (t_first, t_second, tiles))
+    assert tiles2 == tiles and plan2.tiles == tiles
+    assert t_second < t_first
+    out = plan2.adjoint(torch.from_numpy(f).cuda()).cpu().numpy().astype(np.complex128)
+    kidx = W.sample_indices(24 ** 3, 256, g)
+    ref = oracle_mod.ndft_adjoint(N, x, f.astype(np.complex128), kidx=kidx)
+    assert oracle_mod.rel_l2(out.reshape(-1)[kidx], ref) <= 1e-5
 
 
 def test_autotuner_keeps_results(H, oracle_mod):

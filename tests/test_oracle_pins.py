@@ -240,3 +240,22 @@ def test_ewald_forces_match_finite_differences(oracle_mod):
             assert abs(fd - F[i, t]) <= 1e-6 * max(1.0, abs(fd))
     # Newton's third law: the net force vanishes.
     assert np.max(np.abs(F.sum(axis=0))) <= 1e-9
+
+
+def test_selected_ion_ewald_forces(oracle_mod):
+    """The selected-ions variant of Eq. (12) gives the same energy as the full
+    reciprocal sum and, for the listed ions, forces equal to central
+    differences of that (Madelung-pinned) energy."""
+    r, q, L = W.fluorite(1, displacement_std=0.05, seed=23)
+    alpha = 1.6
+    kmax = int(math.ceil(6.2 * alpha * L / math.pi))
+    sel = np.array([5, 0, 9], dtype=np.int64)
+    U, F, _ = oracle_mod.ewald_recip_selected(r, q, L, alpha, kmax, sel)
+    assert abs(U - oracle_mod.ewald_recip(r, q, L, alpha, kmax)) <= 1e-12 * abs(U)
+    h = 1e-5
+    for a, i in enumerate(sel):
+        for t in range(3):
+            rp = r.copy(); rp[i, t] += h
+            rm = r.copy(); rm[i, t] -= h
+            fd = -(oracle_mod.ewald_recip(rp, q, L, alpha, kmax) - oracle_mod.ewald_recip(rm, q, L, alpha, kmax)) / (2 * h)
+            assert abs(fd - F[a, t]) <= 1e-6 * max(1.0, abs(fd))
