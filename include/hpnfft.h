@@ -45,6 +45,7 @@ extern "C" {
 #define HPNFFT_ENOMEM   (-3)  /* host allocation failed or workspace too small       */
 #define HPNFFT_EHIP     (-4)  /* a HIP runtime call failed                           */
 #define HPNFFT_ESTATE   (-5)  /* call out of order (e.g. transform before set_points)*/
+#define HPNFFT_ESIZE    (-6)  /* input exceeds a fixed capacity of the library       */
 
 /* ---- window (Section 2: a window well localised in space and frequency;
  * Section 4 compares these four).  In grid units t = n x - l, each
@@ -177,6 +178,23 @@ int hpnfft_ewald_recip(hpnfft_plan plan, const void *S, double L, double alpha,
 int hpnfft_ewald_real(const double *r, const double *q, int64_t M, double L, double alpha,
                       double rcut, double *energy_dev, double *forces_dev,
                       double *scratch_dev, void *stream);
+
+/* Variant of hpnfft_ewald_real that allocates nothing and takes no scratch
+ * argument, for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Same computation, kernels and results as hpnfft_ewald_real; the block
+ * partial sums live in a static device array of the library (512 KiB per
+ * device, held until the process ends), so M is limited to
+ * hpnfft_ewald_real_static_max_ions() ions: larger M returns HPNFFT_ESIZE
+ * before anything is launched.  Every call on one device shares that array:
+ * calls that overlap on one device (different streams, or different host
+ * threads without ordering) race and give wrong energies.  Nothing needs
+ * clearing between calls (each call writes every partial it reads).
+ * Asynchronous on `stream`. */
+int hpnfft_ewald_real_static(const double *r, const double *q, int64_t M, double L, double alpha,
+                             double rcut, double *energy_dev, double *forces_dev, void *stream);
+/* Largest M hpnfft_ewald_real_static accepts (16,777,216). */
+int64_t hpnfft_ewald_real_static_max_ions(void);
 
 /* Tiling autotuner: times the adjoint and the forward (for gradient plans:
  * the adjoint and the backward) for each candidate tiling on the current

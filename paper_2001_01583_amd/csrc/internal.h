@@ -183,6 +183,8 @@ hipError_t launch_interp(int m, bool grad, const Xform *dxf, const SItem *items,
 template <typename R>
 hipError_t launch_fft(int pass, const Xform *dxf, const FItem *items, int nitems, int max_n,
                       void *fhat_base, hipStream_t s);
+// Ions per workgroup of the real-space pair kernel (one block partial each).
+constexpr int kEwaldRealTile = 256;
 hipError_t launch_ewald_real(const double *r, const double *q, long long M, double L, double alpha,
                              double rcut, double *partials, double *energy, double *forces, hipStream_t s);
 template <typename R>

@@ -210,7 +210,7 @@ hipError_t launch_ewald(const void *S, const Xform &X, double L, double alpha, d
 //   U = 1/2 sum_i sum_{j != i} q_i q_j erfc(alpha r_ij) / r_ij   (r_ij < rcut)
 //   F_i = sum_j q_i q_j [erfc(alpha r)/r + 2 alpha/sqrt(pi) exp(-alpha^2 r^2)] d_ij / r^2
 // One thread per ion i; the j loop streams through LDS tiles of 256 ions.
-constexpr int kRealTile = 256;
+constexpr int kRealTile = kEwaldRealTile;
 
 __global__ __launch_bounds__(kRealTile) void k_ewald_real(const double *__restrict__ r,
                                                           const double *__restrict__ q, long long M,

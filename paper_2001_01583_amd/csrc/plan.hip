@@ -19,6 +19,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -119,6 +120,37 @@ struct hpnfft_plan_s {
 namespace {
 
 int hip_status(hipError_t e) { return e == hipSuccess ? HPNFFT_OK : HPNFFT_EHIP; }
+
+// ---------------------------------------------------------------------------
+// Static scratch for the entry point that allocates nothing
+// (hpnfft_ewald_real_static): the block partial sums of the real-space pair
+// kernel live in this file-scope device array instead of a caller buffer.
+// Each device holds its own copy for the life of the process.  In host code
+// `scratch` only names the symbol; its device address on the current device
+// comes from hipGetSymbolAddress, looked up once per device and cached.
+constexpr int kStaticScratchDoubles = 65536;   // 512 KiB per device
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) double scratch[kStaticScratchDoubles];
+
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up at the first
+// call on that device).
+int static_scratch(double **out)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return HPNFFT_EHIP;
+    if (dev < 0 || dev >= kMaxDevices) return HPNFFT_EINVAL;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return HPNFFT_EHIP;
+        g_scratch_ptr[dev] = static_cast<double *>(ptr);
+    }
+    *out = g_scratch_ptr[dev];
+    return HPNFFT_OK;
+}
 
 // Diagnostics on stderr when the environment variable HPNFFT_LOG is set to a
 // non-empty value other than "0" (read once).
@@ -863,6 +895,7 @@ const char *hpnfft_strerror(int status)
     case HPNFFT_ENOMEM: return "out of memory or workspace too small";
     case HPNFFT_EHIP: return "HIP runtime error";
     case HPNFFT_ESTATE: return "call out of order";
+    case HPNFFT_ESIZE: return "input exceeds the library's fixed scratch capacity";
     default: return "unknown status";
     }
 }
@@ -1019,6 +1052,24 @@ int hpnfft_ewald_real(const double *r, const double *q, int64_t M, double L, dou
     return hip_status(launch_ewald_real(r, q, M, L, alpha, rcut, scratch_dev, energy_dev, forces_dev,
                                         (hipStream_t)stream));
 }
+
+int hpnfft_ewald_real_static(const double *r, const double *q, int64_t M, double L, double alpha, double rcut,
+                             double *energy_dev, double *forces_dev, void *stream)
+{
+    if (!r || !q || !energy_dev || M < 1) return HPNFFT_EINVAL;
+    if (!(L > 0.0) || !(alpha > 0.0) || !(rcut > 0.0) || rcut > 0.5 * L) return HPNFFT_EINVAL;
+    if (M > hpnfft_ewald_real_static_max_ions()) {
+        hlog("ewald_real_static: %lld ions exceed the static scratch (at most %lld)", (long long)M,
+             (long long)hpnfft_ewald_real_static_max_ions());
+        return HPNFFT_ESIZE;
+    }
+    double *part = nullptr;
+    const int rc = static_scratch(&part);
+    if (rc != HPNFFT_OK) return rc;
+    return hip_status(launch_ewald_real(r, q, M, L, alpha, rcut, part, energy_dev, forces_dev, (hipStream_t)stream));
+}
+
+int64_t hpnfft_ewald_real_static_max_ions(void) { return (int64_t)kStaticScratchDoubles * kEwaldRealTile; }
 
 int hpnfft_check_points(const double *x, int64_t M, int d, int64_t *first_bad)
 {

@@ -18,7 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhpnfft.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "hpnfft.h")
 
-OK, EINVAL, EDOMAIN, ENOMEM, EHIP, ESTATE = 0, -1, -2, -3, -4, -5
+OK, EINVAL, EDOMAIN, ENOMEM, EHIP, ESTATE, ESIZE = 0, -1, -2, -3, -4, -5, -6
 KAISER_BESSEL, GAUSSIAN, BSPLINE, SINC_POWER = 0, 1, 2, 3
 WINDOWS = {"kaiser_bessel": KAISER_BESSEL, "kb": KAISER_BESSEL, "gaussian": GAUSSIAN,
            "bspline": BSPLINE, "sinc_power": SINC_POWER}
@@ -71,6 +71,9 @@ def _load():
         "hpnfft_autotune": (ctypes.c_int, [P, P, P, ip, ip, ip]),
         "hpnfft_ewald_real": (ctypes.c_int, [P, P, ctypes.c_int64, ctypes.c_double, ctypes.c_double,
                                              ctypes.c_double, P, P, P, P]),
+        "hpnfft_ewald_real_static": (ctypes.c_int, [P, P, ctypes.c_int64, ctypes.c_double, ctypes.c_double,
+                                                    ctypes.c_double, P, P, P]),
+        "hpnfft_ewald_real_static_max_ions": (ctypes.c_int64, []),
         "hpnfft_plan_info": (ctypes.c_int, [P, i64p, i64p]),
         "hpnfft_check_points": (ctypes.c_int, [P, ctypes.c_int64, ctypes.c_int, i64p]),
         "hpnfft_copy": (ctypes.c_int, [P, P, ctypes.c_size_t, P]),
