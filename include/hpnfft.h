@@ -80,7 +80,12 @@ const char *hpnfft_strerror(int status);
 
 /* Create a plan for one transform (Section 1 defines d, N, M; Section 4 uses
  * sigma = 2 and the cut-off m).
- *   d          must be 3
+ *   d          1, 2 or 3 (Section 1 states the problem for any d).  d < 3
+ *              runs the three-dimensional kernels with 3 - d leading
+ *              dims that carry no coordinate (N_t = 1, unit-impulse
+ *              window: exact); their grid edge is the smallest even
+ *              2^a 3^b 5^c 7^d >= 2m, which multiplies the spread and
+ *              interpolation work by about 2m per such dim
  *   N[d]       bandwidth, each N_t even and >= 2 (Section 1)
  *   M          number of points, >= 1
  *   sigma      oversampling factor; n_t = sigma * N_t must be an even integer
@@ -220,7 +225,7 @@ int hpnfft_check_points(const double *x, int64_t M, int d, int64_t *first_bad);
  * (else EINVAL); the ranges must not overlap.  Asynchronous. */
 int hpnfft_copy(void *dst, const void *src, size_t bytes, void *stream);
 
-/* Oversampled grid size n (d values) and points count. */
+/* Oversampled grid size n (d values: the plan's own dims) and points count. */
 int hpnfft_plan_info(hpnfft_plan plan, int64_t *n_out, int64_t *M_out);
 
 /* ---- batches of independent transforms ------------------------------ */
@@ -288,6 +293,15 @@ int hpnfft_window_eval(int window, int m, double sigma, int64_t count, const dou
  * normalised window at k/n cycles per cell: the divisor of the Scaling step
  * (Section 2). */
 int hpnfft_window_rolloff(int window, int m, double sigma, int64_t n, int64_t N, double *out);
+
+/* A-priori bound E of the one-dimensional error of the gridding scheme with
+ * window `window`, cut-off m and oversampling sigma > 1 (Section 4 compares
+ * the windows' accuracy against m): every output of a one-dimensional
+ * transform satisfies |approximate - exact| <= E ||input||_1 (up to
+ * rounding).  Formulas from the NFFT literature's error estimates (Potts,
+ * Steidl, Tasche 2001); for d dimensions the bound grows to about d E.
+ * sinc-power at m = 1 has no stated bound and reports 4. */
+int hpnfft_window_error_bound(int window, int m, double sigma, double *bound);
 
 #ifdef __cplusplus
 }

@@ -21,7 +21,8 @@ struct Xform {
     int N[3];          // bandwidth
     int ntx, nty;      // tiles along dims 2 and 1
     int nslab;         // slabs along dim 0
-    int pad0;
+    int flat;          // leading dims that carry no coordinate (d = 3 - flat):
+                       // N_t = 1, every point at cell 0, window = unit impulse
     long long M;       // points
     long long poff;    // first sorted point of this transform (packed arrays)
     long long foff;    // first frequency of this transform (packed fhat)
@@ -143,10 +144,13 @@ inline LdsLayout lds_fit(int T, int Zs, int M2, size_t R, int kind, bool comp)
 // few spills, measured faster than 512 threads); the interpolation variants
 // that hold more window values per lane (the gradient, float64 blocked
 // lines) are compiled for 512.
-__host__ __device__ constexpr int spread_max_threads(int, int) { return 1024; }
+// Windows wider than 16 cells (m > 8) hold 2m complex values per lane in the
+// register window and are compiled for 256 threads (up to 512 registers).
+__host__ __device__ constexpr int spread_max_threads(int, int M2) { return M2 > 16 ? 256 : 1024; }
 __host__ __device__ constexpr int interp_max_threads(int real_bytes, int M2, bool grad)
 {
-    return (grad && (real_bytes == 8 || M2 >= 12)) || (real_bytes == 8 && block_w(M2) > 1) ? 512 : 1024;
+    return M2 > 16 ? 256
+                   : (grad && (real_bytes == 8 || M2 >= 12)) || (real_bytes == 8 && block_w(M2) > 1) ? 512 : 1024;
 }
 
 // FFT pass identifiers.
@@ -158,8 +162,10 @@ template <typename R> struct Launch;
 
 hipError_t launch_zero(void *p, size_t bytes, hipStream_t s);
 hipError_t launch_copy(void *dst, const void *src, size_t bytes, int cus, hipStream_t s);
+// x / xf32 hold M x (3 - flat) coordinates; xs_out (if not null) receives
+// them as M x 3 with the flat dims zero.
 hipError_t launch_bin_count(const double *x, const float *xf32, long long M, const Xform &X, int T, int BW,
-                            int *counts, int *rank, int *err, double *xs_out, hipStream_t s);
+                            int flat, int *counts, int *rank, int *err, double *xs_out, hipStream_t s);
 hipError_t launch_scan(int *data, long long n, int *tmp, hipStream_t s);
 template <typename R>
 hipError_t launch_bin_scatter(const double *x, const float *xf32, long long M, const Xform &X, int T, int m,
@@ -170,7 +176,7 @@ hipError_t launch_gather(const void *f, const int *perm, long long total, R *fs,
 template <typename R>
 hipError_t launch_scatter(const R *outs, const int *ipos, long long total, void *f, hipStream_t s);
 template <typename R>
-hipError_t launch_grad_finish(const R *outs4, const void *f, const int *ipos, long long total,
+hipError_t launch_grad_finish(const R *outs4, const void *f, const int *ipos, long long total, int flat,
                               void *grad_f, void *grad_x, hipStream_t s);
 template <typename R>
 hipError_t launch_spread(int m, const Xform *dxf, const SItem *items, int nitems, int *queue,

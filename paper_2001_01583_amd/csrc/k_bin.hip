@@ -51,25 +51,35 @@ __device__ inline int sort_key(const int c[3], int T, int ntx, int n0, int BW)
 // its cell (the counting sort's first half), the domain check, and the
 // float64 copy of the coordinates that later passes (and the tiling
 // autotuner) read.  xs_out may be null when x already is that copy.
+// Plans of d < 3 dimensions (flat = 3 - d leading dims without a
+// coordinate) read d values per point and store three, the flat ones zero.
 template <typename XT>
 __global__ void k_bin_count(const XT *__restrict__ x, long long M, int n0, int n1, int n2, int T, int ntx,
-                            int BW, int *__restrict__ counts, int *__restrict__ rank, int *__restrict__ err,
-                            double *__restrict__ xs_out)
+                            int BW, int flat, int *__restrict__ counts, int *__restrict__ rank,
+                            int *__restrict__ err, double *__restrict__ xs_out)
 {
     long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= M) return;
     const int n[3] = {n0, n1, n2};
+    const int d = 3 - flat;
     bool bad = false;
     int c[3];
+    double xv[3];
     for (int t = 0; t < 3; ++t) {
+        xv[t] = t < flat ? 0.0 : (double)x[j * d + (t - flat)];
         double u;
-        c[t] = cell_of((double)x[j * 3 + t], n[t], &u, &bad);
+        c[t] = cell_of(xv[t], n[t], &u, &bad);
     }
-    // the copy runs over the flat array (words j, j + M, j + 2M), so every
-    // store instruction writes one contiguous span
     if (xs_out) {
+        if (flat == 0) {
+            // the copy runs over the flat array (words j, j + M, j + 2M), so
+            // every store instruction writes one contiguous span
 #pragma unroll
-        for (int t = 0; t < 3; ++t) xs_out[j + t * M] = (double)x[j + t * M];
+            for (int t = 0; t < 3; ++t) xs_out[j + t * M] = (double)x[j + t * M];
+        } else {
+#pragma unroll
+            for (int t = 0; t < 3; ++t) xs_out[j * 3 + t] = xv[t];
+        }
     }
     if (bad) atomicOr(err, 1);
     rank[j] = atomicAdd(&counts[sort_key(c, T, ntx, n0, BW)], 1);
@@ -121,7 +131,7 @@ __global__ __launch_bounds__(256) void k_bin_scatter(const double *__restrict__ 
                                                      const int *__restrict__ rank, int *__restrict__ perm,
                                                      int *__restrict__ ipos, unsigned char *__restrict__ rec,
                                                      size_t rec_bytes, WindowParams wp,
-                                                     const double *__restrict__ poly)
+                                                     const double *__restrict__ poly, int flat)
 {
     constexpr int m = M2 / 2;
     constexpr int NW = 3 * M2;
@@ -157,6 +167,12 @@ __global__ __launch_bounds__(256) void k_bin_scatter(const double *__restrict__ 
             if (!poly || GRAD) win_eval(wp, dist, &ph, GRAD ? &dph : nullptr);
             w[dim * M2 + t] = (R)(poly ? horner<NC>(poly + t * NC, 2.0 * u[dim] - 1.0) : ph);
             if constexpr (GRAD) dw[dim * M2 + t] = (R)((double)n[dim] * dph);
+            // a flat dim (no coordinate, N_t = 1): unit impulse on cell 0,
+            // which the point (at 0) reaches with tap m - 1
+            if (dim < flat) {
+                w[dim * M2 + t] = t == m - 1 ? R(1) : R(0);
+                if constexpr (GRAD) dw[dim * M2 + t] = R(0);
+            }
         }
     }
     // dim 0 into slot order, slot s = (tap + rot) mod 2m: a rotation by rot
@@ -316,16 +332,16 @@ hipError_t launch_scan(int *data, long long n, int *tmp, hipStream_t s)
 
 // ---------------------------------------------------------------------------
 hipError_t launch_bin_count(const double *x, const float *xf32, long long M, const Xform &X, int T, int BW,
-                            int *counts, int *rank, int *err, double *xs_out, hipStream_t s)
+                            int flat, int *counts, int *rank, int *err, double *xs_out, hipStream_t s)
 {
     if (M <= 0) return hipSuccess;
     const unsigned nb = (unsigned)((M + 255) / 256);
     if (x)
         hipLaunchKernelGGL(k_bin_count<double>, dim3(nb), dim3(256), 0, s, x, M, X.n[0], X.n[1], X.n[2], T,
-                           X.ntx, BW, counts, rank, err, xs_out);
+                           X.ntx, BW, flat, counts, rank, err, xs_out);
     else
         hipLaunchKernelGGL(k_bin_count<float>, dim3(nb), dim3(256), 0, s, xf32, M, X.n[0], X.n[1], X.n[2], T,
-                           X.ntx, BW, counts, rank, err, xs_out);
+                           X.ntx, BW, flat, counts, rank, err, xs_out);
     return hipGetLastError();
 }
 
@@ -337,7 +353,7 @@ static void scatter_m(const double *x, const float *xf32, long long M, const Xfo
     const unsigned nb = (unsigned)((M + 255) / 256);
     auto k = grad ? k_bin_scatter<R, M2, true> : k_bin_scatter<R, M2, false>;
     hipLaunchKernelGGL(k, dim3(nb), dim3(256), 0, s, x, xf32, M, X.poff, X.n[0], X.n[1], X.n[2], T, X.ntx,
-                       cell_start, rank, perm, ipos, rec, rec_bytes, wp, poly);
+                       cell_start, rank, perm, ipos, rec, rec_bytes, wp, poly, X.flat);
 }
 
 template <typename R>

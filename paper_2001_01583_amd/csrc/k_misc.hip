@@ -96,8 +96,10 @@ __global__ void k_scatter(const R *__restrict__ outs, const int *__restrict__ ip
 
 // outs4 per sorted point: p, d0 p, d1 p, d2 p (complex).  grad_x = Re(f conj(d p)).
 template <typename R>
+// grad_x has d = 3 - flat columns: the derivatives along the flat leading
+// dims (which carry no coordinate) are not returned.
 __global__ void k_grad_finish(const R *__restrict__ outs4, const R *__restrict__ f,
-                              const int *__restrict__ ipos, long long total, R *__restrict__ grad_f,
+                              const int *__restrict__ ipos, long long total, int flat, R *__restrict__ grad_f,
                               R *__restrict__ grad_x)
 {
     long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -108,8 +110,9 @@ __global__ void k_grad_finish(const R *__restrict__ outs4, const R *__restrict__
         grad_f[2 * j + 1] = o[1];
     }
     if (grad_x) {
+        const int d = 3 - flat;
         R fr = f[2 * j], fi = f[2 * j + 1];
-        for (int t = 0; t < 3; ++t) grad_x[3 * j + t] = fr * o[2 + 2 * t] + fi * o[3 + 2 * t];
+        for (int t = flat; t < 3; ++t) grad_x[d * j + (t - flat)] = fr * o[2 + 2 * t] + fi * o[3 + 2 * t];
     }
 }
 
@@ -132,12 +135,12 @@ hipError_t launch_scatter(const R *outs, const int *ipos, long long total, void 
 }
 
 template <typename R>
-hipError_t launch_grad_finish(const R *outs4, const void *f, const int *ipos, long long total,
+hipError_t launch_grad_finish(const R *outs4, const void *f, const int *ipos, long long total, int flat,
                               void *grad_f, void *grad_x, hipStream_t s)
 {
     if (total <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_grad_finish<R>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, outs4,
-                       (const R *)f, ipos, total, (R *)grad_f, (R *)grad_x);
+                       (const R *)f, ipos, total, flat, (R *)grad_f, (R *)grad_x);
     return hipGetLastError();
 }
 
@@ -280,7 +283,7 @@ hipError_t launch_ewald_real(const double *r, const double *q, long long M, doub
 #define HPNFFT_INST(R)                                                                             \
     template hipError_t launch_gather<R>(const void *, const int *, long long, R *, hipStream_t);   \
     template hipError_t launch_scatter<R>(const R *, const int *, long long, void *, hipStream_t); \
-    template hipError_t launch_grad_finish<R>(const R *, const void *, const int *, long long,     \
+    template hipError_t launch_grad_finish<R>(const R *, const void *, const int *, long long, int,\
                                               void *, void *, hipStream_t);                        \
     template hipError_t launch_ewald<R>(const void *, const Xform &, double, double, double *, int, \
                                         double *, void *, hipStream_t);

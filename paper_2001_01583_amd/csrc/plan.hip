@@ -502,9 +502,14 @@ void prepare_host_tables(hpnfft_plan_s *p)
     p->h_roll.clear();
     for (int b = 0; b < p->B; ++b) {
         const Xform &X = p->hx[b];
-        for (int d = 0; d < 3; ++d)
+        for (int d = 0; d < 3; ++d) {
+            if (d < X.flat) {  // unit impulse: the Scaling step divides by 1
+                p->h_roll.push_back(1.0);
+                continue;
+            }
             for (int k = -X.N[d] / 2; k < X.N[d] / 2; ++k)
                 p->h_roll.push_back(1.0 / window_phihat(p->wp, k, X.n[d]));
+        }
     }
     // window polynomials for set_points (float32 tables: 10 coefficients;
     // float64: 17); without a good fit the tables are evaluated directly
@@ -670,8 +675,11 @@ int bin_points(hpnfft_plan_s *p, const double *x = nullptr, const float *x32 = n
         int *cs = p->at<int>(L.key_off[b]);
         HCHECK(launch_zero(cs, (size_t)p->keys[b] * 4, s));
         double *xb = xs + X.poff * 3;
-        HCHECK(launch_bin_count(stored ? xb : (x ? x + X.poff * 3 : nullptr), x32 ? x32 + X.poff * 3 : nullptr,
-                                X.M, X, p->til.T, block_w(p->M2()), cs, p->at<int>(L.rank), setp, stored ? nullptr : xb, s));
+        // the caller's points have 3 - flat coordinates each; the stored copy three
+        const int dc = 3 - X.flat;
+        HCHECK(launch_bin_count(stored ? xb : (x ? x + X.poff * dc : nullptr), x32 ? x32 + X.poff * dc : nullptr,
+                                X.M, X, p->til.T, block_w(p->M2()), stored ? 0 : X.flat, cs, p->at<int>(L.rank),
+                                setp, stored ? nullptr : xb, s));
         HCHECK(launch_scan(cs, p->keys[b], p->at<int>(L.scan_tmp), s));
         if (p->prec == HPNFFT_F32)
             HCHECK(launch_bin_scatter<float>(xb, nullptr, X.M, X, p->til.T, p->m, p->wp,
@@ -802,13 +810,26 @@ int run_backward(hpnfft_plan_s *p, const void *f, const void *gfhat, void *grad_
     }
     {
         PhaseTimer t(p, HPNFFT_PH_GRAD_FIN);
-        HCHECK(launch_grad_finish<R>(p->at<R>(L.outs), f, p->at<int>(L.ipos), p->Mtot, grad_f, grad_x, s));
+        HCHECK(launch_grad_finish<R>(p->at<R>(L.outs), f, p->at<int>(L.ipos), p->Mtot, p->hx[0].flat, grad_f,
+                                     grad_x, s));
     }
     return HPNFFT_OK;
 }
 
+// Smallest even grid edge >= v whose FFT factors are in {2, 3, 5, 7}.
+int smooth_even_at_least(int v)
+{
+    int e = std::max(2, v + (v & 1));
+    while (!is_smooth(e)) e += 2;
+    return e;
+}
+
+// d < 3 (single transforms): the 3 - d leading dims are flat, with N_t = 1,
+// every point at 0 and a unit-impulse window, so the three-dimensional
+// kernels compute the d-dimensional transform exactly (their grid edge there
+// is the smallest even smooth size >= 2m that the sweeps accept).
 int create_common(hpnfft_plan_s **out, int B, const int64_t *N, const int64_t *M, double sigma, int m,
-                  int window, int precision, unsigned flags)
+                  int window, int precision, unsigned flags, int dims = 3)
 {
     if (!out || B < 1 || !N || !M) return HPNFFT_EINVAL;
     *out = nullptr;
@@ -829,12 +850,19 @@ int create_common(hpnfft_plan_s **out, int B, const int64_t *N, const int64_t *M
     p->hx.resize(B);
     p->keys.resize(B);
     long long Mtot = 0, Ftot = 0;
+    const int flat = 3 - dims;
     for (int b = 0; b < B; ++b) {
         Xform &X = p->hx[b];
         std::memset(&X, 0, sizeof(X));
+        X.flat = flat;
         if (M[b] < 1) { delete p; return HPNFFT_EINVAL; }
-        for (int d = 0; d < 3; ++d) {
-            int64_t Nt = N[3 * b + d];
+        for (int t = 0; t < flat; ++t) {
+            X.N[t] = 1;
+            X.n[t] = smooth_even_at_least(2 * m);
+            p->maxn = std::max(p->maxn, X.n[t]);
+        }
+        for (int d = flat; d < 3; ++d) {
+            int64_t Nt = N[dims * b + (d - flat)];
             if (Nt < 2 || Nt % 2 != 0 || Nt > kMaxN) { delete p; return HPNFFT_EINVAL; }
             double nv = sigma * (double)Nt;
             long nt = std::lround(nv);
@@ -903,8 +931,8 @@ const char *hpnfft_strerror(int status)
 int hpnfft_plan_create(hpnfft_plan *out, int d, const int64_t *N, int64_t M, double sigma, int m, int window,
                        int precision, unsigned flags)
 {
-    if (d != 3) return HPNFFT_EINVAL;
-    return create_common(out, 1, N, &M, sigma, m, window, precision, flags);
+    if (d < 1 || d > 3) return HPNFFT_EINVAL;
+    return create_common(out, 1, N, &M, sigma, m, window, precision, flags, d);
 }
 
 int hpnfft_batch_create(hpnfft_batch *out, int B, const int64_t *N, const int64_t *M, double sigma, int m,
@@ -1100,7 +1128,7 @@ int hpnfft_plan_info(hpnfft_plan p, int64_t *n_out, int64_t *M_out)
 {
     if (!p) return HPNFFT_EINVAL;
     if (n_out)
-        for (int d = 0; d < 3; ++d) n_out[d] = p->hx[0].n[d];
+        for (int d = p->hx[0].flat; d < 3; ++d) n_out[d - p->hx[0].flat] = p->hx[0].n[d];
     if (M_out) *M_out = p->Mtot;
     return HPNFFT_OK;
 }
@@ -1287,6 +1315,14 @@ int hpnfft_window_eval(int window, int m, double sigma, int64_t count, const dou
         phi[i] = v;
         if (dphi) dphi[i] = d;
     }
+    return HPNFFT_OK;
+}
+
+int hpnfft_window_error_bound(int window, int m, double sigma, double *bound)
+{
+    if (window < HPNFFT_KAISER_BESSEL || window > HPNFFT_SINC_POWER) return HPNFFT_EINVAL;
+    if (m < 1 || m > kMaxWindowM || !(sigma > 1.0) || !bound) return HPNFFT_EINVAL;
+    *bound = window_error_bound(window, m, sigma);
     return HPNFFT_OK;
 }
 

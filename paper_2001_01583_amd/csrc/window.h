@@ -248,4 +248,27 @@ inline double window_phihat(const WindowParams &w, long k, long n)
     }
 }
 
+// A-priori bound E(m, sigma) of the one-dimensional approximation error of
+// the gridding scheme, |approximate - exact| <= E ||f||_1 for every output,
+// from the NFFT literature (Potts, Steidl and Tasche 2001, error estimates
+// of the window family):
+//   Kaiser-Bessel  4 pi (sqrt(m) + m) (1 - 1/sigma)^(1/4) exp(-2 pi m sqrt(1 - 1/sigma))
+//   Gaussian       4 exp(-m pi (1 - 1/(2 sigma - 1)))
+//   B-spline       4 (1 / (2 sigma - 1))^(2m)
+//   sinc-power     (2 / sigma^(2m) + (sigma / (2 sigma - 1))^(2m)) / (m - 1),  m >= 2
+// (host only; 4 for sinc-power at m = 1, where no bound is stated).
+inline double window_error_bound(int kind, int m, double sigma)
+{
+    switch (kind) {
+    case W_GAUSSIAN: return 4.0 * exp(-m * M_PI * (1.0 - 1.0 / (2.0 * sigma - 1.0)));
+    case W_BSPLINE: return 4.0 * pow(1.0 / (2.0 * sigma - 1.0), 2.0 * m);
+    case W_SINC_POWER:
+        if (m < 2) return 4.0;
+        return (2.0 / pow(sigma, 2.0 * m) + pow(sigma / (2.0 * sigma - 1.0), 2.0 * m)) / (m - 1.0);
+    default:
+        return 4.0 * M_PI * (sqrt((double)m) + m) * pow(1.0 - 1.0 / sigma, 0.25) *
+               exp(-2.0 * M_PI * m * sqrt(1.0 - 1.0 / sigma));
+    }
+}
+
 }  // namespace hpnfft

@@ -8,6 +8,7 @@ calls raise.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import re
 from typing import Optional, Sequence
@@ -88,6 +89,8 @@ def _load():
                                               P, P, P]),
         "hpnfft_window_rolloff": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int64,
                                                  ctypes.c_int64, P]),
+        "hpnfft_window_error_bound": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                                     ctypes.POINTER(ctypes.c_double)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -147,6 +150,9 @@ class Plan:
             self.batched = True
         self.N, self.M = Ns, Ms
         self.B = len(Ms)
+        self.d = len(Ns[0])
+        if not 1 <= self.d <= 3 or any(len(n) != self.d for n in Ns) or (self.batched and self.d != 3):
+            raise ValueError("N must give 1, 2 or 3 sizes per transform (batches: 3)")
         self.m, self.sigma = int(m), float(sigma)
         self.window = window
         win = _window_code(window)
@@ -156,7 +162,7 @@ class Plan:
         self.rdtype = torch.float64 if precision == "f64" else torch.float32
         self.with_grad = with_grad
         self._h = ctypes.c_void_p()
-        Narr = (ctypes.c_int64 * (3 * self.B))(*[v for n in Ns for v in n])
+        Narr = (ctypes.c_int64 * (self.d * self.B))(*[v for n in Ns for v in n])
         Marr = (ctypes.c_int64 * self.B)(*Ms)
         flags = WITH_GRADIENT if with_grad else 0
         with torch.cuda.device(self.device):
@@ -164,11 +170,11 @@ class Plan:
                 rc = lib.hpnfft_batch_create(ctypes.byref(self._h), self.B, Narr, Marr, self.sigma, self.m,
                                              win, self.prec_code, flags)
             else:
-                rc = lib.hpnfft_plan_create(ctypes.byref(self._h), 3, Narr, Ms[0], self.sigma, self.m,
+                rc = lib.hpnfft_plan_create(ctypes.byref(self._h), self.d, Narr, Ms[0], self.sigma, self.m,
                                             win, self.prec_code, flags)
         _check(rc, "plan_create")
         self.Mtot = sum(Ms)
-        self.Ftot = sum(n[0] * n[1] * n[2] for n in Ns)
+        self.Ftot = sum(math.prod(n) for n in Ns)
         if tiles is not None:
             _check(lib.hpnfft_set_tiles(self._h, *[int(v) for v in tiles]), "set_tiles")
         self._alloc_workspace()
@@ -221,9 +227,9 @@ class Plan:
         self.have_points = False
 
     def set_points(self, x: torch.Tensor):
-        """x: (sum M, 3) float64 (or float32) on the plan's device, in [-1/2, 1/2)."""
-        if x.device != self.device or x.shape != (self.Mtot, 3):
-            raise ValueError("x must be (%d, 3) on %s" % (self.Mtot, self.device))
+        """x: (sum M, d) float64 (or float32) on the plan's device, in [-1/2, 1/2)."""
+        if x.device != self.device or x.shape != (self.Mtot, self.d):
+            raise ValueError("x must be (%d, %d) on %s" % (self.Mtot, self.d, self.device))
         lib = _load()
         self._sync_stream()
         x = x.contiguous()
@@ -267,7 +273,7 @@ class Plan:
         f = self._vals(f, self.Mtot, "f")
         g = self._vals(grad_fhat, self.Ftot, "grad_fhat")
         gf = torch.empty(self.Mtot, dtype=self.cdtype, device=self.device) if need_f else None
-        gx = torch.empty((self.Mtot, 3), dtype=self.rdtype, device=self.device) if need_x else None
+        gx = torch.empty((self.Mtot, self.d), dtype=self.rdtype, device=self.device) if need_x else None
         self._sync_stream()
         _check(_load().hpnfft_adjoint_backward(self._h, _ptr(f), _ptr(g), _ptr(gf), _ptr(gx)),
                "adjoint_backward")
@@ -371,7 +377,7 @@ class Plan:
         n = (ctypes.c_int64 * 3)()
         M = ctypes.c_int64()
         _check(_load().hpnfft_plan_info(self._h, n, ctypes.byref(M)), "plan_info")
-        return tuple(n), M.value
+        return tuple(n)[:self.d], M.value
 
 
 class NFFTAdjoint(torch.autograd.Function):
@@ -460,3 +466,12 @@ def window_rolloff(m: int, sigma: float, n: int, N: int, window="kaiser_bessel")
     _check(_load().hpnfft_window_rolloff(_window_code(window), int(m), float(sigma), int(n), int(N),
                                          out.ctypes.data_as(ctypes.c_void_p)), "window_rolloff")
     return out
+
+
+def window_error_bound(m: int, sigma: float, window="kaiser_bessel") -> float:
+    """Host-only helper: the library's a-priori one-dimensional error bound E
+    (|approximate - exact| <= E ||input||_1 per output)."""
+    out = ctypes.c_double()
+    _check(_load().hpnfft_window_error_bound(_window_code(window), int(m), float(sigma), ctypes.byref(out)),
+           "window_error_bound")
+    return out.value

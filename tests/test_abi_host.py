@@ -38,7 +38,7 @@ def test_strerror_never_null(lib):
 
 
 @pytest.mark.parametrize("kw", [
-    dict(d=4), dict(N=(15, 16, 16)), dict(N=(0, 16, 16)), dict(M=0), dict(m=0), dict(m=16),
+    dict(d=4), dict(d=0), dict(d=2, N=(15, 16)), dict(d=1, N=(2,), m=4), dict(N=(15, 16, 16)), dict(N=(0, 16, 16)), dict(M=0), dict(m=0), dict(m=16),
     dict(sigma=1.7),            # 1.7 * 16 is not an integer
     dict(sigma=0.5), dict(window=4), dict(window=-1), dict(prec=2), dict(flags=8),
     dict(N=(22, 16, 16)),       # n = 44 has a factor 11
@@ -62,6 +62,20 @@ def test_valid_plans_created(lib, N, sigma):
     assert tuple(n) == tuple(int(round(sigma * v)) for v in N) and M.value == 100
     sz = ctypes.c_size_t()
     assert lib.hpnfft_workspace_size(h, ctypes.byref(sz)) == H.OK and sz.value > 0
+    assert lib.hpnfft_plan_destroy(h) == H.OK
+
+
+@pytest.mark.parametrize("N,m", [((24,), 4), ((16, 12), 8), ((64,), 11), ((10, 14), 3)])
+def test_lower_dimensional_plans_created(lib, N, m):
+    """d = 1, 2 (Section 1 defines the transform for any d): the plan reports
+    its own d grid sizes sigma N_t."""
+    rc, h = _create(lib, N=N, d=len(N), m=m)
+    assert rc == H.OK
+    n = (ctypes.c_int64 * 3)(-1, -1, -1)
+    M = ctypes.c_int64()
+    assert lib.hpnfft_plan_info(h, n, ctypes.byref(M)) == H.OK
+    assert tuple(n)[:len(N)] == tuple(2 * v for v in N) and M.value == 100
+    assert all(v == -1 for v in tuple(n)[len(N):])
     assert lib.hpnfft_plan_destroy(h) == H.OK
 
 
@@ -274,3 +288,37 @@ def test_gaussian_and_sinc_power_closed_forms():
         beta = math.pi * (2 * sigma - 1) / (2 * m * sigma)
         ref = (math.sin(beta * t) / (beta * t)) ** (2 * m)
         assert abs(H.window_eval(m, sigma, [t], "sinc_power")[0][0] - ref) < 1e-14
+
+
+def test_error_bounds_known_values():
+    """The a-priori bound at values quoted for the Kaiser-Bessel window at
+    sigma = 2 (1.2e-6 at m = 4, 4.2e-14 at m = 8), and the B-spline's
+    closed form 4 / 3^(2m)."""
+    assert abs(H.window_error_bound(4, 2.0) / 1.2e-6 - 1) < 0.02
+    assert abs(H.window_error_bound(8, 2.0) / 4.2e-14 - 1) < 0.02
+    for m in (1, 5, 15):
+        assert abs(H.window_error_bound(m, 2.0, "bspline") / (4.0 / 9.0 ** m) - 1) < 1e-12
+
+
+@pytest.mark.parametrize("window", WINDOWS)
+def test_one_dimensional_gridding_meets_bound(window):
+    """A one-dimensional adjoint assembled in numpy from the library's host
+    window values and Scaling divisors (spread, DFT of the grid, divide)
+    meets the a-priori bound |error| <= E ||f||_1 at every m: a window that
+    does not match its divisor fails at once."""
+    N, n, Mp = 16, 32, 1500
+    g = np.random.default_rng(3)
+    x = g.random(Mp) - 0.5
+    f = g.standard_normal(Mp) + 1j * g.standard_normal(Mp)
+    k = np.arange(-N // 2, N // 2)
+    exact = np.exp(-2j * np.pi * np.outer(k, x)) @ f
+    dft = np.exp(-2j * np.pi * np.outer(k, np.arange(n)) / n)
+    c = np.floor(n * x).astype(int)
+    for m in range(1, 16):
+        grid = np.zeros(n, complex)
+        for t in range(-m + 1, m + 1):
+            phi, _ = H.window_eval(m, 2.0, n * x - (c + t), window)
+            np.add.at(grid, (c + t) % n, f * phi)
+        approx = (dft @ grid) * H.window_rolloff(m, 2.0, n, N, window)
+        err = np.max(np.abs(approx - exact)) / np.abs(f).sum()
+        assert err <= H.window_error_bound(m, 2.0, window) + 2e-14, (window, m, err)  # + rounding, amplified by 1/D(k)
