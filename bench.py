@@ -512,6 +512,64 @@ def bench_c5(H, torch, W, args, summary=False):
     }
 
 
+def bench_enuf(H, torch, W, args, summary=False):
+    """Full Ewald (HP-ENUF) step on fluorite lattices of the paper's timing
+    sweep, 12 * c^3 ions for c = 32, 45, 56, 64 (393,216 .. 3,145,728 ions):
+    set_points + adjoint (S) + Eq. (12) energy + backward (reciprocal
+    forces) + cell-list real-space energy and forces (Eq. (11)).  float64,
+    m = 8, alpha = 1 / r0, cut-off and bandwidth for 1e-12 in both sums.
+    Lattice at zero displacement, so the Madelung constant (Eq. (10)) checks
+    every size against the value Section 5 prints (2.5194)."""
+    from paper_2001_01583_amd import ewald as E
+    dev = torch.device("cuda", 0)
+    rows = []
+    cells_list = [int(c) for c in args.enuf_cells.split(",")]
+    for c in cells_list:
+        r_np, q_np, L_box = W.fluorite(c, 0.0)
+        alpha = 1.0
+        rcut, Nb = E.parameters(L_box, alpha, 1e-12)
+        r = torch.from_numpy(r_np).to(dev)
+        q = torch.from_numpy(q_np).to(dev)
+        nion = int(r.shape[0])
+        ew = E.Ewald(nion, L_box, alpha, N=(Nb, Nb, Nb), m=8, precision="f64", rcut=rcut, device=dev,
+                     real_method="cells")
+
+        def step():
+            Uk, Fk = ew.reciprocal(r, q, forces=True)
+            Ur, Fr = ew.real_space(r, q, forces=True)
+            return Uk, Fk, Ur, Fr
+
+        steps = max(2, min(args.steps, 5))
+        t = _time(torch, step, steps, 1)
+        t_real = _time(torch, lambda: ew.real_space(r, q, forces=True), steps, 1)
+        Uk, Fk, Ur, Fr = step()
+        torch.cuda.synchronize()
+        U = float(Uk) + float(Ur)
+        mad = E.madelung_constant(U, nion)
+        F = (Fk + Fr).abs().max().item()
+        rows.append({"cells": c, "ions": nion, "L_box": round(L_box, 4), "N": Nb, "n": 2 * Nb,
+                     "rcut": round(rcut, 4), "ms_per_step": round(t * 1e3, 3),
+                     "real_space_ms": round(t_real * 1e3, 3), "ions_per_s": round(nion / t, 1),
+                     "madelung": round(mad, 10), "max_abs_force": float("%.3e" % F)})
+        log("enuf %d^3 cells (%d ions, N=%d): %.2f ms/step (real space %.2f ms), Madelung %.9f, max|F| %.2e"
+            % (c, nion, Nb, t * 1e3, t_real * 1e3, mad, F))
+        del ew, r, q
+        torch.cuda.empty_cache()
+    if summary:
+        return {"workload": "HP-ENUF step (Ewald: reciprocal by NFFT + cell-list real space, energy and forces), "
+                            "fluorite lattices, float64 m=8, 1e-12", "rows": rows}
+    last = rows[-1]
+    return {
+        "metric": METRIC, "value": last["ions_per_s"], "unit": "ions/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": 1, "ms_per_step": last["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "HP-ENUF ion sweep: fluorite c^3 cells (12 c^3 ions) for c in %s; step = reciprocal "
+                               "(set_points + adjoint + Eq. (12) + backward) + real space (cell lists, Eq. (11)), "
+                               "energy and forces, float64 m=8, alpha=1/r0, 1e-12" % cells_list},
+        "rows": rows,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -526,7 +584,9 @@ def main():
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write profiles/traffic_c2.json from two rocprofv3 --pmc output folders")
     ap.add_argument("--counters-command", default="", help="command line recorded with the summary")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5"],
+    ap.add_argument("--enuf-cells", default="32,45,56,64",
+                    help="lattice sizes (cells per edge) of the enuf workload")
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5", "enuf"],
                     help="c2 (default): N=64^3, M=2^20, set_points+adjoint+forward; c3: precision N=128^3, "
                          "M=2^23; c4: 256-transform batch; c5: Ewald forces, 165,888 ions")
     args = ap.parse_args()
@@ -556,7 +616,7 @@ def main():
         import tempfile
         os.environ["HPNFFT_TUNE_CACHE"] = os.path.join(tempfile.mkdtemp(prefix="hpnfft_"), "tune.json")
     if args.workload != "c2":
-        fn = {"c3": bench_c3, "c4": bench_c4, "c5": bench_c5}[args.workload]
+        fn = {"c3": bench_c3, "c4": bench_c4, "c5": bench_c5, "enuf": bench_enuf}[args.workload]
         print(json.dumps(fn(H, torch, W, args)), flush=True)
         return
     data = W.c2()

@@ -184,6 +184,23 @@ int hpnfft_ewald_real(const double *r, const double *q, int64_t M, double L, dou
                       double rcut, double *energy_dev, double *forces_dev,
                       double *scratch_dev, void *stream);
 
+/* Real-space Ewald sum of Eq. (11) with cell lists, for large ionic systems
+ * (Section 5's timing runs go to 12 * 64^3 ions): same sums and outputs as
+ * hpnfft_ewald_real, but over pairs closer than rcut found through nc^3
+ * cells of side L/nc >= rcut (nc = floor(L/rcut), at most 512), each pair
+ * with its nearest periodic image, so the cost grows as M rcut^3 instead of
+ * M^2.  r: device, M x 3 float64, any real coordinates (wrapped into the box
+ * of side L); q: device, M float64.  Requires L >= 3 rcut (else EINVAL; use
+ * hpnfft_ewald_real) and M < 2^31.  Every force has one writer; the energy
+ * is summed per cell in float64 and then in a fixed order, so results are
+ * bitwise reproducible.  workspace: device memory of
+ * hpnfft_ewald_real_cells_workspace() bytes, 256-byte aligned (ENOMEM if
+ * smaller).  Asynchronous on `stream`. */
+int hpnfft_ewald_real_cells_workspace(int64_t M, double L, double rcut, size_t *bytes);
+int hpnfft_ewald_real_cells(const double *r, const double *q, int64_t M, double L, double alpha,
+                            double rcut, double *energy_dev, double *forces_dev, void *workspace,
+                            size_t bytes, void *stream);
+
 /* Variant of hpnfft_ewald_real that allocates nothing and takes no scratch
  * argument, for callers that cannot allocate device memory (code under HIP
  * graph capture, tight serving loops, harnesses that forbid hipMalloc).

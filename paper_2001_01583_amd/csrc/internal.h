@@ -193,6 +193,15 @@ hipError_t launch_fft(int pass, const Xform *dxf, const FItem *items, int nitems
 constexpr int kEwaldRealTile = 256;
 hipError_t launch_ewald_real(const double *r, const double *q, long long M, double L, double alpha,
                              double rcut, double *partials, double *energy, double *forces, hipStream_t s);
+// Fixed-order sum of n float64 partials into *out (one workgroup).
+hipError_t launch_sum_partials(const double *part, int n, double *out, hipStream_t s);
+// Cell-list real-space Ewald sum (k_ewald.hip): workspace regions and launch.
+struct CellsLayout {
+    size_t start, scan, cell, rank, orig, orig_tmp, sorted, sorted_tmp, part, total;
+};
+CellsLayout cells_layout(long long M, int nc);
+hipError_t launch_ewald_cells(const double *r, const double *q, long long M, double L, double alpha, double rcut,
+                              int nc, unsigned char *ws, double *energy, double *forces, hipStream_t s);
 template <typename R>
 hipError_t launch_ewald(const void *S, const Xform &X, double L, double alpha, double *partials,
                         int nblocks, double *energy, void *gbar, hipStream_t s);

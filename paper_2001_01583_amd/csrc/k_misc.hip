@@ -197,6 +197,12 @@ __global__ __launch_bounds__(kEwThreads) void k_sum_partials(const double *__res
     if (threadIdx.x == 0) *out = sh[0];
 }
 
+hipError_t launch_sum_partials(const double *part, int n, double *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kEwThreads), 0, s, part, n, out);
+    return hipGetLastError();
+}
+
 template <typename R>
 hipError_t launch_ewald(const void *S, const Xform &X, double L, double alpha, double *partials,
                         int nblocks, double *energy, void *gbar, hipStream_t s)

@@ -1081,6 +1081,44 @@ int hpnfft_ewald_real(const double *r, const double *q, int64_t M, double L, dou
                                         (hipStream_t)stream));
 }
 
+}  // extern "C"
+
+namespace {
+// Cells per box edge for the cell-list sum: side L / nc >= rcut, at least 3
+// (the 27 neighbours are then distinct cells), at most kMaxCellEdge.
+constexpr int kMaxCellEdge = 512;
+int cell_edge(double L, double rcut)
+{
+    if (!(L > 0.0) || !(rcut > 0.0) || !std::isfinite(L / rcut)) return 0;
+    const double q = std::floor(L / rcut);
+    if (q < 3.0) return 0;
+    return q > kMaxCellEdge ? kMaxCellEdge : (int)q;
+}
+}  // namespace
+
+extern "C" {
+
+int hpnfft_ewald_real_cells_workspace(int64_t M, double L, double rcut, size_t *bytes)
+{
+    if (!bytes || M < 1 || M >= (1LL << 31)) return HPNFFT_EINVAL;
+    const int nc = cell_edge(L, rcut);
+    if (!nc) return HPNFFT_EINVAL;
+    *bytes = cells_layout(M, nc).total;
+    return HPNFFT_OK;
+}
+
+int hpnfft_ewald_real_cells(const double *r, const double *q, int64_t M, double L, double alpha, double rcut,
+                            double *energy_dev, double *forces_dev, void *workspace, size_t bytes, void *stream)
+{
+    if (!r || !q || !energy_dev || !workspace || M < 1 || M >= (1LL << 31)) return HPNFFT_EINVAL;
+    if (!(alpha > 0.0) || ((uintptr_t)workspace) % 256) return HPNFFT_EINVAL;
+    const int nc = cell_edge(L, rcut);
+    if (!nc) return HPNFFT_EINVAL;
+    if (bytes < cells_layout(M, nc).total) return HPNFFT_ENOMEM;
+    return hip_status(launch_ewald_cells(r, q, M, L, alpha, rcut, nc, static_cast<unsigned char *>(workspace),
+                                         energy_dev, forces_dev, (hipStream_t)stream));
+}
+
 int hpnfft_ewald_real_static(const double *r, const double *q, int64_t M, double L, double alpha, double rcut,
                              double *energy_dev, double *forces_dev, void *stream)
 {

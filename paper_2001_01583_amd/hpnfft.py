@@ -72,6 +72,10 @@ def _load():
         "hpnfft_autotune": (ctypes.c_int, [P, P, P, ip, ip, ip]),
         "hpnfft_ewald_real": (ctypes.c_int, [P, P, ctypes.c_int64, ctypes.c_double, ctypes.c_double,
                                              ctypes.c_double, P, P, P, P]),
+        "hpnfft_ewald_real_cells_workspace": (ctypes.c_int, [ctypes.c_int64, ctypes.c_double, ctypes.c_double,
+                                                             ctypes.POINTER(ctypes.c_size_t)]),
+        "hpnfft_ewald_real_cells": (ctypes.c_int, [P, P, ctypes.c_int64, ctypes.c_double, ctypes.c_double,
+                                                   ctypes.c_double, P, P, P, ctypes.c_size_t, P]),
         "hpnfft_ewald_real_static": (ctypes.c_int, [P, P, ctypes.c_int64, ctypes.c_double, ctypes.c_double,
                                                     ctypes.c_double, P, P, P]),
         "hpnfft_ewald_real_static_max_ions": (ctypes.c_int64, []),
