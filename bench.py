@@ -180,10 +180,10 @@ def summarize_counters(fetch_dir: str, write_dir: str, out_json: str, command: s
     print(json.dumps({k: v for k, v in out.items() if k != "raw_kib"}, indent=1))
 
 
-def run_path(H, torch, W, data, prec: str, m: int, steps: int, warmup: int):
+def run_path(H, torch, W, data, prec: str, m: int, steps: int, warmup: int, method: str = "auto"):
     dev = torch.device("cuda", 0)
     cd = torch.complex128 if prec == "f64" else torch.complex64
-    plan = H.Plan(N, M, m=m, precision=prec, device=dev)
+    plan = H.Plan(N, M, m=m, precision=prec, device=dev, method=method)
     x = torch.from_numpy(data["x"]).to(dev)
     f = torch.from_numpy(data["f"]).to(dev).to(cd)
     fh_in = torch.from_numpy(data["fhat"]).to(dev).to(cd)
@@ -219,7 +219,7 @@ def run_path(H, torch, W, data, prec: str, m: int, steps: int, warmup: int):
     plan.profile(False)
     ms_step = (t1 - t0) * 1e3 / steps
     return dict(plan=plan, ms_per_step=ms_step, phases=phases, dom=dom, dom_timed=dom_timed,
-                fhat=fh_out.cpu().numpy(), fout=f_out.cpu().numpy(), tiles=plan.tiles)
+                fhat=fh_out.cpu().numpy(), fout=f_out.cpu().numpy(), tiles=plan.tiles, method=plan.method)
 
 
 def summarize(res, prec, m, copy_gbs=None):
@@ -353,7 +353,7 @@ def bench_c3(H, torch, W, args, summary=False):
     res = {}
     for prec in ("f32", "f64"):
         cd = torch.complex64 if prec == "f32" else torch.complex128
-        plan = H.Plan(N, Mp, m=4, precision=prec, device=dev)
+        plan = H.Plan(N, Mp, m=4, precision=prec, device=dev, method=args.method)
         f = torch.from_numpy(f_np).to(dev).to(cd)
         out = torch.empty(N, dtype=cd, device=dev)
 
@@ -413,7 +413,7 @@ def bench_c4(H, torch, W, args, summary=False):
     Ms = [e["x"].shape[0] for e in elems]
     stream = torch.cuda.Stream(device=dev)
     with torch.cuda.stream(stream):
-        plan = H.Plan([e["N"] for e in elems], Ms, m=4, precision="f32", device=dev)
+        plan = H.Plan([e["N"] for e in elems], Ms, m=4, precision="f32", device=dev, method=args.method)
         plan.set_points(x)
         t_tune = time.perf_counter()
         plan.autotune()  # bin sizes (tile, slab, threads) chosen on these points
@@ -471,7 +471,8 @@ def bench_c5(H, torch, W, args, summary=False):
     alpha = 0.5 * (lo + hi)
     out = {}
     for prec, m in (("f64", 8), ("f32", 4)):
-        ew = E.Ewald(r.shape[0], L_box, alpha, N=(128, 128, 128), m=m, precision=prec, device=dev)
+        ew = E.Ewald(r.shape[0], L_box, alpha, N=(128, 128, 128), m=m, precision=prec, device=dev,
+                     method=args.method)
         t_tune = time.perf_counter()
         tiles = ew.autotune(r)  # once per lattice: tiling timed on these ions, gradient included
         t_tune = time.perf_counter() - t_tune
@@ -532,6 +533,7 @@ def bench_enuf(H, torch, W, args, summary=False):
         q = torch.from_numpy(q_np).to(dev)
         nion = int(r.shape[0])
         ew = E.Ewald(nion, L_box, alpha, N=(Nb, Nb, Nb), m=8, precision="f64", rcut=rcut, device=dev,
+                     method=args.method,
                      real_method="cells")
 
         def step():
@@ -584,6 +586,8 @@ def main():
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write profiles/traffic_c2.json from two rocprofv3 --pmc output folders")
     ap.add_argument("--counters-command", default="", help="command line recorded with the summary")
+    ap.add_argument("--method", default="auto", choices=["auto", "lines", "boxes"],
+                    help="sweep method of the spread and interpolation (default: the library's choice)")
     ap.add_argument("--enuf-cells", default="32,45,56,64",
                     help="lattice sizes (cells per edge) of the enuf workload")
     ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5", "enuf"],
@@ -626,12 +630,12 @@ def main():
     copy_gbs = hbm_copy_gbs(torch, H)
     log("streaming copy: %.1f GB/s" % copy_gbs)
     gpu = {}
-    gpu["f32_m4"] = run_path(H, torch, W, data, "f32", 4, args.steps, args.warmup)
+    gpu["f32_m4"] = run_path(H, torch, W, data, "f32", 4, args.steps, args.warmup, args.method)
     log("f32 m=4: %.3f ms/step" % gpu["f32_m4"]["ms_per_step"])
     if not args.no_fp64:
-        gpu["f64_m4"] = run_path(H, torch, W, data, "f64", 4, max(3, args.steps // 2), args.warmup)
+        gpu["f64_m4"] = run_path(H, torch, W, data, "f64", 4, max(3, args.steps // 2), args.warmup, args.method)
         log("f64 m=4: %.3f ms/step" % gpu["f64_m4"]["ms_per_step"])
-        gpu["f64_m8"] = run_path(H, torch, W, data, "f64", 8, max(3, args.steps // 2), args.warmup)
+        gpu["f64_m8"] = run_path(H, torch, W, data, "f64", 8, max(3, args.steps // 2), args.warmup, args.method)
         log("f64 m=8: %.3f ms/step" % gpu["f64_m8"]["ms_per_step"])
 
     main_res = gpu["f32_m4"]
@@ -651,7 +655,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "NFFT N=64^3 (n=128^3, sigma=2), M=2^20 uniform points, complex64, "
                                "Kaiser-Bessel m=4; step = set_points + adjoint (Eq. 5) + forward (Eq. 6)",
-                   "N": list(N), "M": M, "m": 4, "sigma": 2.0, "tiles": list(main_res["tiles"])},
+                   "N": list(N), "M": M, "m": 4, "sigma": 2.0, "tiles": list(main_res["tiles"]),
+                   "method": main_res["method"]},
         "roofline": roof,
         "hbm_copy_gbs": round(copy_gbs, 1),
         "spread_gbs_algorithmic": None if spread_gbs is None else round(spread_gbs, 1),
@@ -667,7 +672,7 @@ def main():
             t64, roof64, sp64 = summarize(r64, "f64", mm, copy_gbs)
             out["fp64_m%d" % mm] = {"value": round(M / (r64["ms_per_step"] * 1e-3), 1), "unit": "points/s",
                                     "ms_per_step": round(r64["ms_per_step"], 4), "dtype": "f64", "m": mm,
-                                    "tiles": list(r64["tiles"]), "roofline": roof64,
+                                    "tiles": list(r64["tiles"]), "method": r64["method"], "roofline": roof64,
                                     "spread_gbs_algorithmic": None if sp64 is None else round(sp64, 1),
                                     "phases": t64}
         # E1 speed-up at equal M, N and m; the m = 8 ratio is the 1e-12 path's

@@ -109,9 +109,32 @@ int hpnfft_plan_destroy(hpnfft_plan plan);
  * hpnfft_batch_capture is in use. */
 int hpnfft_set_stream(hpnfft_plan plan, void *hip_stream);
 
+/* Sweep method of the spread and the interpolation (the Spreading and
+ * Interpolating steps of Section 3).  Must be called before
+ * hpnfft_set_workspace; resets the tiling to the method's default.
+ *   HPNFFT_METHOD_LINES  points sorted into runs along dim 0 and swept with
+ *                        register windows; LDS tiles with a halo of 2m - 1
+ *                        cells flushed with global atomic adds (dense
+ *                        point sets)
+ *   HPNFFT_METHOD_BOXES  every workgroup owns one output box (>= m cells per
+ *                        edge) and takes the points of the 27 boxes around
+ *                        it; the grid is written once, with plain stores
+ *                        (sparse point sets)
+ *   HPNFFT_METHOD_AUTO   (the default) boxes below 0.1 (float64) or 0.02
+ *                        (float32) points per grid cell
+ * The results agree to rounding; hpnfft_get_method reports the method in use
+ * (LINES or BOXES). */
+#define HPNFFT_METHOD_AUTO  0
+#define HPNFFT_METHOD_LINES 1
+#define HPNFFT_METHOD_BOXES 2
+int hpnfft_set_method(hpnfft_plan plan, int method);
+int hpnfft_get_method(hpnfft_plan plan, int *method);
+
 /* Spread/interpolation tiling: tile edge in the two fastest grid dimensions
  * (cells, 4..32), slab depth along the slowest dimension (cells, 2..64) and
  * threads per workgroup (multiple of 64, <= 1024).  Pass 0 to keep a value.
+ * With the box method, tile and slab are the target box edges (>= m) in
+ * dims 1, 2 and in dim 0; threads is not used (512).
  * Must be called before hpnfft_set_workspace.  EINVAL if the tile does not
  * fit the 160 KiB local data share, or if 2m = 8 and the tile edge is not a
  * multiple of 8 (those plans sort points in blocks of 8 lines). */

@@ -23,6 +23,8 @@ struct Xform {
     int nslab;         // slabs along dim 0
     int flat;          // leading dims that carry no coordinate (d = 3 - flat):
                        // N_t = 1, every point at cell 0, window = unit impulse
+    int nbox[3];       // box method: point bins along dims 0, 1, 2 (0: line method)
+    int gbox[3];       // box method: bins per output box along dims 0, 1, 2
     long long M;       // points
     long long poff;    // first sorted point of this transform (packed arrays)
     long long foff;    // first frequency of this transform (packed fhat)
@@ -39,6 +41,19 @@ struct Xform {
 struct SItem {
     int xf, tile, slab, lb, le, pad0, pad1, pad2;
 };
+
+// Point bins of the box method: bin i along a dim of n cells split into nb
+// bins covers cells [box_lo(i), box_lo(i + 1)); box_of inverts it.  Every
+// bin is at least m cells wide, so a window reaches only the bins next to its
+// own; an output box is a block of gbox consecutive bins per dim.
+__host__ __device__ inline int box_lo(int i, int n, int nb) { return (int)(((long long)i * n) / nb); }
+__host__ __device__ inline int box_of(int c, int n, int nb) { return (int)(((long long)(c + 1) * nb - 1) / n); }
+__host__ __device__ inline int box_key(const int c[3], const int n[3], const int nb[3])
+{
+    return (box_of(c[0], n[0], nb[0]) * nb[1] + box_of(c[1], n[1], nb[1])) * nb[2] + box_of(c[2], n[2], nb[2]);
+}
+// Box method record header: plane c0, and (c1 << 11) | c2 (cells < 2048).
+constexpr int kBoxCellBits = 11;
 
 // Work item of an FFT pass: `count` pencils starting at (outer, inner0).
 struct FItem {
@@ -164,6 +179,7 @@ hipError_t launch_zero(void *p, size_t bytes, hipStream_t s);
 hipError_t launch_copy(void *dst, const void *src, size_t bytes, int cus, hipStream_t s);
 // x / xf32 hold M x (3 - flat) coordinates; xs_out (if not null) receives
 // them as M x 3 with the flat dims zero.
+// Box-method plans (X.nbox[0] > 0) sort by output box instead of by line.
 hipError_t launch_bin_count(const double *x, const float *xf32, long long M, const Xform &X, int T, int BW,
                             int flat, int *counts, int *rank, int *err, double *xs_out, hipStream_t s);
 hipError_t launch_scan(int *data, long long n, int *tmp, hipStream_t s);
@@ -193,6 +209,17 @@ hipError_t launch_fft(int pass, const Xform *dxf, const FItem *items, int nitems
 constexpr int kEwaldRealTile = 256;
 hipError_t launch_ewald_real(const double *r, const double *q, long long M, double L, double alpha,
                              double rcut, double *partials, double *energy, double *forces, hipStream_t s);
+// Box method (k_boxes.hip): every workgroup owns one output box of the grid
+// and takes every point whose window reaches it.
+template <typename R>
+hipError_t launch_spread_box(int m, const Xform *dxf, const SItem *items, int nitems, int *queue, int max_cells,
+                             const unsigned char *rec, size_t rec_bytes, const R *fs, const int *cell_start,
+                             hipStream_t s);
+template <typename R>
+hipError_t launch_interp_box(int m, bool grad, const Xform *dxf, const SItem *items, int nitems, int *queue,
+                             int max_cells, const unsigned char *rec, size_t rec_bytes, const int *cell_start,
+                             R *outs, hipStream_t s);
+
 // Fixed-order sum of n float64 partials into *out (one workgroup).
 hipError_t launch_sum_partials(const double *part, int n, double *out, hipStream_t s);
 // Cell-list real-space Ewald sum (k_ewald.hip): workspace regions and launch.

@@ -55,12 +55,13 @@ __device__ inline int sort_key(const int c[3], int T, int ntx, int n0, int BW)
 // coordinate) read d values per point and store three, the flat ones zero.
 template <typename XT>
 __global__ void k_bin_count(const XT *__restrict__ x, long long M, int n0, int n1, int n2, int T, int ntx,
-                            int BW, int flat, int *__restrict__ counts, int *__restrict__ rank,
-                            int *__restrict__ err, double *__restrict__ xs_out)
+                            int BW, int flat, int nb0, int nb1, int nb2, int *__restrict__ counts,
+                            int *__restrict__ rank, int *__restrict__ err, double *__restrict__ xs_out)
 {
     long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= M) return;
     const int n[3] = {n0, n1, n2};
+    const int nbox[3] = {nb0, nb1, nb2};
     const int d = 3 - flat;
     bool bad = false;
     int c[3];
@@ -82,7 +83,8 @@ __global__ void k_bin_count(const XT *__restrict__ x, long long M, int n0, int n
         }
     }
     if (bad) atomicOr(err, 1);
-    rank[j] = atomicAdd(&counts[sort_key(c, T, ntx, n0, BW)], 1);
+    const int key = nb0 ? box_key(c, n, nbox) : sort_key(c, T, ntx, n0, BW);
+    rank[j] = atomicAdd(&counts[key], 1);
 }
 
 // Scatter of the points into sorted order, with the window values of each
@@ -131,7 +133,8 @@ __global__ __launch_bounds__(256) void k_bin_scatter(const double *__restrict__ 
                                                      const int *__restrict__ rank, int *__restrict__ perm,
                                                      int *__restrict__ ipos, unsigned char *__restrict__ rec,
                                                      size_t rec_bytes, WindowParams wp,
-                                                     const double *__restrict__ poly, int flat)
+                                                     const double *__restrict__ poly, int flat, int nb0, int nb1,
+                                                     int nb2)
 {
     constexpr int m = M2 / 2;
     constexpr int NW = 3 * M2;
@@ -147,7 +150,9 @@ __global__ __launch_bounds__(256) void k_bin_scatter(const double *__restrict__ 
         const double xv = xd ? xd[j * 3 + t] : (double)xf[j * 3 + t];
         c[t] = cell_of(xv, n[t], &u[t], &bad);
     }
-    const long long pos = poff + cell_start[sort_key(c, T, ntx, n0, block_w(M2))] + rank[j];
+    const int nbox[3] = {nb0, nb1, nb2};
+    const int key = nb0 ? box_key(c, n, nbox) : sort_key(c, T, ntx, n0, block_w(M2));
+    const long long pos = poff + cell_start[key] + rank[j];
     perm[pos] = (int)(poff + j);
     ipos[poff + j] = (int)pos;
     unsigned char *rp = rec + pos * rec_bytes;
@@ -176,7 +181,9 @@ __global__ __launch_bounds__(256) void k_bin_scatter(const double *__restrict__ 
         }
     }
     // dim 0 into slot order, slot s = (tap + rot) mod 2m: a rotation by rot
-    // composed of conditional rotations by 1, 2, 4, ... (constant indices)
+    // composed of conditional rotations by 1, 2, 4, ... (constant indices).
+    // The box method keeps tap order.
+    if (nb0) rot = 0;
 #pragma unroll
     for (int k = 1; k < M2; k <<= 1) {
         if (rot & k) {
@@ -194,7 +201,8 @@ __global__ __launch_bounds__(256) void k_bin_scatter(const double *__restrict__ 
         }
     }
     store_block<NW * sizeof(R)>(rp, w);
-    *reinterpret_cast<int2 *>(rp + rec_off_pz(M2, sizeof(R))) = make_int2(c[0], (c[2] % T) % block_w(M2));
+    *reinterpret_cast<int2 *>(rp + rec_off_pz(M2, sizeof(R))) =
+        nb0 ? make_int2(c[0], (c[1] << kBoxCellBits) | c[2]) : make_int2(c[0], (c[2] % T) % block_w(M2));
     if constexpr (GRAD) store_block<NW * sizeof(R)>(rp + rec_prefix(M2, sizeof(R)), dw);
 }
 
@@ -338,10 +346,10 @@ hipError_t launch_bin_count(const double *x, const float *xf32, long long M, con
     const unsigned nb = (unsigned)((M + 255) / 256);
     if (x)
         hipLaunchKernelGGL(k_bin_count<double>, dim3(nb), dim3(256), 0, s, x, M, X.n[0], X.n[1], X.n[2], T,
-                           X.ntx, BW, flat, counts, rank, err, xs_out);
+                           X.ntx, BW, flat, X.nbox[0], X.nbox[1], X.nbox[2], counts, rank, err, xs_out);
     else
         hipLaunchKernelGGL(k_bin_count<float>, dim3(nb), dim3(256), 0, s, xf32, M, X.n[0], X.n[1], X.n[2], T,
-                           X.ntx, BW, flat, counts, rank, err, xs_out);
+                           X.ntx, BW, flat, X.nbox[0], X.nbox[1], X.nbox[2], counts, rank, err, xs_out);
     return hipGetLastError();
 }
 
@@ -353,7 +361,8 @@ static void scatter_m(const double *x, const float *xf32, long long M, const Xfo
     const unsigned nb = (unsigned)((M + 255) / 256);
     auto k = grad ? k_bin_scatter<R, M2, true> : k_bin_scatter<R, M2, false>;
     hipLaunchKernelGGL(k, dim3(nb), dim3(256), 0, s, x, xf32, M, X.poff, X.n[0], X.n[1], X.n[2], T, X.ntx,
-                       cell_start, rank, perm, ipos, rec, rec_bytes, wp, poly, X.flat);
+                       cell_start, rank, perm, ipos, rec, rec_bytes, wp, poly, X.flat, X.nbox[0], X.nbox[1],
+                       X.nbox[2]);
 }
 
 template <typename R>

@@ -93,6 +93,12 @@ struct hpnfft_plan_s {
     std::map<int, std::vector<unsigned char>> h_tw;
     std::vector<FItem> h_fit[3];
     int nitems = 0;
+    // sweep method: requested (HPNFFT_METHOD_*) and in use; the box method's
+    // static work list (one item per output box) and largest box (cells)
+    int method = HPNFFT_METHOD_AUTO;
+    bool boxes = false;
+    int max_cells = 0;
+    std::vector<SItem> h_box_items;
     int cus = 256;
     char arch[64] = "unknown";
     int maxn = 0;
@@ -186,7 +192,7 @@ void hlog(const char *fmt, ...)
 // architecture and compute-unit count, precision, cut-off, window, sigma,
 // the gradient flag, and per transform the grid edges and the point count
 // rounded down to a power of two (batches: a hash of that list).
-constexpr int kTuneCacheVersion = 1;
+constexpr int kTuneCacheVersion = 2;
 
 const char *tune_cache_path()
 {
@@ -197,9 +203,9 @@ const char *tune_cache_path()
 std::string tune_key(const hpnfft_plan_s *p)
 {
     char head[256];
-    std::snprintf(head, sizeof(head), "v%d|%s|cu%d|%s|m%d|w%d|s%.6g|g%d|B%d", kTuneCacheVersion, p->arch,
+    std::snprintf(head, sizeof(head), "v%d|%s|cu%d|%s|m%d|w%d|s%.6g|g%d|B%d|%s", kTuneCacheVersion, p->arch,
                   p->cus, p->prec == HPNFFT_F32 ? "f32" : "f64", p->m, p->window, p->sigma, p->grad() ? 1 : 0,
-                  p->B);
+                  p->B, p->boxes ? "boxes" : "lines");
     std::string list;
     for (const Xform &X : p->hx) {
         int mb = 0;
@@ -299,10 +305,72 @@ void drop_graph(hpnfft_plan_s *p)
     p->graph = nullptr;
 }
 
+// Boxes along a dim of n cells for a target box edge Tb: edges stay >= m (a
+// window then reaches only the neighbouring boxes) and <= Tb when n allows.
+int box_count(int n, int Tb, int m)
+{
+    return std::max(1, std::min(n / m, (n + Tb - 1) / Tb));
+}
+
+// Box method along one dim of n cells, for a target box edge Tb >= m:
+// point bins of about max(m, 4) cells (at least m), gbox bins per output
+// box, nb boxes, and an upper bound on the box edge.
+struct BoxDim {
+    int nbins, gbox, nb, maxw;
+};
+BoxDim box_dim(int n, int Tb, int m)
+{
+    BoxDim b;
+    const int edge = std::max(m, 4);
+    b.nbins = box_count(n, edge, m);
+    b.gbox = std::max(1, std::min(6, Tb / edge));  // at most 8^3 bins around a box
+    b.nb = (b.nbins + b.gbox - 1) / b.gbox;
+    b.maxw = b.gbox * ((n + b.nbins - 1) / b.nbins);
+    return b;
+}
+
+// Largest box (cells) of the box method over the plan's transforms.
+long long box_max_cells(const hpnfft_plan_s *p, Tiling t)
+{
+    long long best = 0;
+    for (const Xform &X : p->hx) {
+        long long c = 1;
+        for (int d = 0; d < 3; ++d) c *= box_dim(X.n[d], d == 0 ? t.Zs : t.T, p->m).maxw;
+        best = std::max(best, c);
+    }
+    return best;
+}
+
+// Method in use: the box method below a density of points per grid cell
+// (or when requested).  Its float64 taps are single native LDS atomic adds;
+// float32 taps need a compensated compare-and-swap each (gfx950's LDS
+// float32 atomic add runs at 0.33 lanes per clock per compute unit against
+// 7.6 for float64 and 3.5 for the 64-bit swap), so float32 switches later.
+// Measured on MI355X: at 0.5 points per cell the line sweeps are 3.5-10x
+// faster; at 0.05 (the 256-transform batch, float32) 1.9x; at 0.01 (the
+// 24^3-cell Ewald lattice on a 256^3 grid) the boxes are 2.2x (float64) and
+// 1.3x (float32) faster.
+constexpr double kBoxDensityF64 = 0.1;
+constexpr double kBoxDensityF32 = 0.02;
+bool choose_boxes(const hpnfft_plan_s *p)
+{
+    if (p->method == HPNFFT_METHOD_LINES) return false;
+    if (p->method == HPNFFT_METHOD_BOXES) return true;
+    double cells = 0.0;
+    for (const Xform &X : p->hx) cells += (double)X.n[0] * X.n[1] * X.n[2];
+    return (double)p->Mtot < (p->prec == HPNFFT_F32 ? kBoxDensityF32 : kBoxDensityF64) * cells;
+}
+
 bool tiling_fits(const hpnfft_plan_s *p, Tiling t)
 {
     if (t.T < 4 || t.T > 32 || t.Zs < 2 || t.Zs > 64) return false;
     if (t.threads < 64 || t.threads > 1024 || t.threads % 64) return false;
+    if (p->boxes) {
+        // box edges (dims 1, 2: T; dim 0: Zs) of at least m cells
+        if (t.T < p->m || t.Zs < p->m) return false;
+        // the box tile in LDS beside the run lists (12 KiB of static LDS)
+        return box_max_cells(p, t) * 16 + 12 * 1024 <= (long long)kLdsLimit;
+    }
     if (t.T % block_w(p->M2())) return false;  // whole blocks of lines per tile row
     bool comp = p->prec == HPNFFT_F32;
     if (!lds_fit(t.T, t.Zs, p->M2(), p->rbytes(), 0, comp).cap) return false;
@@ -322,6 +390,12 @@ bool tiling_fits(const hpnfft_plan_s *p, Tiling t)
 Tiling default_tiling(const hpnfft_plan_s *p)
 {
     const int M2 = p->M2();
+    if (p->boxes) {
+        // boxes of 16 cells per edge (16 KiB of (sum, error) or float64 pairs
+        // per 1024 cells: 64 KiB, two workgroups per compute unit)
+        for (int Tb : {16, 12, 8})
+            if (tiling_fits(p, Tiling{Tb, Tb, 512})) return Tiling{Tb, Tb, 512};
+    }
     // blocked 2m = 8 sweeps: tiles of one block of lines per row fit best
     const int target = block_w(M2) > 1 ? 8 : std::max(4, 22 - M2);
     std::vector<int> Ts = {4, 6, 8, 12, 16, 24, 32};
@@ -362,17 +436,36 @@ void build_layout(hpnfft_plan_s *p)
     L.xs = take((size_t)p->Mtot * 24);
     size_t gbytes = 0;
     long long maxkeys = 0, maxM = 0, pairs = 0, maxF = 0;
+    p->h_box_items.clear();
+    p->max_cells = 0;
     for (int b = 0; b < p->B; ++b) {
         Xform &X = p->hx[b];
         X.ntx = (X.n[2] + T - 1) / T;
         X.nty = (X.n[1] + T - 1) / T;
         X.nslab = (X.n[0] + Zs - 1) / Zs;
         p->keys[b] = (long long)X.ntx * X.nty * T * T * X.n[0] + 1;
+        for (int d = 0; d < 3; ++d) X.nbox[d] = X.gbox[d] = 0;
+        if (p->boxes) {
+            // box method: sort keys are point bins; one work item per output box
+            long long nbins = 1, nboxes = 1, cells = 1;
+            for (int d = 0; d < 3; ++d) {
+                const BoxDim bd = box_dim(X.n[d], d == 0 ? Zs : T, p->m);
+                X.nbox[d] = bd.nbins;
+                X.gbox[d] = bd.gbox;
+                nbins *= bd.nbins;
+                nboxes *= bd.nb;
+                cells *= bd.maxw;
+            }
+            p->keys[b] = nbins + 1;
+            for (long long q = 0; q < nboxes; ++q) p->h_box_items.push_back(SItem{b, (int)q, 0, 0, 0, 0, 0, 0});
+            p->max_cells = std::max(p->max_cells, (int)cells);
+        }
         maxkeys = std::max(maxkeys, p->keys[b]);
         maxM = std::max(maxM, X.M);
         pairs += (long long)X.ntx * X.nty * X.nslab;
         maxF = std::max(maxF, (long long)X.N[0] * X.N[1] * X.N[2]);
     }
+    if (p->boxes) pairs = std::max<long long>(pairs, (long long)p->h_box_items.size());
     // grids (contiguous, zeroed by one launch)
     L.grids = off;
     for (int b = 0; b < p->B; ++b) {
@@ -407,7 +500,7 @@ void build_layout(hpnfft_plan_s *p)
     L.tcost = off;
     for (int b = 0; b < p->B; ++b) {
         const Xform &X = p->hx[b];
-        L.tcost_off.push_back(take((size_t)X.ntx * X.nty * X.nslab * (T * T / block_w(p->M2())) * 4));
+        L.tcost_off.push_back(take(p->boxes ? 0 : (size_t)X.ntx * X.nty * X.nslab * (T * T / block_w(p->M2())) * 4));
     }
     L.max_items = (int)std::min<long long>(pairs + (long long)p->cus * 4 + 64, 0x7fffffffLL / 64);
     L.items = take((size_t)L.max_items * sizeof(SItem));
@@ -606,6 +699,12 @@ int upload_tables(hpnfft_plan_s *p)
     }
     HCHECK(hipMemcpyAsync(p->ws + L.xf, p->hx.data(), p->hx.size() * sizeof(Xform), hipMemcpyHostToDevice,
                           p->stream));
+    if (p->boxes) {
+        // the box method's work list does not depend on the points
+        HCHECK(hipMemcpyAsync(p->ws + L.items, p->h_box_items.data(), p->h_box_items.size() * sizeof(SItem),
+                              hipMemcpyHostToDevice, p->stream));
+        p->nitems = (int)p->h_box_items.size();
+    }
     // the host sources must outlive the copies
     HCHECK(hipStreamSynchronize(p->stream));
     return HPNFFT_OK;
@@ -691,10 +790,11 @@ int bin_points(hpnfft_plan_s *p, const double *x = nullptr, const float *x32 = n
                                               p->poly_ok ? p->at<double>(L.poly) : nullptr, cs,
                                               p->at<int>(L.rank), p->at<int>(L.perm), p->at<int>(L.ipos),
                                               p->at<unsigned char>(L.rec), L.rec_bytes, p->grad(), s));
-        HCHECK(launch_tile_cost(cs, X, p->til.T, p->til.Zs, p->m, p->at<int>(L.tcost_off[b]), total, s));
+        if (!p->boxes)
+            HCHECK(launch_tile_cost(cs, X, p->til.T, p->til.Zs, p->m, p->at<int>(L.tcost_off[b]), total, s));
     }
     const int cap_div = p->cus * 4;
-    for (int b = 0; b < p->B; ++b) {
+    for (int b = 0; b < p->B && !p->boxes; ++b) {
         const Xform &X = p->hx[b];
         HCHECK(launch_make_items(p->at<int>(L.tcost_off[b]), b, X, p->til.T, p->m, total, cap_div, kMinCap,
                                  L.max_items, p->at<SItem>(L.items), setp + 1, setp + 2, s));
@@ -716,6 +816,10 @@ int bin_points(hpnfft_plan_s *p, const double *x = nullptr, const float *x32 = n
     std::memcpy(host, p->hres, sizeof(host));
     if (host[0]) return HPNFFT_EDOMAIN;
     if (host[2]) return HPNFFT_ENOMEM;
+    if (p->boxes) {
+        p->nitems = (int)p->h_box_items.size();
+        return HPNFFT_OK;
+    }
     p->nitems = std::min(host[1], L.max_items);
     // staging worth reserving per chunk: twice the mean points per item
     unsigned long long tot = 0;
@@ -730,7 +834,7 @@ template <typename R> int run_adjoint(hpnfft_plan_s *p, const void *f, void *fha
     const Layout &L = p->L;
     hipStream_t s = p->stream;
     const Xform *dxf = p->at<Xform>(L.xf);
-    {
+    if (!p->boxes) {  // the box method writes every grid cell itself
         PhaseTimer t(p, HPNFFT_PH_ZERO);
         HCHECK(launch_zero(p->ws + L.grids, L.grids_bytes, s));
     }
@@ -740,9 +844,14 @@ template <typename R> int run_adjoint(hpnfft_plan_s *p, const void *f, void *fha
     }
     {
         PhaseTimer t(p, HPNFFT_PH_SPREAD);
-        HCHECK(launch_spread<R>(p->m, dxf, p->at<SItem>(L.items), p->nitems, p->at<int>(L.counters), p->til,
-                                p->at<unsigned char>(L.rec), L.rec_bytes, p->at<R>(L.fs), p->at<int>(L.cell_start),
-                                s));
+        if (p->boxes)
+            HCHECK(launch_spread_box<R>(p->m, dxf, p->at<SItem>(L.items), p->nitems, p->at<int>(L.counters),
+                                        p->max_cells, p->at<unsigned char>(L.rec), L.rec_bytes, p->at<R>(L.fs),
+                                        p->at<int>(L.cell_start), s));
+        else
+            HCHECK(launch_spread<R>(p->m, dxf, p->at<SItem>(L.items), p->nitems, p->at<int>(L.counters), p->til,
+                                    p->at<unsigned char>(L.rec), L.rec_bytes, p->at<R>(L.fs),
+                                    p->at<int>(L.cell_start), s));
     }
     for (int pass = P_ADJ0; pass <= P_ADJ2; ++pass) {
         int d = pass == P_ADJ0 ? 2 : (pass == P_ADJ1 ? 1 : 0);
@@ -779,9 +888,14 @@ template <typename R> int run_forward(hpnfft_plan_s *p, const void *fhat, void *
     if (rc) return rc;
     {
         PhaseTimer t(p, HPNFFT_PH_INTERP);
-        HCHECK(launch_interp<R>(p->m, false, dxf, p->at<SItem>(L.items), p->nitems,
-                                p->at<int>(L.counters) + 1, p->til, p->at<unsigned char>(L.rec), L.rec_bytes,
-                                p->at<int>(L.cell_start), p->at<R>(L.outs), s));
+        if (p->boxes)
+            HCHECK(launch_interp_box<R>(p->m, false, dxf, p->at<SItem>(L.items), p->nitems,
+                                        p->at<int>(L.counters) + 1, p->max_cells, p->at<unsigned char>(L.rec),
+                                        L.rec_bytes, p->at<int>(L.cell_start), p->at<R>(L.outs), s));
+        else
+            HCHECK(launch_interp<R>(p->m, false, dxf, p->at<SItem>(L.items), p->nitems,
+                                    p->at<int>(L.counters) + 1, p->til, p->at<unsigned char>(L.rec), L.rec_bytes,
+                                    p->at<int>(L.cell_start), p->at<R>(L.outs), s));
     }
     {
         PhaseTimer t(p, HPNFFT_PH_SCATTER);
@@ -804,9 +918,14 @@ int run_backward(hpnfft_plan_s *p, const void *f, const void *gfhat, void *grad_
     if (rc) return rc;
     {
         PhaseTimer t(p, HPNFFT_PH_GRAD);
-        HCHECK(launch_interp<R>(p->m, true, dxf, p->at<SItem>(L.items), p->nitems,
-                                p->at<int>(L.counters) + 1, p->til, p->at<unsigned char>(L.rec), L.rec_bytes,
-                                p->at<int>(L.cell_start), p->at<R>(L.outs), s));
+        if (p->boxes)
+            HCHECK(launch_interp_box<R>(p->m, true, dxf, p->at<SItem>(L.items), p->nitems,
+                                        p->at<int>(L.counters) + 1, p->max_cells, p->at<unsigned char>(L.rec),
+                                        L.rec_bytes, p->at<int>(L.cell_start), p->at<R>(L.outs), s));
+        else
+            HCHECK(launch_interp<R>(p->m, true, dxf, p->at<SItem>(L.items), p->nitems,
+                                    p->at<int>(L.counters) + 1, p->til, p->at<unsigned char>(L.rec), L.rec_bytes,
+                                    p->at<int>(L.cell_start), p->at<R>(L.outs), s));
     }
     {
         PhaseTimer t(p, HPNFFT_PH_GRAD_FIN);
@@ -899,6 +1018,7 @@ int create_common(hpnfft_plan_s **out, int B, const int64_t *N, const int64_t *M
             p->arch[k] = 0;
         }
     }
+    p->boxes = choose_boxes(p);
     p->til = default_tiling(p);
     build_layout(p);
     prepare_host_tables(p);
@@ -977,6 +1097,26 @@ int hpnfft_set_tiles(hpnfft_plan p, int tile, int slab, int threads)
     build_layout(p);
     p->have_ws = false;
     p->have_points = false;
+    return HPNFFT_OK;
+}
+
+int hpnfft_set_method(hpnfft_plan p, int method)
+{
+    if (!p || method < HPNFFT_METHOD_AUTO || method > HPNFFT_METHOD_BOXES) return HPNFFT_EINVAL;
+    drop_graph(p);
+    p->method = method;
+    p->boxes = choose_boxes(p);
+    p->til = default_tiling(p);
+    build_layout(p);
+    p->have_ws = false;
+    p->have_points = false;
+    return HPNFFT_OK;
+}
+
+int hpnfft_get_method(hpnfft_plan p, int *method)
+{
+    if (!p || !method) return HPNFFT_EINVAL;
+    *method = p->boxes ? HPNFFT_METHOD_BOXES : HPNFFT_METHOD_LINES;
     return HPNFFT_OK;
 }
 
@@ -1223,20 +1363,27 @@ int hpnfft_autotune(hpnfft_plan p, void *scratch_f, void *scratch_fhat, int *til
     if (!p->have_points) return HPNFFT_ESTATE;
     drop_graph(p);
     // candidates that fit the attached workspace
+    // (line method: tile edge, slab depth, threads; box method: box edges)
     std::vector<Tiling> cand;
-    for (int T : {4, 6, 8, 12, 16})
-        for (int Zs : {8, 16, 24, 32})
-            for (int th : {512, 1024}) {
-                Tiling t{T, Zs, th};
-                if (!tiling_fits(p, t)) continue;
-                Tiling keep = p->til;
-                p->til = t;
-                build_layout(p);
-                size_t need = p->L.total;
-                p->til = keep;
-                build_layout(p);
-                if (need <= p->ws_bytes) cand.push_back(t);
-            }
+    std::vector<Tiling> grid;
+    if (p->boxes) {
+        for (int T : {8, 12, 16, 20, 24, 32})
+            for (int Zs : {8, 12, 16, 20, 24, 32}) grid.push_back(Tiling{T, Zs, 512});
+    } else {
+        for (int T : {4, 6, 8, 12, 16})
+            for (int Zs : {8, 16, 24, 32})
+                for (int th : {512, 1024}) grid.push_back(Tiling{T, Zs, th});
+    }
+    for (const Tiling &t : grid) {
+        if (!tiling_fits(p, t)) continue;
+        Tiling keep = p->til;
+        p->til = t;
+        build_layout(p);
+        size_t need = p->L.total;
+        p->til = keep;
+        build_layout(p);
+        if (need <= p->ws_bytes) cand.push_back(t);
+    }
     // The stored float64 points sit at the same workspace offset in every
     // layout (build_layout), so a candidate re-bins them where they are.
     auto install = [&](Tiling t) -> int {

@@ -66,10 +66,12 @@ class Ewald:
     in a cubic box of side L (positions anywhere; wrapped periodically)."""
 
     def __init__(self, M: int, L_box: float, alpha: float, N: Sequence[int] = (64, 64, 64), m: int = 8,
-                 precision: str = "f64", rcut: Optional[float] = None, device="cuda", real_method: str = "auto"):
+                 precision: str = "f64", rcut: Optional[float] = None, device="cuda", real_method: str = "auto",
+                 method: str = "auto"):
         self.M, self.L, self.alpha = int(M), float(L_box), float(alpha)
         self.rcut = float(rcut) if rcut is not None else 0.5 * self.L
-        self.plan = H.Plan(tuple(N), self.M, m=m, precision=precision, with_grad=True, device=device)
+        self.plan = H.Plan(tuple(N), self.M, m=m, precision=precision, with_grad=True, device=device,
+                           method=method)
         self.device = self.plan.device
         if real_method not in ("auto", "cells", "direct"):
             raise ValueError("real_method must be auto, cells or direct")

@@ -21,6 +21,8 @@ HEADER = os.path.join(os.path.dirname(_HERE), "include", "hpnfft.h")
 
 OK, EINVAL, EDOMAIN, ENOMEM, EHIP, ESTATE, ESIZE = 0, -1, -2, -3, -4, -5, -6
 KAISER_BESSEL, GAUSSIAN, BSPLINE, SINC_POWER = 0, 1, 2, 3
+METHOD_AUTO, METHOD_LINES, METHOD_BOXES = 0, 1, 2
+METHODS = {"auto": METHOD_AUTO, "lines": METHOD_LINES, "boxes": METHOD_BOXES}
 WINDOWS = {"kaiser_bessel": KAISER_BESSEL, "kb": KAISER_BESSEL, "gaussian": GAUSSIAN,
            "bspline": BSPLINE, "sinc_power": SINC_POWER}
 F64, F32 = 0, 1
@@ -57,6 +59,8 @@ def _load():
         "hpnfft_plan_destroy": (ctypes.c_int, [P]),
         "hpnfft_set_stream": (ctypes.c_int, [P, P]),
         "hpnfft_set_tiles": (ctypes.c_int, [P, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
+        "hpnfft_set_method": (ctypes.c_int, [P, ctypes.c_int]),
+        "hpnfft_get_method": (ctypes.c_int, [P, ip]),
         "hpnfft_get_tiles": (ctypes.c_int, [P, ip, ip, ip]),
         "hpnfft_workspace_size": (ctypes.c_int, [P, ctypes.POINTER(ctypes.c_size_t)]),
         "hpnfft_set_workspace": (ctypes.c_int, [P, P, ctypes.c_size_t]),
@@ -143,7 +147,7 @@ class Plan:
 
     def __init__(self, N, M, sigma: float = 2.0, m: int = 8, precision: str = "f64",
                  with_grad: bool = False, device="cuda", tiles: Optional[Sequence[int]] = None,
-                 window: str = "kaiser_bessel"):
+                 window: str = "kaiser_bessel", method: str = "auto"):
         lib = _load()
         self.device = _require_gpu(device)
         if isinstance(M, int):
@@ -177,6 +181,8 @@ class Plan:
                 rc = lib.hpnfft_plan_create(ctypes.byref(self._h), self.d, Narr, Ms[0], self.sigma, self.m,
                                             win, self.prec_code, flags)
         _check(rc, "plan_create")
+        if method != "auto":
+            _check(lib.hpnfft_set_method(self._h, METHODS[method]), "set_method")
         self.Mtot = sum(Ms)
         self.Ftot = sum(math.prod(n) for n in Ns)
         if tiles is not None:
@@ -218,6 +224,13 @@ class Plan:
         return t.contiguous()
 
     # -- API ---------------------------------------------------------------
+    @property
+    def method(self) -> str:
+        """Sweep method in use: "lines" or "boxes"."""
+        v = ctypes.c_int()
+        _check(_load().hpnfft_get_method(self._h, ctypes.byref(v)), "get_method")
+        return {METHOD_LINES: "lines", METHOD_BOXES: "boxes"}[v.value]
+
     @property
     def tiles(self):
         a, b, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
@@ -302,14 +315,17 @@ class Plan:
         # grow the workspace to fit every candidate (sizes depend on tiling)
         need = self.ws_bytes
         keep = self.tiles
-        # the candidate set of hpnfft_autotune
-        for T in (4, 6, 8, 12, 16):
-            for Zs in (8, 16, 24, 32):
-                for th in (512, 1024):
-                    if lib.hpnfft_set_tiles(self._h, T, Zs, th) == OK:
-                        sz = ctypes.c_size_t()
-                        lib.hpnfft_workspace_size(self._h, ctypes.byref(sz))
-                        need = max(need, int(sz.value))
+        # the candidate set of hpnfft_autotune (line method: tile, slab,
+        # threads; box method: box edges)
+        if self.method == "boxes":
+            grid = [(T, Zs, 512) for T in (8, 12, 16, 20, 24, 32) for Zs in (8, 12, 16, 20, 24, 32)]
+        else:
+            grid = [(T, Zs, th) for T in (4, 6, 8, 12, 16) for Zs in (8, 16, 24, 32) for th in (512, 1024)]
+        for T, Zs, th in grid:
+            if lib.hpnfft_set_tiles(self._h, T, Zs, th) == OK:
+                sz = ctypes.c_size_t()
+                lib.hpnfft_workspace_size(self._h, ctypes.byref(sz))
+                need = max(need, int(sz.value))
         if max_workspace_bytes is not None:
             need = min(need, int(max_workspace_bytes))
         _check(lib.hpnfft_set_tiles(self._h, *keep), "set_tiles")

@@ -72,7 +72,7 @@ def test_autograd_gradcheck_tiny(H):
     N = (8, 8, 8)
     M = 5
     g = W.rng(402)
-    plan = H.Plan(N, M, m=8, precision="f64", with_grad=True, tiles=(4, 8, 256))
+    plan = H.Plan(N, M, m=8, precision="f64", with_grad=True, tiles=(4, 8, 256), method="lines")
     x = torch.from_numpy(W.uniform_points(M, 3, g) * 0.8).cuda().requires_grad_(True)
     f = torch.from_numpy(W.complex_normal(M, g)).cuda().requires_grad_(True)
     fn = lambda xx, ff: H.nfft_adjoint(xx, ff, plan)  # noqa: E731
