@@ -71,6 +71,16 @@ extern "C" {
 /* ---- plan flags ------------------------------------------------------ */
 #define HPNFFT_WITH_GRADIENT 1u  /* also tabulate window derivatives at set_points,
                                     enabling hpnfft_adjoint_backward            */
+#define HPNFFT_DETERMINISTIC 2u  /* bitwise reproducible results: points sorted
+                                    stably by bin and input index, every sum
+                                    taken in a fixed order (one wavefront per
+                                    output box in the spread, per point in the
+                                    interpolation), no floating-point atomics.
+                                    Repeated calls, and repeated set_points of
+                                    the same points, give identical bits for a
+                                    given plan and tiling.  Uses the box bins
+                                    (hpnfft_set_method: LINES is refused);
+                                    slower than the default paths.           */
 
 typedef struct hpnfft_plan_s *hpnfft_plan;
 typedef struct hpnfft_plan_s *hpnfft_batch;   /* a batch is a plan over B transforms */
@@ -94,7 +104,7 @@ const char *hpnfft_strerror(int status);
  *   window     HPNFFT_KAISER_BESSEL, HPNFFT_GAUSSIAN, HPNFFT_BSPLINE or
  *              HPNFFT_SINC_POWER
  *   precision  HPNFFT_F64 or HPNFFT_F32
- *   flags      0 or HPNFFT_WITH_GRADIENT
+ *   flags      0, HPNFFT_WITH_GRADIENT and/or HPNFFT_DETERMINISTIC
  * The plan starts without a workspace and without points.
  * Errors: EINVAL on any invalid argument, ENOMEM. */
 int hpnfft_plan_create(hpnfft_plan *out, int d, const int64_t *N, int64_t M,

@@ -180,13 +180,18 @@ hipError_t launch_copy(void *dst, const void *src, size_t bytes, int cus, hipStr
 // x / xf32 hold M x (3 - flat) coordinates; xs_out (if not null) receives
 // them as M x 3 with the flat dims zero.
 // Box-method plans (X.nbox[0] > 0) sort by output box instead of by line.
+// keys_out (if not null) receives every point's sort key.
 hipError_t launch_bin_count(const double *x, const float *xf32, long long M, const Xform &X, int T, int BW,
-                            int flat, int *counts, int *rank, int *err, double *xs_out, hipStream_t s);
+                            int flat, int *counts, int *rank, int *err, double *xs_out, int *keys_out,
+                            hipStream_t s);
 hipError_t launch_scan(int *data, long long n, int *tmp, hipStream_t s);
+// fixed_pos (if not null): sorted positions already in ipos (deterministic
+// mode); perm and ipos are then left as they are.
 template <typename R>
 hipError_t launch_bin_scatter(const double *x, const float *xf32, long long M, const Xform &X, int T, int m,
                               const WindowParams &wp, const double *poly, const int *cell_start, const int *rank, int *perm,
-                              int *ipos, unsigned char *rec, size_t rec_bytes, bool grad, hipStream_t s);
+                              int *ipos, unsigned char *rec, size_t rec_bytes, bool grad, const int *fixed_pos,
+                              hipStream_t s);
 template <typename R>
 hipError_t launch_gather(const void *f, const int *perm, long long total, R *fs, hipStream_t s);
 template <typename R>
@@ -209,6 +214,19 @@ hipError_t launch_fft(int pass, const Xform *dxf, const FItem *items, int nitems
 constexpr int kEwaldRealTile = 256;
 hipError_t launch_ewald_real(const double *r, const double *q, long long M, double L, double alpha,
                              double rcut, double *partials, double *energy, double *forces, hipStream_t s);
+// Deterministic mode (k_det.hip): stable sort by bin, one wavefront per
+// output box (spread) and per point (interpolation), no atomics.
+size_t det_sort_bytes(long long n);
+hipError_t launch_det_sort(const int *keys, long long n, int key_bits, int *keys_out, int *vals_in, int *vals_out,
+                           void *tmp, size_t tmp_bytes, long long poff, int *perm, int *ipos, hipStream_t s);
+template <typename R>
+hipError_t launch_spread_det(int m, const Xform *dxf, const SItem *items, int nitems, int max_cells,
+                             const unsigned char *rec, size_t rec_bytes, const R *fs, const int *cell_start,
+                             hipStream_t s);
+template <typename R>
+hipError_t launch_interp_det(int m, bool grad, const Xform *dxf, int B, long long Mtot, const unsigned char *rec,
+                             size_t rec_bytes, R *outs, int cus, hipStream_t s);
+
 // Box method (k_boxes.hip): every workgroup owns one output box of the grid
 // and takes every point whose window reaches it.
 template <typename R>

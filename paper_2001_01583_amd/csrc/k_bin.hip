@@ -56,7 +56,8 @@ __device__ inline int sort_key(const int c[3], int T, int ntx, int n0, int BW)
 template <typename XT>
 __global__ void k_bin_count(const XT *__restrict__ x, long long M, int n0, int n1, int n2, int T, int ntx,
                             int BW, int flat, int nb0, int nb1, int nb2, int *__restrict__ counts,
-                            int *__restrict__ rank, int *__restrict__ err, double *__restrict__ xs_out)
+                            int *__restrict__ rank, int *__restrict__ err, double *__restrict__ xs_out,
+                            int *__restrict__ keys_out)
 {
     long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= M) return;
@@ -85,6 +86,7 @@ __global__ void k_bin_count(const XT *__restrict__ x, long long M, int n0, int n
     if (bad) atomicOr(err, 1);
     const int key = nb0 ? box_key(c, n, nbox) : sort_key(c, T, ntx, n0, BW);
     rank[j] = atomicAdd(&counts[key], 1);
+    if (keys_out) keys_out[j] = key;
 }
 
 // Scatter of the points into sorted order, with the window values of each
@@ -134,7 +136,7 @@ __global__ __launch_bounds__(256) void k_bin_scatter(const double *__restrict__ 
                                                      int *__restrict__ ipos, unsigned char *__restrict__ rec,
                                                      size_t rec_bytes, WindowParams wp,
                                                      const double *__restrict__ poly, int flat, int nb0, int nb1,
-                                                     int nb2)
+                                                     int nb2, const int *__restrict__ fixed_pos)
 {
     constexpr int m = M2 / 2;
     constexpr int NW = 3 * M2;
@@ -152,9 +154,14 @@ __global__ __launch_bounds__(256) void k_bin_scatter(const double *__restrict__ 
     }
     const int nbox[3] = {nb0, nb1, nb2};
     const int key = nb0 ? box_key(c, n, nbox) : sort_key(c, T, ntx, n0, block_w(M2));
-    const long long pos = poff + cell_start[key] + rank[j];
-    perm[pos] = (int)(poff + j);
-    ipos[poff + j] = (int)pos;
+    long long pos;
+    if (fixed_pos) {
+        pos = fixed_pos[poff + j];
+    } else {
+        pos = poff + cell_start[key] + rank[j];
+        perm[pos] = (int)(poff + j);
+        ipos[poff + j] = (int)pos;
+    }
     unsigned char *rp = rec + pos * rec_bytes;
 
     int rot = (c[0] - m + 1) % M2;
@@ -340,40 +347,43 @@ hipError_t launch_scan(int *data, long long n, int *tmp, hipStream_t s)
 
 // ---------------------------------------------------------------------------
 hipError_t launch_bin_count(const double *x, const float *xf32, long long M, const Xform &X, int T, int BW,
-                            int flat, int *counts, int *rank, int *err, double *xs_out, hipStream_t s)
+                            int flat, int *counts, int *rank, int *err, double *xs_out, int *keys_out,
+                            hipStream_t s)
 {
     if (M <= 0) return hipSuccess;
     const unsigned nb = (unsigned)((M + 255) / 256);
     if (x)
         hipLaunchKernelGGL(k_bin_count<double>, dim3(nb), dim3(256), 0, s, x, M, X.n[0], X.n[1], X.n[2], T,
-                           X.ntx, BW, flat, X.nbox[0], X.nbox[1], X.nbox[2], counts, rank, err, xs_out);
+                           X.ntx, BW, flat, X.nbox[0], X.nbox[1], X.nbox[2], counts, rank, err, xs_out, keys_out);
     else
         hipLaunchKernelGGL(k_bin_count<float>, dim3(nb), dim3(256), 0, s, xf32, M, X.n[0], X.n[1], X.n[2], T,
-                           X.ntx, BW, flat, X.nbox[0], X.nbox[1], X.nbox[2], counts, rank, err, xs_out);
+                           X.ntx, BW, flat, X.nbox[0], X.nbox[1], X.nbox[2], counts, rank, err, xs_out, keys_out);
     return hipGetLastError();
 }
 
 template <typename R, int M2>
 static void scatter_m(const double *x, const float *xf32, long long M, const Xform &X, int T,
                       const int *cell_start, const int *rank, int *perm, int *ipos, unsigned char *rec,
-                      size_t rec_bytes, const WindowParams &wp, const double *poly, bool grad, hipStream_t s)
+                      size_t rec_bytes, const WindowParams &wp, const double *poly, bool grad, const int *fixed_pos,
+                      hipStream_t s)
 {
     const unsigned nb = (unsigned)((M + 255) / 256);
     auto k = grad ? k_bin_scatter<R, M2, true> : k_bin_scatter<R, M2, false>;
     hipLaunchKernelGGL(k, dim3(nb), dim3(256), 0, s, x, xf32, M, X.poff, X.n[0], X.n[1], X.n[2], T, X.ntx,
                        cell_start, rank, perm, ipos, rec, rec_bytes, wp, poly, X.flat, X.nbox[0], X.nbox[1],
-                       X.nbox[2]);
+                       X.nbox[2], fixed_pos);
 }
 
 template <typename R>
 hipError_t launch_bin_scatter(const double *x, const float *xf32, long long M, const Xform &X, int T, int m,
                               const WindowParams &wp, const double *poly, const int *cell_start, const int *rank,
-                              int *perm, int *ipos, unsigned char *rec, size_t rec_bytes, bool grad, hipStream_t s)
+                              int *perm, int *ipos, unsigned char *rec, size_t rec_bytes, bool grad,
+                              const int *fixed_pos, hipStream_t s)
 {
     if (M <= 0) return hipSuccess;
     switch (m) {
 #define HPNFFT_SCATTER_CASE(MM) \
-    case MM: scatter_m<R, 2 * MM>(x, xf32, M, X, T, cell_start, rank, perm, ipos, rec, rec_bytes, wp, poly, grad, s); break;
+    case MM: scatter_m<R, 2 * MM>(x, xf32, M, X, T, cell_start, rank, perm, ipos, rec, rec_bytes, wp, poly, grad, fixed_pos, s); break;
         HPNFFT_SCATTER_CASE(1)
         HPNFFT_SCATTER_CASE(2)
         HPNFFT_SCATTER_CASE(3)
@@ -397,9 +407,9 @@ hipError_t launch_bin_scatter(const double *x, const float *xf32, long long M, c
 
 template hipError_t launch_bin_scatter<double>(const double *, const float *, long long, const Xform &, int, int,
                                                const WindowParams &, const double *, const int *, const int *, int *, int *,
-                                               unsigned char *, size_t, bool, hipStream_t);
+                                               unsigned char *, size_t, bool, const int *, hipStream_t);
 template hipError_t launch_bin_scatter<float>(const double *, const float *, long long, const Xform &, int, int,
                                               const WindowParams &, const double *, const int *, const int *, int *, int *,
-                                              unsigned char *, size_t, bool, hipStream_t);
+                                              unsigned char *, size_t, bool, const int *, hipStream_t);
 
 }  // namespace hpnfft

@@ -64,6 +64,7 @@ int fft_count(int n)
 struct Layout {
     size_t counters, setp, grids, tmpA, tmpB, cell_start, scan_tmp, rank, perm, ipos, fs, xs, rec, outs, tcost, poly,
         items, fit[3], ewald, roll, tw, xf, total;
+    size_t dkeys = 0, dkeys_out = 0, dvals = 0, dvals_out = 0, dsort = 0, dsort_bytes = 0;  // deterministic sort
     size_t rec_bytes = 0;
     std::vector<size_t> grid_off, tmpA_off, tmpB_off, key_off, tcost_off, roll_off;
     std::map<int, size_t> tw_off;
@@ -120,6 +121,7 @@ struct hpnfft_plan_s {
     size_t rbytes() const { return prec == HPNFFT_F32 ? 4 : 8; }
     int M2() const { return 2 * m; }
     bool grad() const { return (flags & HPNFFT_WITH_GRADIENT) != 0; }
+    bool det() const { return (flags & HPNFFT_DETERMINISTIC) != 0; }
     template <typename T> T *at(size_t off) const { return reinterpret_cast<T *>(ws + off); }
 };
 
@@ -354,6 +356,7 @@ constexpr double kBoxDensityF64 = 0.1;
 constexpr double kBoxDensityF32 = 0.02;
 bool choose_boxes(const hpnfft_plan_s *p)
 {
+    if (p->det()) return true;  // the deterministic kernels use the box bins
     if (p->method == HPNFFT_METHOD_LINES) return false;
     if (p->method == HPNFFT_METHOD_BOXES) return true;
     double cells = 0.0;
@@ -390,6 +393,11 @@ bool tiling_fits(const hpnfft_plan_s *p, Tiling t)
 Tiling default_tiling(const hpnfft_plan_s *p)
 {
     const int M2 = p->M2();
+    if (p->det()) {
+        // one wavefront per box: small boxes (8 cells, or m) keep many per CU
+        const int Tb = std::max(8, p->m);
+        if (tiling_fits(p, Tiling{Tb, Tb, 64})) return Tiling{Tb, Tb, 64};
+    }
     if (p->boxes) {
         // boxes of 16 cells per edge (16 KiB of (sum, error) or float64 pairs
         // per 1024 cells: 64 KiB, two workgroups per compute unit)
@@ -497,6 +505,14 @@ void build_layout(hpnfft_plan_s *p)
     L.rec = take((size_t)p->Mtot * L.rec_bytes);
     L.outs_bytes = (size_t)p->Mtot * C * (p->grad() ? 4 : 1);
     L.outs = take(L.outs_bytes);
+    if (p->det()) {
+        L.dkeys = take((size_t)maxM * 4);
+        L.dkeys_out = take((size_t)maxM * 4);
+        L.dvals = take((size_t)maxM * 4);
+        L.dvals_out = take((size_t)maxM * 4);
+        L.dsort_bytes = det_sort_bytes(maxM);
+        L.dsort = take(L.dsort_bytes);
+    }
     L.tcost = off;
     for (int b = 0; b < p->B; ++b) {
         const Xform &X = p->hx[b];
@@ -778,18 +794,27 @@ int bin_points(hpnfft_plan_s *p, const double *x = nullptr, const float *x32 = n
         const int dc = 3 - X.flat;
         HCHECK(launch_bin_count(stored ? xb : (x ? x + X.poff * dc : nullptr), x32 ? x32 + X.poff * dc : nullptr,
                                 X.M, X, p->til.T, block_w(p->M2()), stored ? 0 : X.flat, cs, p->at<int>(L.rank),
-                                setp, stored ? nullptr : xb, s));
+                                setp, stored ? nullptr : xb, p->det() ? p->at<int>(L.dkeys) : nullptr, s));
         HCHECK(launch_scan(cs, p->keys[b], p->at<int>(L.scan_tmp), s));
+        if (p->det()) {
+            // stable order within each bin: sort (bin, input index)
+            int bits = 1;
+            while ((1LL << bits) < p->keys[b]) ++bits;
+            HCHECK(launch_det_sort(p->at<int>(L.dkeys), X.M, bits, p->at<int>(L.dkeys_out), p->at<int>(L.dvals),
+                                   p->at<int>(L.dvals_out), p->ws + L.dsort, L.dsort_bytes, X.poff,
+                                   p->at<int>(L.perm), p->at<int>(L.ipos), s));
+        }
+        const int *fixed = p->det() ? p->at<int>(L.ipos) : nullptr;
         if (p->prec == HPNFFT_F32)
             HCHECK(launch_bin_scatter<float>(xb, nullptr, X.M, X, p->til.T, p->m, p->wp,
                                              p->poly_ok ? p->at<double>(L.poly) : nullptr, cs,
                                              p->at<int>(L.rank), p->at<int>(L.perm), p->at<int>(L.ipos),
-                                             p->at<unsigned char>(L.rec), L.rec_bytes, p->grad(), s));
+                                             p->at<unsigned char>(L.rec), L.rec_bytes, p->grad(), fixed, s));
         else
             HCHECK(launch_bin_scatter<double>(xb, nullptr, X.M, X, p->til.T, p->m, p->wp,
                                               p->poly_ok ? p->at<double>(L.poly) : nullptr, cs,
                                               p->at<int>(L.rank), p->at<int>(L.perm), p->at<int>(L.ipos),
-                                              p->at<unsigned char>(L.rec), L.rec_bytes, p->grad(), s));
+                                              p->at<unsigned char>(L.rec), L.rec_bytes, p->grad(), fixed, s));
         if (!p->boxes)
             HCHECK(launch_tile_cost(cs, X, p->til.T, p->til.Zs, p->m, p->at<int>(L.tcost_off[b]), total, s));
     }
@@ -844,7 +869,11 @@ template <typename R> int run_adjoint(hpnfft_plan_s *p, const void *f, void *fha
     }
     {
         PhaseTimer t(p, HPNFFT_PH_SPREAD);
-        if (p->boxes)
+        if (p->det())
+            HCHECK(launch_spread_det<R>(p->m, dxf, p->at<SItem>(L.items), p->nitems, p->max_cells,
+                                        p->at<unsigned char>(L.rec), L.rec_bytes, p->at<R>(L.fs),
+                                        p->at<int>(L.cell_start), s));
+        else if (p->boxes)
             HCHECK(launch_spread_box<R>(p->m, dxf, p->at<SItem>(L.items), p->nitems, p->at<int>(L.counters),
                                         p->max_cells, p->at<unsigned char>(L.rec), L.rec_bytes, p->at<R>(L.fs),
                                         p->at<int>(L.cell_start), s));
@@ -888,7 +917,10 @@ template <typename R> int run_forward(hpnfft_plan_s *p, const void *fhat, void *
     if (rc) return rc;
     {
         PhaseTimer t(p, HPNFFT_PH_INTERP);
-        if (p->boxes)
+        if (p->det())
+            HCHECK(launch_interp_det<R>(p->m, false, dxf, p->B, p->Mtot, p->at<unsigned char>(L.rec), L.rec_bytes,
+                                        p->at<R>(L.outs), p->cus, s));
+        else if (p->boxes)
             HCHECK(launch_interp_box<R>(p->m, false, dxf, p->at<SItem>(L.items), p->nitems,
                                         p->at<int>(L.counters) + 1, p->max_cells, p->at<unsigned char>(L.rec),
                                         L.rec_bytes, p->at<int>(L.cell_start), p->at<R>(L.outs), s));
@@ -918,7 +950,10 @@ int run_backward(hpnfft_plan_s *p, const void *f, const void *gfhat, void *grad_
     if (rc) return rc;
     {
         PhaseTimer t(p, HPNFFT_PH_GRAD);
-        if (p->boxes)
+        if (p->det())
+            HCHECK(launch_interp_det<R>(p->m, true, dxf, p->B, p->Mtot, p->at<unsigned char>(L.rec), L.rec_bytes,
+                                        p->at<R>(L.outs), p->cus, s));
+        else if (p->boxes)
             HCHECK(launch_interp_box<R>(p->m, true, dxf, p->at<SItem>(L.items), p->nitems,
                                         p->at<int>(L.counters) + 1, p->max_cells, p->at<unsigned char>(L.rec),
                                         L.rec_bytes, p->at<int>(L.cell_start), p->at<R>(L.outs), s));
@@ -955,7 +990,7 @@ int create_common(hpnfft_plan_s **out, int B, const int64_t *N, const int64_t *M
     if (window < HPNFFT_KAISER_BESSEL || window > HPNFFT_SINC_POWER) return HPNFFT_EINVAL;
     if (precision != HPNFFT_F64 && precision != HPNFFT_F32) return HPNFFT_EINVAL;
     if (m < 1 || m > kMaxWindowM) return HPNFFT_EINVAL;
-    if (flags & ~HPNFFT_WITH_GRADIENT) return HPNFFT_EINVAL;
+    if (flags & ~(HPNFFT_WITH_GRADIENT | HPNFFT_DETERMINISTIC)) return HPNFFT_EINVAL;
     if (!(sigma >= 1.0) || !std::isfinite(sigma)) return HPNFFT_EINVAL;
     hpnfft_plan_s *p = new (std::nothrow) hpnfft_plan_s();
     if (!p) return HPNFFT_ENOMEM;
@@ -1103,6 +1138,7 @@ int hpnfft_set_tiles(hpnfft_plan p, int tile, int slab, int threads)
 int hpnfft_set_method(hpnfft_plan p, int method)
 {
     if (!p || method < HPNFFT_METHOD_AUTO || method > HPNFFT_METHOD_BOXES) return HPNFFT_EINVAL;
+    if (p->det() && method == HPNFFT_METHOD_LINES) return HPNFFT_EINVAL;  // deterministic plans use boxes
     drop_graph(p);
     p->method = method;
     p->boxes = choose_boxes(p);

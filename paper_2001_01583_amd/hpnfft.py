@@ -27,6 +27,7 @@ WINDOWS = {"kaiser_bessel": KAISER_BESSEL, "kb": KAISER_BESSEL, "gaussian": GAUS
            "bspline": BSPLINE, "sinc_power": SINC_POWER}
 F64, F32 = 0, 1
 WITH_GRADIENT = 1
+DETERMINISTIC = 2
 
 _lib = None
 
@@ -147,7 +148,7 @@ class Plan:
 
     def __init__(self, N, M, sigma: float = 2.0, m: int = 8, precision: str = "f64",
                  with_grad: bool = False, device="cuda", tiles: Optional[Sequence[int]] = None,
-                 window: str = "kaiser_bessel", method: str = "auto"):
+                 window: str = "kaiser_bessel", method: str = "auto", deterministic: bool = False):
         lib = _load()
         self.device = _require_gpu(device)
         if isinstance(M, int):
@@ -172,7 +173,7 @@ class Plan:
         self._h = ctypes.c_void_p()
         Narr = (ctypes.c_int64 * (self.d * self.B))(*[v for n in Ns for v in n])
         Marr = (ctypes.c_int64 * self.B)(*Ms)
-        flags = WITH_GRADIENT if with_grad else 0
+        flags = (WITH_GRADIENT if with_grad else 0) | (DETERMINISTIC if deterministic else 0)
         with torch.cuda.device(self.device):
             if self.batched:
                 rc = lib.hpnfft_batch_create(ctypes.byref(self._h), self.B, Narr, Marr, self.sigma, self.m,
