@@ -207,8 +207,9 @@ template <typename R>
 hipError_t launch_interp(int m, bool grad, const Xform *dxf, const SItem *items, int nitems, int *queue,
                          Tiling t, const unsigned char *rec, size_t rec_bytes, const int *cell_start,
                          R *outs, hipStream_t s);
+// odd: some grid edge has a factor 5 or 7
 template <typename R>
-hipError_t launch_fft(int pass, const Xform *dxf, const FItem *items, int nitems, int max_n,
+hipError_t launch_fft(int pass, const Xform *dxf, const FItem *items, int nitems, int max_n, bool odd,
                       void *fhat_base, hipStream_t s);
 // Ions per workgroup of the real-space pair kernel (one block partial each).
 constexpr int kEwaldRealTile = 256;

@@ -7,7 +7,9 @@
 // `count` pencils (coalesced: a run of contiguous elements per pencil row),
 // runs a mixed-radix (8, 4, 2, 3, 5, 7) Stockham autosort FFT in LDS with FP64
 // twiddles (rounded once for the float path), and stores only the outputs the
-// next step needs.  The passes are HBM-bound; pruning keeps the traffic at
+// next step needs.  The stages run in place in one LDS buffer (each thread
+// reads its butterflies' inputs into registers before any output is
+// written), so more workgroups fit on a compute unit.  The passes are HBM-bound; pruning keeps the traffic at
 // about 2.6 grid volumes per transform instead of 6.
 //
 // Adjoint (sign -):  grid[n0][n1][n2] --dim2--> A[n0][n1][N2] --dim1--> B[n0][N1][N2]
@@ -15,13 +17,15 @@
 // Forward (sign +):  fhat --x 1/c_k, pad, dim0--> B --dim1--> A --dim2--> grid
 // Frequency k of a length-n transform sits at bin k mod n; the cropped
 // (centred) arrays store k at k + N/2.
+#include <algorithm>
+
 #include "internal.h"
 
 namespace hpnfft {
 
 constexpr int kFftThreads = 256;
-constexpr int kFftCap = 2112;  // complex elements per LDS buffer
-constexpr int kLoadU = 8;      // loads in flight per thread
+constexpr int kFftCap = 2048;  // complex elements per LDS buffer (count * n)
+constexpr int kLoadU = 8;      // loads in flight per thread: kLoadU * kFftThreads >= kFftCap
 
 template <typename R> struct C2 { R x, y; };
 // loads and stores through global pointers, member by member (the compiler
@@ -142,35 +146,51 @@ template <int P, int S, typename R> __device__ inline void dft_odd(C2<R> *v)
     for (int r = 0; r < P; ++r) v[r] = out[r];
 }
 
-// One Stockham stage of radix RAD for `count` pencils of length n.
+// One in-place Stockham stage of radix RAD for `count` pencils of length n:
+// every thread first reads the inputs of its butterflies into registers,
+// then (after a barrier) writes their outputs to the same buffer, so one LDS
+// buffer serves all stages.
 template <int RAD, int S, typename R>
-__device__ inline void stage(const C2<R> *__restrict__ src, C2<R> *__restrict__ dst, const C2<R> *tw,
-                             int n, int ld, int count, int Ns)
+__device__ inline void stage(C2<R> *buf, const C2<R> *tw, int n, int ld, int count, int Ns)
 {
+    constexpr int MAXB = (kFftCap + RAD * kFftThreads - 1) / (RAD * kFftThreads);  // butterflies per thread
     const int nb = n / RAD;
     const int tstep = n / (Ns * RAD);
-    for (int t = threadIdx.x; t < count * nb; t += blockDim.x) {
-        int pen = t / nb, j = t - pen * nb;
-        const C2<R> *sp = src + pen * ld;
-        C2<R> *dp = dst + pen * ld;
-        int k = j % Ns;
-        C2<R> v[RAD];
+    const int total = count * nb;
+    C2<R> v[MAXB][RAD];
+    int dst[MAXB];
 #pragma unroll
-        for (int r = 0; r < RAD; ++r) v[r] = sp[j + r * nb];
-        if (Ns > 1) {
+    for (int q = 0; q < MAXB; ++q) {
+        const int t = threadIdx.x + q * kFftThreads;
+        dst[q] = -1;
+        if (t < total) {
+            const int pen = t / nb, j = t - pen * nb;
+            const int k = j % Ns;
+            const C2<R> *sp = buf + pen * ld;
 #pragma unroll
-            for (int r = 1; r < RAD; ++r) v[r] = cmul(v[r], tw[k * r * tstep]);
+            for (int r = 0; r < RAD; ++r) v[q][r] = sp[j + r * nb];
+            if (Ns > 1) {
+#pragma unroll
+                for (int r = 1; r < RAD; ++r) v[q][r] = cmul(v[q][r], tw[k * r * tstep]);
+            }
+            if (RAD == 2) dft2<S>(v[q]);
+            if (RAD == 3) dft3<S>(v[q]);
+            if (RAD == 4) dft4<S>(v[q]);
+            if (RAD == 8) dft8<S>(v[q]);
+            if (RAD == 5) dft_odd<5, S>(v[q]);
+            if (RAD == 7) dft_odd<7, S>(v[q]);
+            dst[q] = pen * ld + (j / Ns) * Ns * RAD + k;
         }
-        if (RAD == 2) dft2<S>(v);
-        if (RAD == 3) dft3<S>(v);
-        if (RAD == 4) dft4<S>(v);
-        if (RAD == 8) dft8<S>(v);
-        if (RAD == 5) dft_odd<5, S>(v);
-        if (RAD == 7) dft_odd<7, S>(v);
-        int idx = (j / Ns) * Ns * RAD + k;
-#pragma unroll
-        for (int r = 0; r < RAD; ++r) dp[idx + r * Ns] = v[r];
     }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < MAXB; ++q) {
+        if (dst[q] >= 0) {
+#pragma unroll
+            for (int r = 0; r < RAD; ++r) buf[dst[q] + r * Ns] = v[q][r];
+        }
+    }
+    __syncthreads();
 }
 
 struct PassGeom {
@@ -201,174 +221,197 @@ __device__ inline PassGeom pass_geom(int pass, const Xform &X)
     return g;
 }
 
-template <typename R, int S>
-__global__ __launch_bounds__(kFftThreads) void k_fft(int pass, const Xform *__restrict__ xfs,
-                                                     const FItem *__restrict__ items, void *fhat_base)
-{
-    extern __shared__ __align__(16) unsigned char smem[];
-    C2<R> *bufA = reinterpret_cast<C2<R> *>(smem);
-    C2<R> *bufB = bufA + kFftCap;
-    C2<R> *tw = bufB + kFftCap;
-
-    const FItem W = items[blockIdx.x];
-    const Xform &X = xfs[W.xf];
-    const PassGeom g = pass_geom(pass, X);
-    const int n = g.n, ld = n + 1, cnt = W.count;
-    const int tid = threadIdx.x, nthr = blockDim.x;
-
-    // global addressing for the descriptor's pointers (see as_global)
+// Source and destination arrays of a pass.
+template <typename R> struct PassArrays {
     gptr<const C2<R>> src;
     gptr<C2<R>> dst;
+};
+template <typename R> __device__ inline PassArrays<R> pass_arrays(int pass, const Xform &X, void *fhat_base)
+{
+    PassArrays<R> a;
     gptr<C2<R>> fh = as_global(reinterpret_cast<C2<R> *>(fhat_base)) + X.foff;
     switch (pass) {
-    case P_ADJ0: src = as_global((const C2<R> *)X.grid); dst = as_global((C2<R> *)X.tmpA); break;
-    case P_ADJ1: src = as_global((const C2<R> *)X.tmpA); dst = as_global((C2<R> *)X.tmpB); break;
-    case P_ADJ2: src = as_global((const C2<R> *)X.tmpB); dst = fh; break;
-    case P_FWD0: src = fh; dst = as_global((C2<R> *)X.tmpB); break;
-    case P_FWD1: src = as_global((const C2<R> *)X.tmpB); dst = as_global((C2<R> *)X.tmpA); break;
-    default:     src = as_global((const C2<R> *)X.tmpA); dst = as_global((C2<R> *)X.grid); break;
+    case P_ADJ0: a.src = as_global((const C2<R> *)X.grid); a.dst = as_global((C2<R> *)X.tmpA); break;
+    case P_ADJ1: a.src = as_global((const C2<R> *)X.tmpA); a.dst = as_global((C2<R> *)X.tmpB); break;
+    case P_ADJ2: a.src = as_global((const C2<R> *)X.tmpB); a.dst = fh; break;
+    case P_FWD0: a.src = fh; a.dst = as_global((C2<R> *)X.tmpB); break;
+    case P_FWD1: a.src = as_global((const C2<R> *)X.tmpB); a.dst = as_global((C2<R> *)X.tmpA); break;
+    default:     a.src = as_global((const C2<R> *)X.tmpA); a.dst = as_global((C2<R> *)X.grid); break;
     }
-    const gptr<const double> roll0 = as_global(X.roll[0]), roll1 = as_global(X.roll[1]),
-                             roll2 = as_global(X.roll[2]);
+    return a;
+}
 
-    // twiddles exp(S 2 pi i j / n), table holds exp(-2 pi i j / n)
-    const gptr<const C2<R>> twg = as_global(reinterpret_cast<const C2<R> *>(X.tw[g.dim]));
-    for (int j = tid; j < n; j += nthr) {
-        C2<R> w = gload<R>(twg + j);
-        if (S > 0) w.y = -w.y;
-        tw[j] = w;
-    }
+// element (pencil p, position j) of an array with L positions per pencil
+__device__ inline long long pass_addr(const FItem &W, int inner, int p, int j, int L)
+{
+    if (inner == 1) return ((long long)W.outer + p) * L + j;
+    return ((long long)W.outer * L + j) * inner + W.inner0 + p;
+}
 
-    // element (pencil p, position j) of an array with L positions per pencil
-    const int inner = g.inner;
-    auto addr = [&](int p, int j, int L) -> long long {
-        if (inner == 1) return ((long long)W.outer + p) * L + j;
-        return ((long long)W.outer * L + j) * inner + W.inner0 + p;
-    };
-
-    // ---- load ----
-    // kLoadU independent loads per thread are in flight before any LDS write
-    // (indices clamped into range, so the loads need no branch).
-    if (g.crop) {
-        const int tot = cnt * n;
-        for (int base = 0; base < tot; base += kLoadU * nthr) {
-            R vx[kLoadU], vy[kLoadU];
-            int at[kLoadU];
+// One item's input, in registers: kLoadU values per thread and their LDS
+// positions (-1: none).  Crop passes load all n positions of each pencil;
+// pad passes load the N nonzero ones (with the roll-off factors of the
+// Subdividing step in the first forward pass) into their FFT bins.
+template <typename R> struct PassLoad {
+    R vx[kLoadU], vy[kLoadU];
+    int at[kLoadU];
+};
+template <typename R>
+__device__ inline void pass_issue(int pass, const Xform &X, const FItem &W, void *fhat_base, PassLoad<R> &L)
+{
+    const PassGeom g = pass_geom(pass, X);
+    const PassArrays<R> a = pass_arrays<R>(pass, X, fhat_base);
+    const int n = g.n, ld = n, cnt = W.count, inner = g.inner;
+    const int Lin = g.crop ? n : g.N;
+    const int tot = cnt * Lin;
+    const int tid = threadIdx.x, nthr = blockDim.x;
 #pragma unroll
-            for (int u = 0; u < kLoadU; ++u) {
-                int e = base + tid + u * nthr;
-                at[u] = -1;
-                int ec = e < tot ? e : tot - 1;
-                int p, j;
-                if (inner == 1) { p = ec / n; j = ec - p * n; }
-                else { j = ec / cnt; p = ec - j * cnt; }
-                C2<R> w = gload<R>(src + addr(p, j, n));
-                vx[u] = w.x;
-                vy[u] = w.y;
-                if (e < tot) at[u] = p * ld + j;
+    for (int u = 0; u < kLoadU; ++u) {
+        const int e = tid + u * nthr;
+        const int ec = e < tot ? e : tot - 1;  // clamped: no branch around the load
+        int p, j;
+        if (inner == 1) {
+            p = ec / Lin;
+            j = ec - p * Lin;
+        } else {
+            j = ec / cnt;
+            p = ec - j * cnt;
+        }
+        C2<R> w = gload<R>(a.src + pass_addr(W, inner, p, j, Lin));
+        if (!g.crop) {
+            if (g.roll_in) {
+                const int ii = W.inner0 + p;
+                const double f = as_global(X.roll[0])[j] * as_global(X.roll[1])[ii / X.N[2]] *
+                                 as_global(X.roll[2])[ii % X.N[2]];
+                w.x = (R)(w.x * f);
+                w.y = (R)(w.y * f);
             }
-#pragma unroll
-            for (int u = 0; u < kLoadU; ++u)
-                if (at[u] >= 0) bufA[at[u]] = C2<R>{vx[u], vy[u]};
-        }
-    } else {
-        for (int e = tid; e < cnt * n; e += nthr) {
-            int p = e / n, j = e - p * n;
-            bufA[p * ld + j] = C2<R>{R(0), R(0)};
-        }
-        __syncthreads();
-        const int N = g.N, tot = cnt * N;
-        for (int base = 0; base < tot; base += kLoadU * nthr) {
-            R vx[kLoadU], vy[kLoadU];
-            int at[kLoadU];
-#pragma unroll
-            for (int u = 0; u < kLoadU; ++u) {
-                int e = base + tid + u * nthr;
-                at[u] = -1;
-                int ec = e < tot ? e : tot - 1;
-                int p, i;
-                if (inner == 1) { p = ec / N; i = ec - p * N; }
-                else { i = ec / cnt; p = ec - i * cnt; }
-                C2<R> w = gload<R>(src + addr(p, i, N));
-                if (g.roll_in) {
-                    int ii = W.inner0 + p;
-                    double f = roll0[i] * roll1[ii / X.N[2]] * roll2[ii % X.N[2]];
-                    w.x = (R)(w.x * f);
-                    w.y = (R)(w.y * f);
-                }
-                vx[u] = w.x;
-                vy[u] = w.y;
-                int bin = i - N / 2;
-                if (bin < 0) bin += n;
-                if (e < tot) at[u] = p * ld + bin;
-            }
-#pragma unroll
-            for (int u = 0; u < kLoadU; ++u)
-                if (at[u] >= 0) bufA[at[u]] = C2<R>{vx[u], vy[u]};
-        }
-    }
-    __syncthreads();
-
-    // ---- Stockham stages: radix 8 first, then 4, 2, 3, 5, 7 ----
-    C2<R> *cur = bufA, *nxt = bufB;
-    int rem = n, Ns = 1;
-    while (rem > 1) {
-        int rad = (rem % 8 == 0) ? 8 : (rem % 4 == 0) ? 4 : (rem % 2 == 0) ? 2 : (rem % 3 == 0) ? 3
-                : (rem % 5 == 0) ? 5 : 7;
-        switch (rad) {
-        case 8: stage<8, S, R>(cur, nxt, tw, n, ld, cnt, Ns); break;
-        case 4: stage<4, S, R>(cur, nxt, tw, n, ld, cnt, Ns); break;
-        case 2: stage<2, S, R>(cur, nxt, tw, n, ld, cnt, Ns); break;
-        case 3: stage<3, S, R>(cur, nxt, tw, n, ld, cnt, Ns); break;
-        case 5: stage<5, S, R>(cur, nxt, tw, n, ld, cnt, Ns); break;
-        default: stage<7, S, R>(cur, nxt, tw, n, ld, cnt, Ns); break;
-        }
-        __syncthreads();
-        C2<R> *t = cur;
-        cur = nxt;
-        nxt = t;
-        Ns *= rad;
-        rem /= rad;
-    }
-
-    // ---- store ----
-    const int Lout = g.Lout, tot = cnt * Lout;
-    for (int e = tid; e < tot; e += nthr) {
-        int p, o;
-        if (inner == 1) { p = e / Lout; o = e - p * Lout; }
-        else { o = e / cnt; p = e - o * cnt; }
-        int bin = o;
-        if (g.crop) {
-            bin = o - g.N / 2;
+            int bin = j - g.N / 2;
             if (bin < 0) bin += n;
+            j = bin;
         }
-        C2<R> v = cur[p * ld + bin];
-        if (g.roll_out) {
-            int ii = W.inner0 + p;
-            double f = roll0[o] * roll1[ii / X.N[2]] * roll2[ii % X.N[2]];
-            v.x = (R)(v.x * f);
-            v.y = (R)(v.y * f);
+        L.vx[u] = w.x;
+        L.vy[u] = w.y;
+        L.at[u] = e < tot ? p * ld + j : -1;
+    }
+}
+
+// ODD: grids with factors 5 or 7 (their stages hold more values per thread;
+// the other grids run a variant without them, with fewer registers).
+template <typename R, int S, bool ODD>
+__global__ __launch_bounds__(kFftThreads) void k_fft(int pass, const Xform *__restrict__ xfs,
+                                                     const FItem *__restrict__ items, int nitems, void *fhat_base)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    C2<R> *buf = reinterpret_cast<C2<R> *>(smem);
+    C2<R> *tw = buf + kFftCap;
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const FItem W = items[it];
+        const Xform &X = xfs[W.xf];
+        const PassGeom g = pass_geom(pass, X);
+        const int n = g.n, ld = n, cnt = W.count;
+        // all of the item's loads are issued before any LDS write
+        PassLoad<R> ld_regs;
+        pass_issue<R>(pass, X, W, fhat_base, ld_regs);
+        // twiddles exp(S 2 pi i j / n) of this dimension (the table holds
+        // exp(-2 pi i j / n))
+        const gptr<const C2<R>> twg = as_global(reinterpret_cast<const C2<R> *>(X.tw[g.dim]));
+        for (int j = tid; j < n; j += nthr) {
+            C2<R> w = gload<R>(twg + j);
+            if (S > 0) w.y = -w.y;
+            tw[j] = w;
         }
-        gstore<R>(dst + addr(p, o, Lout), v);
+        // pad passes: the positions no input lands on are zero
+        if (!g.crop) {
+            const int z0 = g.N - g.N / 2, z1 = n - g.N / 2;  // [z0, z1) holds no data
+            const int zw = z1 - z0;
+            for (int e = tid; e < cnt * zw; e += nthr) {
+                const int p = e / zw, j = z0 + (e - p * zw);
+                buf[p * ld + j] = C2<R>{R(0), R(0)};
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kLoadU; ++u)
+            if (ld_regs.at[u] >= 0) buf[ld_regs.at[u]] = C2<R>{ld_regs.vx[u], ld_regs.vy[u]};
+        __syncthreads();
+
+        // ---- Stockham stages: radix 8 first, then 4, 2, 3, 5, 7 ----
+        int rem = n, Ns = 1;
+        while (rem > 1) {
+            const int rad = (rem % 8 == 0) ? 8 : (rem % 4 == 0) ? 4 : (rem % 2 == 0) ? 2 : (rem % 3 == 0) ? 3
+                          : (rem % 5 == 0) ? 5 : 7;
+            switch (rad) {
+            case 8: stage<8, S, R>(buf, tw, n, ld, cnt, Ns); break;
+            case 4: stage<4, S, R>(buf, tw, n, ld, cnt, Ns); break;
+            case 2: stage<2, S, R>(buf, tw, n, ld, cnt, Ns); break;
+            case 3: stage<3, S, R>(buf, tw, n, ld, cnt, Ns); break;
+            default:
+                if constexpr (ODD) {
+                    if (rad == 5) stage<5, S, R>(buf, tw, n, ld, cnt, Ns);
+                    else stage<7, S, R>(buf, tw, n, ld, cnt, Ns);
+                }
+                break;
+            }
+            Ns *= rad;
+            rem /= rad;
+        }
+
+        // ---- store (crop to I_N and Scaling in the last adjoint pass) ----
+        const PassArrays<R> a = pass_arrays<R>(pass, X, fhat_base);
+        const gptr<const double> roll0 = as_global(X.roll[0]), roll1 = as_global(X.roll[1]),
+                                 roll2 = as_global(X.roll[2]);
+        const int Lout = g.Lout, tot = cnt * Lout, inner = g.inner;
+        for (int e = tid; e < tot; e += nthr) {
+            int p, o;
+            if (inner == 1) { p = e / Lout; o = e - p * Lout; }
+            else { o = e / cnt; p = e - o * cnt; }
+            int bin = o;
+            if (g.crop) {
+                bin = o - g.N / 2;
+                if (bin < 0) bin += n;
+            }
+            C2<R> v = buf[p * ld + bin];
+            if (g.roll_out) {
+                const int ii = W.inner0 + p;
+                const double f = roll0[o] * roll1[ii / X.N[2]] * roll2[ii % X.N[2]];
+                v.x = (R)(v.x * f);
+                v.y = (R)(v.y * f);
+            }
+            gstore<R>(a.dst + pass_addr(W, inner, p, o, Lout), v);
+        }
+        __syncthreads();  // the next item writes the buffer
     }
 }
 
 template <typename R>
-hipError_t launch_fft(int pass, const Xform *dxf, const FItem *items, int nitems, int max_n,
+hipError_t launch_fft(int pass, const Xform *dxf, const FItem *items, int nitems, int max_n, bool odd,
                       void *fhat_base, hipStream_t s)
 {
     if (nitems <= 0) return hipSuccess;
-    size_t lds = (size_t)(2 * kFftCap + max_n) * 2 * sizeof(R);
-    bool adj = pass <= P_ADJ2;
-    auto kern = adj ? k_fft<R, -1> : k_fft<R, 1>;
+    const size_t lds = (size_t)(kFftCap + max_n) * 2 * sizeof(R);
+    const bool adj = pass <= P_ADJ2;
+    auto kern = adj ? (odd ? k_fft<R, -1, true> : k_fft<R, -1, false>)
+                    : (odd ? k_fft<R, 1, true> : k_fft<R, 1, false>);
     hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3(nitems), dim3(kFftThreads), lds, s, pass, dxf, items, fhat_base);
+    static int cus = 0;
+    if (!cus) {
+        int dev = 0;
+        hipGetDevice(&dev);
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+            cus = 256;
+    }
+    // one workgroup per item up to a few rounds of the chip (LDS, 8 x 256
+    // threads per CU); beyond that workgroups take several items in turn
+    const int per_cu = std::max(1, std::min(8, (int)((160 * 1024) / (lds + 512))));
+    const int grid = std::min(nitems, cus * per_cu * 4);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(kFftThreads), lds, s, pass, dxf, items, nitems, fhat_base);
     return hipGetLastError();
 }
 
-template hipError_t launch_fft<double>(int, const Xform *, const FItem *, int, int, void *, hipStream_t);
-template hipError_t launch_fft<float>(int, const Xform *, const FItem *, int, int, void *, hipStream_t);
+template hipError_t launch_fft<double>(int, const Xform *, const FItem *, int, int, bool, void *, hipStream_t);
+template hipError_t launch_fft<float>(int, const Xform *, const FItem *, int, int, bool, void *, hipStream_t);
 
 }  // namespace hpnfft

@@ -40,7 +40,7 @@ using namespace hpnfft;
 
 namespace {
 
-constexpr int kFftCap = 2112;
+constexpr int kFftCap = 2048;  // complex elements per FFT workgroup (count * n)
 constexpr int kMinCap = 2048;
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
@@ -57,7 +57,7 @@ bool is_smooth(long v)
 int fft_count(int n)
 {
     int c = 1;
-    while ((c * 2) * (n + 1) <= kFftCap) c *= 2;
+    while ((c * 2) * n <= kFftCap) c *= 2;
     return c;
 }
 
@@ -122,6 +122,14 @@ struct hpnfft_plan_s {
     int M2() const { return 2 * m; }
     bool grad() const { return (flags & HPNFFT_WITH_GRADIENT) != 0; }
     bool det() const { return (flags & HPNFFT_DETERMINISTIC) != 0; }
+    // some grid edge has a factor 5 or 7 (the FFT then runs its odd-radix variant)
+    bool odd_fft() const
+    {
+        for (const Xform &X : hx)
+            for (int d = 0; d < 3; ++d)
+                if (X.n[d] % 5 == 0 || X.n[d] % 7 == 0) return true;
+        return false;
+    }
     template <typename T> T *at(size_t off) const { return reinterpret_cast<T *>(ws + off); }
 };
 
@@ -885,7 +893,7 @@ template <typename R> int run_adjoint(hpnfft_plan_s *p, const void *f, void *fha
     for (int pass = P_ADJ0; pass <= P_ADJ2; ++pass) {
         int d = pass == P_ADJ0 ? 2 : (pass == P_ADJ1 ? 1 : 0);
         PhaseTimer t(p, HPNFFT_PH_FFT_A0 + pass - P_ADJ0);
-        HCHECK(launch_fft<R>(pass, dxf, p->at<FItem>(L.fit[d]), L.nfit[d], p->maxn, fhat, s));
+        HCHECK(launch_fft<R>(pass, dxf, p->at<FItem>(L.fit[d]), L.nfit[d], p->maxn, p->odd_fft(), fhat, s));
     }
     return HPNFFT_OK;
 }
@@ -898,7 +906,7 @@ template <typename R> int run_to_grid(hpnfft_plan_s *p, const void *fhat)
     for (int pass = P_FWD0; pass <= P_FWD2; ++pass) {
         int d = pass == P_FWD0 ? 0 : (pass == P_FWD1 ? 1 : 2);
         PhaseTimer t(p, HPNFFT_PH_FFT_F0 + pass - P_FWD0);
-        HCHECK(launch_fft<R>(pass, dxf, p->at<FItem>(L.fit[d]), L.nfit[d], p->maxn,
+        HCHECK(launch_fft<R>(pass, dxf, p->at<FItem>(L.fit[d]), L.nfit[d], p->maxn, p->odd_fft(),
                              const_cast<void *>(fhat), s));
     }
     return HPNFFT_OK;
