@@ -130,13 +130,16 @@ int hpnfft_set_stream(hpnfft_plan plan, void *hip_stream);
  *                        edge) and takes the points of the 27 boxes around
  *                        it; the grid is written once, with plain stores
  *                        (sparse point sets)
- *   HPNFFT_METHOD_AUTO   (the default) boxes below 0.1 (float64) or 0.02
- *                        (float32) points per grid cell
+ *   HPNFFT_METHOD_AUTO   (the default) per transform: boxes below 0.1
+ *                        (float64) or 0.02 (float32) points per grid cell,
+ *                        so a batch may mix the two (its tiling then sets the
+ *                        line sweeps; its box transforms use 16-cell boxes)
  * The results agree to rounding; hpnfft_get_method reports the method in use
- * (LINES or BOXES). */
+ * (LINES, BOXES, or MIXED for a batch that uses both). */
 #define HPNFFT_METHOD_AUTO  0
 #define HPNFFT_METHOD_LINES 1
 #define HPNFFT_METHOD_BOXES 2
+#define HPNFFT_METHOD_MIXED 3   /* reported by hpnfft_get_method only */
 int hpnfft_set_method(hpnfft_plan plan, int method);
 int hpnfft_get_method(hpnfft_plan plan, int *method);
 

@@ -65,6 +65,7 @@ struct Layout {
     size_t counters, setp, grids, tmpA, tmpB, cell_start, scan_tmp, rank, perm, ipos, fs, xs, rec, outs, tcost, poly,
         items, fit[3], ewald, roll, tw, xf, total;
     size_t dkeys = 0, dkeys_out = 0, dvals = 0, dvals_out = 0, dsort = 0, dsort_bytes = 0;  // deterministic sort
+    size_t bitems = 0;  // box work items
     size_t rec_bytes = 0;
     std::vector<size_t> grid_off, tmpA_off, tmpB_off, key_off, tcost_off, roll_off;
     std::map<int, size_t> tw_off;
@@ -97,8 +98,12 @@ struct hpnfft_plan_s {
     // sweep method: requested (HPNFFT_METHOD_*) and in use; the box method's
     // static work list (one item per output box) and largest box (cells)
     int method = HPNFFT_METHOD_AUTO;
-    bool boxes = false;
+    bool boxes = false;            // every transform uses boxes (tiling = box edges)
+    bool any_box = false;          // some transform uses boxes
+    bool any_lines = true;         // some transform uses the line sweeps
+    std::vector<char> tbox;        // per transform: box method
     int max_cells = 0;
+    int nbitems = 0;               // box work items (one per output box)
     std::vector<SItem> h_box_items;
     int cus = 256;
     char arch[64] = "unknown";
@@ -215,7 +220,7 @@ std::string tune_key(const hpnfft_plan_s *p)
     char head[256];
     std::snprintf(head, sizeof(head), "v%d|%s|cu%d|%s|m%d|w%d|s%.6g|g%d|B%d|%s", kTuneCacheVersion, p->arch,
                   p->cus, p->prec == HPNFFT_F32 ? "f32" : "f64", p->m, p->window, p->sigma, p->grad() ? 1 : 0,
-                  p->B, p->boxes ? "boxes" : "lines");
+                  p->B, p->boxes ? "boxes" : (p->any_box ? "mixed" : "lines"));
     std::string list;
     for (const Xform &X : p->hx) {
         int mb = 0;
@@ -343,7 +348,9 @@ BoxDim box_dim(int n, int Tb, int m)
 long long box_max_cells(const hpnfft_plan_s *p, Tiling t)
 {
     long long best = 0;
-    for (const Xform &X : p->hx) {
+    for (int b = 0; b < p->B; ++b) {
+        if (!p->tbox[b]) continue;
+        const Xform &X = p->hx[b];
         long long c = 1;
         for (int d = 0; d < 3; ++d) c *= box_dim(X.n[d], d == 0 ? t.Zs : t.T, p->m).maxw;
         best = std::max(best, c);
@@ -362,25 +369,42 @@ long long box_max_cells(const hpnfft_plan_s *p, Tiling t)
 // 1.3x (float32) faster.
 constexpr double kBoxDensityF64 = 0.1;
 constexpr double kBoxDensityF32 = 0.02;
-bool choose_boxes(const hpnfft_plan_s *p)
+// The method of every transform (a batch may mix them: sparse transforms
+// take boxes, dense ones the line sweeps).
+void choose_methods(hpnfft_plan_s *p)
 {
-    if (p->det()) return true;  // the deterministic kernels use the box bins
-    if (p->method == HPNFFT_METHOD_LINES) return false;
-    if (p->method == HPNFFT_METHOD_BOXES) return true;
-    double cells = 0.0;
-    for (const Xform &X : p->hx) cells += (double)X.n[0] * X.n[1] * X.n[2];
-    return (double)p->Mtot < (p->prec == HPNFFT_F32 ? kBoxDensityF32 : kBoxDensityF64) * cells;
+    const double thr = p->prec == HPNFFT_F32 ? kBoxDensityF32 : kBoxDensityF64;
+    p->tbox.assign(p->B, 0);
+    for (int b = 0; b < p->B; ++b) {
+        const Xform &X = p->hx[b];
+        bool box;
+        if (p->det()) box = true;  // the deterministic kernels use the box bins
+        else if (p->method == HPNFFT_METHOD_LINES) box = false;
+        else if (p->method == HPNFFT_METHOD_BOXES) box = true;
+        else box = (double)X.M < thr * (double)X.n[0] * X.n[1] * X.n[2];
+        p->tbox[b] = box;
+    }
+    p->any_box = std::count(p->tbox.begin(), p->tbox.end(), 1) > 0;
+    p->any_lines = std::count(p->tbox.begin(), p->tbox.end(), 0) > 0;
+    p->boxes = !p->any_lines;
 }
+
+// Box edges of the box transforms: the plan's tiling when every transform
+// uses boxes; in a batch that mixes methods (the tiling then belongs to the
+// line sweeps), 16 cells.
+Tiling box_tiling(const hpnfft_plan_s *p, Tiling t) { return p->boxes ? t : Tiling{16, 16, 512}; }
 
 bool tiling_fits(const hpnfft_plan_s *p, Tiling t)
 {
     if (t.T < 4 || t.T > 32 || t.Zs < 2 || t.Zs > 64) return false;
     if (t.threads < 64 || t.threads > 1024 || t.threads % 64) return false;
-    if (p->boxes) {
+    if (p->any_box) {
         // box edges (dims 1, 2: T; dim 0: Zs) of at least m cells
-        if (t.T < p->m || t.Zs < p->m) return false;
+        const Tiling bt = box_tiling(p, t);
+        if (bt.T < p->m || bt.Zs < p->m) return false;
         // the box tile in LDS beside the run lists (12 KiB of static LDS)
-        return box_max_cells(p, t) * 16 + 12 * 1024 <= (long long)kLdsLimit;
+        if (box_max_cells(p, bt) * 16 + 12 * 1024 > (long long)kLdsLimit) return false;
+        if (p->boxes) return true;
     }
     if (t.T % block_w(p->M2())) return false;  // whole blocks of lines per tile row
     bool comp = p->prec == HPNFFT_F32;
@@ -461,11 +485,12 @@ void build_layout(hpnfft_plan_s *p)
         X.nslab = (X.n[0] + Zs - 1) / Zs;
         p->keys[b] = (long long)X.ntx * X.nty * T * T * X.n[0] + 1;
         for (int d = 0; d < 3; ++d) X.nbox[d] = X.gbox[d] = 0;
-        if (p->boxes) {
+        if (p->tbox[b]) {
             // box method: sort keys are point bins; one work item per output box
+            const Tiling bt = box_tiling(p, p->til);
             long long nbins = 1, nboxes = 1, cells = 1;
             for (int d = 0; d < 3; ++d) {
-                const BoxDim bd = box_dim(X.n[d], d == 0 ? Zs : T, p->m);
+                const BoxDim bd = box_dim(X.n[d], d == 0 ? bt.Zs : bt.T, p->m);
                 X.nbox[d] = bd.nbins;
                 X.gbox[d] = bd.gbox;
                 nbins *= bd.nbins;
@@ -478,10 +503,9 @@ void build_layout(hpnfft_plan_s *p)
         }
         maxkeys = std::max(maxkeys, p->keys[b]);
         maxM = std::max(maxM, X.M);
-        pairs += (long long)X.ntx * X.nty * X.nslab;
+        if (!p->tbox[b]) pairs += (long long)X.ntx * X.nty * X.nslab;
         maxF = std::max(maxF, (long long)X.N[0] * X.N[1] * X.N[2]);
     }
-    if (p->boxes) pairs = std::max<long long>(pairs, (long long)p->h_box_items.size());
     // grids (contiguous, zeroed by one launch)
     L.grids = off;
     for (int b = 0; b < p->B; ++b) {
@@ -524,10 +548,11 @@ void build_layout(hpnfft_plan_s *p)
     L.tcost = off;
     for (int b = 0; b < p->B; ++b) {
         const Xform &X = p->hx[b];
-        L.tcost_off.push_back(take(p->boxes ? 0 : (size_t)X.ntx * X.nty * X.nslab * (T * T / block_w(p->M2())) * 4));
+        L.tcost_off.push_back(take(p->tbox[b] ? 0 : (size_t)X.ntx * X.nty * X.nslab * (T * T / block_w(p->M2())) * 4));
     }
     L.max_items = (int)std::min<long long>(pairs + (long long)p->cus * 4 + 64, 0x7fffffffLL / 64);
     L.items = take((size_t)L.max_items * sizeof(SItem));
+    L.bitems = take(std::max<size_t>(1, p->h_box_items.size()) * sizeof(SItem));
     for (int d = 0; d < 3; ++d) {
         long long cnt = 0;
         for (int b = 0; b < p->B; ++b) {
@@ -723,12 +748,12 @@ int upload_tables(hpnfft_plan_s *p)
     }
     HCHECK(hipMemcpyAsync(p->ws + L.xf, p->hx.data(), p->hx.size() * sizeof(Xform), hipMemcpyHostToDevice,
                           p->stream));
-    if (p->boxes) {
+    if (p->any_box) {
         // the box method's work list does not depend on the points
-        HCHECK(hipMemcpyAsync(p->ws + L.items, p->h_box_items.data(), p->h_box_items.size() * sizeof(SItem),
+        HCHECK(hipMemcpyAsync(p->ws + L.bitems, p->h_box_items.data(), p->h_box_items.size() * sizeof(SItem),
                               hipMemcpyHostToDevice, p->stream));
-        p->nitems = (int)p->h_box_items.size();
     }
+    p->nbitems = (int)p->h_box_items.size();
     // the host sources must outlive the copies
     HCHECK(hipStreamSynchronize(p->stream));
     return HPNFFT_OK;
@@ -823,11 +848,12 @@ int bin_points(hpnfft_plan_s *p, const double *x = nullptr, const float *x32 = n
                                               p->poly_ok ? p->at<double>(L.poly) : nullptr, cs,
                                               p->at<int>(L.rank), p->at<int>(L.perm), p->at<int>(L.ipos),
                                               p->at<unsigned char>(L.rec), L.rec_bytes, p->grad(), fixed, s));
-        if (!p->boxes)
+        if (!p->tbox[b])
             HCHECK(launch_tile_cost(cs, X, p->til.T, p->til.Zs, p->m, p->at<int>(L.tcost_off[b]), total, s));
     }
     const int cap_div = p->cus * 4;
-    for (int b = 0; b < p->B && !p->boxes; ++b) {
+    for (int b = 0; b < p->B; ++b) {
+        if (p->tbox[b]) continue;
         const Xform &X = p->hx[b];
         HCHECK(launch_make_items(p->at<int>(L.tcost_off[b]), b, X, p->til.T, p->m, total, cap_div, kMinCap,
                                  L.max_items, p->at<SItem>(L.items), setp + 1, setp + 2, s));
@@ -849,11 +875,8 @@ int bin_points(hpnfft_plan_s *p, const double *x = nullptr, const float *x32 = n
     std::memcpy(host, p->hres, sizeof(host));
     if (host[0]) return HPNFFT_EDOMAIN;
     if (host[2]) return HPNFFT_ENOMEM;
-    if (p->boxes) {
-        p->nitems = (int)p->h_box_items.size();
-        return HPNFFT_OK;
-    }
-    p->nitems = std::min(host[1], L.max_items);
+    p->nbitems = (int)p->h_box_items.size();
+    p->nitems = p->any_lines ? std::min(host[1], L.max_items) : 0;
     // staging worth reserving per chunk: twice the mean points per item
     unsigned long long tot = 0;
     std::memcpy(&tot, host + 4, sizeof(tot));
@@ -867,7 +890,7 @@ template <typename R> int run_adjoint(hpnfft_plan_s *p, const void *f, void *fha
     const Layout &L = p->L;
     hipStream_t s = p->stream;
     const Xform *dxf = p->at<Xform>(L.xf);
-    if (!p->boxes) {  // the box method writes every grid cell itself
+    if (p->any_lines) {  // (the box method writes every grid cell of its transforms itself)
         PhaseTimer t(p, HPNFFT_PH_ZERO);
         HCHECK(launch_zero(p->ws + L.grids, L.grids_bytes, s));
     }
@@ -878,14 +901,14 @@ template <typename R> int run_adjoint(hpnfft_plan_s *p, const void *f, void *fha
     {
         PhaseTimer t(p, HPNFFT_PH_SPREAD);
         if (p->det())
-            HCHECK(launch_spread_det<R>(p->m, dxf, p->at<SItem>(L.items), p->nitems, p->max_cells,
+            HCHECK(launch_spread_det<R>(p->m, dxf, p->at<SItem>(L.bitems), p->nbitems, p->max_cells,
                                         p->at<unsigned char>(L.rec), L.rec_bytes, p->at<R>(L.fs),
                                         p->at<int>(L.cell_start), s));
-        else if (p->boxes)
-            HCHECK(launch_spread_box<R>(p->m, dxf, p->at<SItem>(L.items), p->nitems, p->at<int>(L.counters),
+        else if (p->any_box)
+            HCHECK(launch_spread_box<R>(p->m, dxf, p->at<SItem>(L.bitems), p->nbitems, p->at<int>(L.counters),
                                         p->max_cells, p->at<unsigned char>(L.rec), L.rec_bytes, p->at<R>(L.fs),
                                         p->at<int>(L.cell_start), s));
-        else
+        if (p->any_lines)
             HCHECK(launch_spread<R>(p->m, dxf, p->at<SItem>(L.items), p->nitems, p->at<int>(L.counters), p->til,
                                     p->at<unsigned char>(L.rec), L.rec_bytes, p->at<R>(L.fs),
                                     p->at<int>(L.cell_start), s));
@@ -928,11 +951,11 @@ template <typename R> int run_forward(hpnfft_plan_s *p, const void *fhat, void *
         if (p->det())
             HCHECK(launch_interp_det<R>(p->m, false, dxf, p->B, p->Mtot, p->at<unsigned char>(L.rec), L.rec_bytes,
                                         p->at<R>(L.outs), p->cus, s));
-        else if (p->boxes)
-            HCHECK(launch_interp_box<R>(p->m, false, dxf, p->at<SItem>(L.items), p->nitems,
+        else if (p->any_box)
+            HCHECK(launch_interp_box<R>(p->m, false, dxf, p->at<SItem>(L.bitems), p->nbitems,
                                         p->at<int>(L.counters) + 1, p->max_cells, p->at<unsigned char>(L.rec),
                                         L.rec_bytes, p->at<int>(L.cell_start), p->at<R>(L.outs), s));
-        else
+        if (p->any_lines)
             HCHECK(launch_interp<R>(p->m, false, dxf, p->at<SItem>(L.items), p->nitems,
                                     p->at<int>(L.counters) + 1, p->til, p->at<unsigned char>(L.rec), L.rec_bytes,
                                     p->at<int>(L.cell_start), p->at<R>(L.outs), s));
@@ -961,11 +984,11 @@ int run_backward(hpnfft_plan_s *p, const void *f, const void *gfhat, void *grad_
         if (p->det())
             HCHECK(launch_interp_det<R>(p->m, true, dxf, p->B, p->Mtot, p->at<unsigned char>(L.rec), L.rec_bytes,
                                         p->at<R>(L.outs), p->cus, s));
-        else if (p->boxes)
-            HCHECK(launch_interp_box<R>(p->m, true, dxf, p->at<SItem>(L.items), p->nitems,
+        else if (p->any_box)
+            HCHECK(launch_interp_box<R>(p->m, true, dxf, p->at<SItem>(L.bitems), p->nbitems,
                                         p->at<int>(L.counters) + 1, p->max_cells, p->at<unsigned char>(L.rec),
                                         L.rec_bytes, p->at<int>(L.cell_start), p->at<R>(L.outs), s));
-        else
+        if (p->any_lines)
             HCHECK(launch_interp<R>(p->m, true, dxf, p->at<SItem>(L.items), p->nitems,
                                     p->at<int>(L.counters) + 1, p->til, p->at<unsigned char>(L.rec), L.rec_bytes,
                                     p->at<int>(L.cell_start), p->at<R>(L.outs), s));
@@ -1061,7 +1084,7 @@ int create_common(hpnfft_plan_s **out, int B, const int64_t *N, const int64_t *M
             p->arch[k] = 0;
         }
     }
-    p->boxes = choose_boxes(p);
+    choose_methods(p);
     p->til = default_tiling(p);
     build_layout(p);
     prepare_host_tables(p);
@@ -1149,7 +1172,7 @@ int hpnfft_set_method(hpnfft_plan p, int method)
     if (p->det() && method == HPNFFT_METHOD_LINES) return HPNFFT_EINVAL;  // deterministic plans use boxes
     drop_graph(p);
     p->method = method;
-    p->boxes = choose_boxes(p);
+    choose_methods(p);
     p->til = default_tiling(p);
     build_layout(p);
     p->have_ws = false;
@@ -1160,7 +1183,7 @@ int hpnfft_set_method(hpnfft_plan p, int method)
 int hpnfft_get_method(hpnfft_plan p, int *method)
 {
     if (!p || !method) return HPNFFT_EINVAL;
-    *method = p->boxes ? HPNFFT_METHOD_BOXES : HPNFFT_METHOD_LINES;
+    *method = p->boxes ? HPNFFT_METHOD_BOXES : (p->any_box ? HPNFFT_METHOD_MIXED : HPNFFT_METHOD_LINES);
     return HPNFFT_OK;
 }
 

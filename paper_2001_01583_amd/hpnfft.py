@@ -21,7 +21,7 @@ HEADER = os.path.join(os.path.dirname(_HERE), "include", "hpnfft.h")
 
 OK, EINVAL, EDOMAIN, ENOMEM, EHIP, ESTATE, ESIZE = 0, -1, -2, -3, -4, -5, -6
 KAISER_BESSEL, GAUSSIAN, BSPLINE, SINC_POWER = 0, 1, 2, 3
-METHOD_AUTO, METHOD_LINES, METHOD_BOXES = 0, 1, 2
+METHOD_AUTO, METHOD_LINES, METHOD_BOXES, METHOD_MIXED = 0, 1, 2, 3
 METHODS = {"auto": METHOD_AUTO, "lines": METHOD_LINES, "boxes": METHOD_BOXES}
 WINDOWS = {"kaiser_bessel": KAISER_BESSEL, "kb": KAISER_BESSEL, "gaussian": GAUSSIAN,
            "bspline": BSPLINE, "sinc_power": SINC_POWER}
@@ -227,10 +227,10 @@ class Plan:
     # -- API ---------------------------------------------------------------
     @property
     def method(self) -> str:
-        """Sweep method in use: "lines" or "boxes"."""
+        """Sweep method in use: "lines", "boxes" or "mixed" (a batch using both)."""
         v = ctypes.c_int()
         _check(_load().hpnfft_get_method(self._h, ctypes.byref(v)), "get_method")
-        return {METHOD_LINES: "lines", METHOD_BOXES: "boxes"}[v.value]
+        return {METHOD_LINES: "lines", METHOD_BOXES: "boxes", METHOD_MIXED: "mixed"}[v.value]
 
     @property
     def tiles(self):

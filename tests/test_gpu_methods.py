@@ -147,3 +147,40 @@ def test_methods_agree(H, oracle_mod):
     _, _, a1, b1 = _run(H, oracle_mod, N, x, f, fh, 8, "f64", "lines")
     _, _, a2, b2 = _run(H, oracle_mod, N, x, f, fh, 8, "f64", "boxes")
     assert oracle_mod.rel_l2(a2, a1) <= 1e-14 and oracle_mod.rel_l2(b2, b1) <= 1e-14
+
+
+@pytest.mark.parametrize("prec,m,tol", [("f64", 6, 1e-10), ("f32", 4, 1e-5)])
+def test_mixed_batch(H, oracle_mod, prec, m, tol):
+    """A batch whose dense transforms take the line sweeps and whose sparse
+    ones take boxes (the default per-transform choice), each against the
+    oracle, eager and graph-replayed."""
+    Ns = [(16, 16, 16), (32, 32, 32), (24, 24, 24), (16, 16, 16)]
+    Ms = [20000, 200, 9000, 3]        # densities 0.6, 0.0008, 0.08, 0.0001 points per cell
+    g = W.rng(1600 + m)
+    xs = [W.uniform_points(M, 3, g) for M in Ms]
+    fs = [W.complex_normal(M, g) for M in Ms]
+    if prec == "f32":
+        fs = [f.astype(np.complex64).astype(np.complex128) for f in fs]
+    cd = torch.complex128 if prec == "f64" else torch.complex64
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        plan = H.Plan(Ns, Ms, m=m, precision=prec)
+        assert plan.method == "mixed"
+        plan.set_points(torch.from_numpy(np.concatenate(xs)).cuda())
+        ft = torch.from_numpy(np.concatenate(fs)).cuda().to(cd)
+        eager = plan.adjoint(ft).clone()
+        out = torch.empty_like(eager)
+        plan.capture(ft, out)
+        for _ in range(2):
+            out.zero_()
+            plan.replay()
+            torch.cuda.synchronize()
+            err = (out - eager).abs().max().item() / eager.abs().max().item()
+            assert err <= 1e-5, err
+    torch.cuda.synchronize()
+    eager = eager.cpu().numpy().astype(np.complex128)
+    for b, (N, x, f) in enumerate(zip(Ns, xs, fs)):
+        _, fo = plan.offsets(b)
+        a = eager[fo:fo + int(np.prod(N))].reshape(N)
+        e = oracle_mod.rel_l2(a, oracle_mod.ndft_adjoint(N, x, f))
+        assert e <= tol, (b, e)
