@@ -131,7 +131,8 @@ int hpnfft_set_stream(hpnfft_plan plan, void *hip_stream);
  *                        it; the grid is written once, with plain stores
  *                        (sparse point sets)
  *   HPNFFT_METHOD_AUTO   (the default) per transform: boxes below 0.1
- *                        (float64) or 0.02 (float32) points per grid cell,
+ *                        (float64) or 0.05 (float32) points per grid cell
+ *                        (environment variable HPNFFT_BOX_DENSITY overrides),
  *                        so a batch may mix the two (its tiling then sets the
  *                        line sweeps; its box transforms use 16-cell boxes)
  * The results agree to rounding; hpnfft_get_method reports the method in use

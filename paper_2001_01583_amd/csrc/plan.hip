@@ -364,16 +364,24 @@ long long box_max_cells(const hpnfft_plan_s *p, Tiling t)
 // float32 atomic add runs at 0.33 lanes per clock per compute unit against
 // 7.6 for float64 and 3.5 for the 64-bit swap), so float32 switches later.
 // Measured on MI355X: at 0.5 points per cell the line sweeps are 3.5-10x
-// faster; at 0.05 (the 256-transform batch, float32) 1.9x; at 0.01 (the
-// 24^3-cell Ewald lattice on a 256^3 grid) the boxes are 2.2x (float64) and
-// 1.3x (float32) faster.
+// faster; at 0.01 (the 24^3-cell Ewald lattice on a 256^3 grid) the boxes
+// are 2.2x (float64) and 1.3x (float32) faster.  The 256-transform float32
+// batch (0.0001 - 4 points per cell per transform) runs fastest with the
+// float32 switch at 0.05 (29.0 ms; 31.3 at 0.005, 32.6 at 0.1, 38.9 all
+// lines).
 constexpr double kBoxDensityF64 = 0.1;
-constexpr double kBoxDensityF32 = 0.02;
+constexpr double kBoxDensityF32 = 0.05;
 // The method of every transform (a batch may mix them: sparse transforms
 // take boxes, dense ones the line sweeps).
 void choose_methods(hpnfft_plan_s *p)
 {
-    const double thr = p->prec == HPNFFT_F32 ? kBoxDensityF32 : kBoxDensityF64;
+    double thr = p->prec == HPNFFT_F32 ? kBoxDensityF32 : kBoxDensityF64;
+    // HPNFFT_BOX_DENSITY overrides the switch-over density (read per plan)
+    if (const char *v = std::getenv("HPNFFT_BOX_DENSITY")) {
+        char *end = nullptr;
+        const double d = std::strtod(v, &end);
+        if (end != v && d >= 0.0) thr = d;
+    }
     p->tbox.assign(p->B, 0);
     for (int b = 0; b < p->B; ++b) {
         const Xform &X = p->hx[b];
