@@ -66,6 +66,7 @@ struct Tiling {
     int Zs;       // slab depth (planes) along dim 0
     int threads;  // threads per workgroup of spread / interp
     int cap_hint = 0;  // points per staging chunk worth reserving (0: as many as fit)
+    int ring = 0;      // spread by the ring sweep (set per launch by the plan)
 };
 
 __host__ __device__ constexpr size_t align16(size_t v) { return (v + 15) & ~(size_t)15; }
@@ -76,6 +77,10 @@ __host__ __device__ constexpr size_t align16(size_t v) { return (v + 15) & ~(siz
 // for the HBM access too.  as_global restores global addressing.
 template <typename T> using gptr = __attribute__((address_space(1))) T *;
 template <typename T> __device__ __forceinline__ gptr<T> as_global(T *p) { return (gptr<T>)p; }
+// Read-only data (not written while the kernel runs) addressed as constant
+// memory: loads from wavefront-uniform addresses become scalar loads.
+template <typename T> using cptr = __attribute__((address_space(4))) const T *;
+template <typename T> __device__ __forceinline__ cptr<T> as_const(const T *p) { return (cptr<T>)p; }
 
 // Record of one sorted point (16-byte aligned, contiguous per run):
 //   [psi: 3 x 2m window values (dim 0 rotated, dims 1, 2 natural)]
@@ -98,6 +103,18 @@ __host__ __device__ constexpr size_t rec_off_xr(int M2, size_t R) { return 3 * M
 // footprint, so the register window a lane retires per plane serves the
 // points of 8 lines instead of one.  Other windows use single lines.
 __host__ __device__ constexpr int block_w(int M2) { return M2 == 8 ? 8 : 1; }
+
+// Ring sweep of the 2m = 8 spread (ring.h): tiles of kRingT x kRingT lines,
+// phases of kRingZp planes, slabs of a multiple of 2m planes.  The records store the
+// dim-0 weights rotated by the absolute plane (mod 2m) while the ring counts
+// planes from the slab start through the periodic images, so the plan also
+// requires n0 to be a multiple of 2m.
+constexpr int kRingT = 8;
+constexpr int kRingZp = 8;
+__host__ __device__ constexpr bool ring_tiling(int M2, int T, int Zs)
+{
+    return M2 == 8 && T == kRingT && Zs >= M2 && Zs % M2 == 0;
+}
 
 // Coefficients of the per-tap window polynomials (see fit_window_poly).
 constexpr int kPolyF32 = 10;

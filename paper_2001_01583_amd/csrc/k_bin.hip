@@ -207,6 +207,28 @@ __global__ __launch_bounds__(256) void k_bin_scatter(const double *__restrict__ 
             }
         }
     }
+    // blocks of lines (line method): dim 2 in lane order, slot x = (tap +
+    // j) mod 2m for the point's line j in its block, so that the lane of
+    // block column x (which receives tap (x - j) mod 2m) reads a fixed slot
+    if (block_w(M2) > 1 && !nb0) {
+        const int jl = (c[2] % T) % block_w(M2);
+#pragma unroll
+        for (int k = 1; k < M2; k <<= 1) {
+            if (jl & k) {
+                R tmp[M2], dtmp[GRAD ? M2 : 1];
+#pragma unroll
+                for (int s = 0; s < M2; ++s) {
+                    tmp[s] = w[2 * M2 + (s - k + M2) % M2];
+                    if constexpr (GRAD) dtmp[s] = dw[2 * M2 + (s - k + M2) % M2];
+                }
+#pragma unroll
+                for (int s = 0; s < M2; ++s) {
+                    w[2 * M2 + s] = tmp[s];
+                    if constexpr (GRAD) dw[2 * M2 + s] = dtmp[s];
+                }
+            }
+        }
+    }
     store_block<NW * sizeof(R)>(rp, w);
     *reinterpret_cast<int2 *>(rp + rec_off_pz(M2, sizeof(R))) =
         nb0 ? make_int2(c[0], (c[1] << kBoxCellBits) | c[2]) : make_int2(c[0], (c[2] % T) % block_w(M2));

@@ -1,7 +1,7 @@
 // Spread and interpolation launchers for windows of 2m <= 16 cells (m <= 8);
 // wider windows (m = 9 .. 15) are instantiated in k_spread_wide.hip.  The
 // kernels themselves are in sweep.h.
-#include "sweep.h"
+#include "ring.h"
 
 namespace hpnfft {
 
@@ -20,6 +20,8 @@ hipError_t launch_spread(int m, const Xform *dxf, const SItem *items, int nitems
 {
 #define HPNFFT_SPREAD_CASE(MM) \
     case MM: return spread_m<R, 2 * MM>(dxf, items, nitems, queue, t, rec, rec_bytes, fs, cell_start, s);
+    if (m == 4 && t.ring && ring_tiling(8, t.T, t.Zs))
+        return spread_ring<R>(dxf, items, nitems, queue, t, rec, rec_bytes, fs, cell_start, s);
     switch (m) {
         HPNFFT_SPREAD_CASE(1)
         HPNFFT_SPREAD_CASE(2)

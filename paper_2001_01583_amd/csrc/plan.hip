@@ -207,7 +207,7 @@ void hlog(const char *fmt, ...)
 // architecture and compute-unit count, precision, cut-off, window, sigma,
 // the gradient flag, and per transform the grid edges and the point count
 // rounded down to a power of two (batches: a hash of that list).
-constexpr int kTuneCacheVersion = 2;
+constexpr int kTuneCacheVersion = 3;
 
 const char *tune_cache_path()
 {
@@ -402,6 +402,22 @@ void choose_methods(hpnfft_plan_s *p)
 // line sweeps), 16 cells.
 Tiling box_tiling(const hpnfft_plan_s *p, Tiling t) { return p->boxes ? t : Tiling{16, 16, 512}; }
 
+// Whether the line spread of this plan runs as the ring sweep: a 2m = 8
+// plan with a ring tiling whose line-method transforms all have n0 a
+// multiple of 2m (HPNFFT_RING=0 turns the ring sweep off).
+bool use_ring(const hpnfft_plan_s *p, const Tiling &t)
+{
+    static int on = -1;
+    if (on < 0) {
+        const char *e = getenv("HPNFFT_RING");
+        on = (e && e[0] == '0') ? 0 : 1;
+    }
+    if (!on || !ring_tiling(p->M2(), t.T, t.Zs)) return false;
+    for (size_t b = 0; b < p->hx.size(); ++b)
+        if (!p->tbox[b] && p->hx[b].n[0] % p->M2()) return false;
+    return true;
+}
+
 bool tiling_fits(const hpnfft_plan_s *p, Tiling t)
 {
     if (t.T < 4 || t.T > 32 || t.Zs < 2 || t.Zs > 64) return false;
@@ -416,7 +432,7 @@ bool tiling_fits(const hpnfft_plan_s *p, Tiling t)
     }
     if (t.T % block_w(p->M2())) return false;  // whole blocks of lines per tile row
     bool comp = p->prec == HPNFFT_F32;
-    if (!lds_fit(t.T, t.Zs, p->M2(), p->rbytes(), 0, comp).cap) return false;
+    if (!use_ring(p, t) && !lds_fit(t.T, t.Zs, p->M2(), p->rbytes(), 0, comp).cap) return false;
     if (!lds_fit(t.T, t.Zs, p->M2(), p->rbytes(), 1, false).cap) return false;
     if (p->grad() && !lds_fit(t.T, t.Zs, p->M2(), p->rbytes(), 2, false).cap) return false;
     return true;
@@ -443,6 +459,14 @@ Tiling default_tiling(const hpnfft_plan_s *p)
         // per 1024 cells: 64 KiB, two workgroups per compute unit)
         for (int Tb : {16, 12, 8})
             if (tiling_fits(p, Tiling{Tb, Tb, 512})) return Tiling{Tb, Tb, 512};
+    }
+    // 2m = 8: the ring spread (tiles of 8 x 8 lines) with the slab depth
+    // that measured fastest for spread plus interpolation at 0.5 points
+    // per cell (float32: 16 planes, 0.229 + 0.221 ms at N = 64^3, M = 2^20;
+    // float64: 32 planes)
+    if (block_w(M2) > 1) {
+        const Tiling r{kRingT, p->prec == HPNFFT_F32 ? 16 : 32, 512};
+        if (use_ring(p, r) && tiling_fits(p, r)) return r;
     }
     // blocked 2m = 8 sweeps: tiles of one block of lines per row fit best
     const int target = block_w(M2) > 1 ? 8 : std::max(4, 22 - M2);
@@ -916,10 +940,13 @@ template <typename R> int run_adjoint(hpnfft_plan_s *p, const void *f, void *fha
             HCHECK(launch_spread_box<R>(p->m, dxf, p->at<SItem>(L.bitems), p->nbitems, p->at<int>(L.counters),
                                         p->max_cells, p->at<unsigned char>(L.rec), L.rec_bytes, p->at<R>(L.fs),
                                         p->at<int>(L.cell_start), s));
-        if (p->any_lines)
-            HCHECK(launch_spread<R>(p->m, dxf, p->at<SItem>(L.items), p->nitems, p->at<int>(L.counters), p->til,
+        if (p->any_lines) {
+            Tiling t = p->til;
+            t.ring = use_ring(p, t);
+            HCHECK(launch_spread<R>(p->m, dxf, p->at<SItem>(L.items), p->nitems, p->at<int>(L.counters), t,
                                     p->at<unsigned char>(L.rec), L.rec_bytes, p->at<R>(L.fs),
                                     p->at<int>(L.cell_start), s));
+        }
     }
     for (int pass = P_ADJ0; pass <= P_ADJ2; ++pass) {
         int d = pass == P_ADJ0 ? 2 : (pass == P_ADJ1 ? 1 : 0);

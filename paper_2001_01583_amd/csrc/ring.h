@@ -1,0 +1,265 @@
+// Ring sweep of the spread (the Spreading step of Algorithm 2, Section 3)
+// for windows of 2m = 8 cells, the blocked-line layout of sweep.h.
+//
+// A work item is a tile of 8 x 8 z-lines (eight blocks of 8 lines, one per
+// tile row) restricted to a slab of Zs planes along dim 0.  Each wavefront
+// owns one block and sweeps all of its points through the slab in plane
+// order, the three periodic images of the block's line segment merged into
+// one stream, so a point is read once per slab it reaches rather than once
+// per chunk of a staging buffer.  The per-point values that are the same on
+// every lane (dim-0 weights, the value, the header) come through scalar
+// loads; the lane's own dim-1 and dim-2 weights are one load each from fixed
+// slots of the record (dim 2 is stored in lane order).
+//
+// The blocks of one tile overlap in their tap rows, so their retired planes
+// meet in LDS: a ring of kRingZp = 2m planes, one phase.  In phase k the
+// wavefronts retire planes [k Zp, (k + 1) Zp); after a barrier all threads
+// add the ring to the grid (one atomic per cell) and clear it, and a second
+// barrier opens the next phase.  Register windows (the planes still open
+// when a phase ends) carry over to the next phase.  The ring is small (30
+// KiB) so that four workgroups share a compute unit and hide each other's
+// barriers and load latencies.
+#pragma once
+
+#include "sweep.h"
+
+namespace hpnfft {
+
+constexpr int kRingP = kRingT + 7;  // footprint rows (and used columns) of a tile
+constexpr int kRingPitch = 16;   // cells per LDS row; column 15 only ever receives zeros
+constexpr int kRingPlane = kRingP * kRingPitch;
+constexpr int kRingThreads = 512;  // eight wavefronts: one per block of the tile
+constexpr size_t kRingLds = (size_t)kRingZp * kRingPlane * 16;  // re and im arrays of 8-byte cells
+
+// Wavefronts per SIMD the register budget is set for: the ring takes 30 KiB
+// of LDS, so four workgroups (eight wavefronts per SIMD, 64 registers per
+// lane) fit in float32; the float64 sweep holds twice the window in
+// registers and keeps four wavefronts per SIMD.
+template <typename R> constexpr int ring_waves_per_simd() { return sizeof(R) == 4 ? 8 : 4; }
+
+template <typename R, bool COMP>
+__global__ __launch_bounds__(kRingThreads, ring_waves_per_simd<R>()) void k_spread_ring(const Xform *__restrict__ xfs,
+                                                               const SItem *__restrict__ items, int nitems,
+                                                               int *__restrict__ queue, int Zs,
+                                                               const unsigned char *__restrict__ rec, int rbytes,
+                                                               const R *__restrict__ fs,
+                                                               const int *__restrict__ cell_start)
+{
+    constexpr int M2 = 8, m = 4, BW = 8;
+    constexpr int NRP = kRingZp;           // ring planes
+    constexpr int IM = NRP * kRingPlane;   // cells before the imaginary array
+    constexpr int OFF_PZ = (int)rec_off_pz(M2, sizeof(R));
+    static_assert((NRP & (NRP - 1)) == 0, "ring planes: a power of two");
+    extern __shared__ uint4 smem16[];
+    unsigned long long *pairs = reinterpret_cast<unsigned long long *>(smem16);
+    R *acc = reinterpret_cast<R *>(smem16);
+    __shared__ int s_item;
+    const int tid = threadIdx.x, lane = tid & 63, wave = uni(tid >> 6);
+    const int dy = lane >> 3, xm = lane & 7;
+
+    // the flushes leave every cell they read at zero
+    for (int i = tid; i < 2 * IM; i += blockDim.x) pairs[i] = 0ull;
+
+    for (int it = next_item(queue, &s_item); it < nitems; it = next_item(queue, &s_item)) {
+        const SItem W = items[uni(it)];
+        const Xform *X = xfs + W.xf;
+        const int n0 = X->n[0], n1 = X->n[1], n2 = X->n[2];
+        const int ntx = X->ntx;
+        const int X0 = (W.tile % ntx) * kRingT, Y0 = (W.tile / ntx) * kRingT;
+        const int z0 = W.slab * Zs, zs = min(Zs, n0 - z0);
+        const long long poff = X->poff;
+        const int li = W.lb + wave;  // this wavefront's block (tile row li)
+        const bool mine = li < W.le && Y0 + li < n1;
+
+        // The block's points by plane: sorted positions [cs[8 c], cs[8 (c + 1)])
+        // hold plane c of the block (every line).  Slab-relative plane q is
+        // the first tap plane of the points in grid plane c = q + m - 1 + z0
+        // (mod n0): the periodic images of the line segment come in plane
+        // order by themselves.
+        const int *cs = cell_start + X->key_off + ((long long)W.tile * (kRingT * kRingT / BW) + li) * n0 * BW;
+        const int Mx = (int)X->M;
+        auto plane_c = [&](int q) __attribute__((always_inline)) {
+            int c = q + (m - 1) + z0;  // within [-m, 2 n0)
+            c += c < 0 ? n0 : 0;
+            c -= c >= n0 ? n0 : 0;
+            return c;
+        };
+
+        // Point data, one point ahead: the loads of the next point in memory
+        // are in flight while the current one is added (a point whose data
+        // was not prefetched, the first of a plane after a periodic wrap, is
+        // loaded when it is reached).
+        struct PointData {
+            R wz[M2];
+            R f0, f1, wy, wx;
+            int j;
+        };
+        // (the wavefront-uniform parts are read as constant memory, i.e.
+        // through scalar loads: records and values do not change while the
+        // kernel runs)
+        const unsigned char *recb = rec + (size_t)poff * rbytes;
+        const R *fsb = fs + 2 * poff;
+        auto fetch = [&](const unsigned char *rp, const R *fp, PointData &d) __attribute__((always_inline)) {
+            const cptr<R> pc = as_const(reinterpret_cast<const R *>(rp));
+#pragma unroll
+            for (int s = 0; s < M2; ++s) d.wz[s] = pc[s];
+            d.j = as_const(reinterpret_cast<const int *>(rp + OFF_PZ))[1];
+            d.f0 = as_const(fp)[0];
+            d.f1 = as_const(fp)[1];
+            const R *ps = reinterpret_cast<const R *>(rp);
+            d.wy = ps[M2 + dy];
+            d.wx = ps[2 * M2 + xm];
+        };
+        PointData cur{};
+        int cidx = -1;  // point whose data cur holds
+        const unsigned char *rcur = recb;  // its record
+        const R *fcur = fsb;               // its value
+
+        R wr[2][M2], wi[2][M2];
+#pragma unroll
+        for (int w = 0; w < 2; ++w)
+#pragma unroll
+            for (int s = 0; s < M2; ++s) wr[w][s] = wi[w][s] = R(0);
+
+        const int rowc = (li + dy) * kRingPitch + xm;  // lane's first cell in a ring plane
+        int last = -1000;  // first tap plane of the last point added
+        // sorted range of the next plane to sweep, loaded one plane ahead
+        // (the first plane with points is -(2m - 1): windows that end on
+        // the slab's first plane)
+        int na = 0, nb = 0;
+        if (mine) {
+            const int c = plane_c(-(M2 - 1));
+            na = cs[c * BW];
+            nb = cs[(c + 1) * BW];
+        }
+
+        // plane q: add its points, retire slot k = q mod 2m (if in this
+        // phase's planes and reached by some window), clear the slot
+        auto plane_step = [&](const int k, const int q, const int pe) __attribute__((always_inline)) {
+            if (q >= -(M2 - 1) && q < zs) {
+                const int pa = uni(na), pb = uni(nb);
+                const int c = plane_c(q + 1);
+                na = cs[c * BW];
+                nb = cs[(c + 1) * BW];
+                for (int sp = pa; sp < pb; ++sp) {
+                    if (sp != cidx) {
+                        rcur = recb + (size_t)sp * rbytes;
+                        fcur = fsb + 2 * sp;
+                        fetch(rcur, fcur, cur);
+                    }
+                    const bool adv = sp + 1 < Mx;
+                    const unsigned char *rnx = adv ? rcur + rbytes : rcur;
+                    const R *fnx = adv ? fcur + 2 : fcur;
+                    PointData nxt;
+                    fetch(rnx, fnx, nxt);
+                    const int j = uni(cur.j);
+                    const R w12 = cur.wy * cur.wx;
+                    const R fr = cur.f0 * w12, fi = cur.f1 * w12;
+                    // a point on line j reaches column xm (tap xm - j) when
+                    // xm >= j, else column xm + 8
+                    const bool hi = xm < j;
+                    const R s0r = hi ? R(0) : fr, s0i = hi ? R(0) : fi;
+                    const R s1r = hi ? fr : R(0), s1i = hi ? fi : R(0);
+#pragma unroll
+                    for (int s = 0; s < M2; ++s) {
+                        const R wz = cur.wz[s];
+                        wr[0][s] = fma(s0r, wz, wr[0][s]);
+                        wi[0][s] = fma(s0i, wz, wi[0][s]);
+                        wr[1][s] = fma(s1r, wz, wr[1][s]);
+                        wi[1][s] = fma(s1i, wz, wi[1][s]);
+                    }
+                    cur = nxt;
+                    cidx = adv ? sp + 1 : sp;
+                    rcur = rnx;
+                    fcur = fnx;
+                }
+                if (pb > pa) last = q;
+            }
+            if (q >= 0 && q < pe && last + M2 > q) {
+                const int o = (q & (NRP - 1)) * kRingPlane + rowc;
+                if constexpr (COMP) {
+                    unsigned long long *c[4] = {&pairs[o], &pairs[o + 8], &pairs[o + IM], &pairs[o + IM + 8]};
+                    const float v[4] = {(float)wr[0][k], (float)wr[1][k], (float)wi[0][k], (float)wi[1][k]};
+                    const bool ok[4] = {true, true, true, true};
+                    lds_add_comp<4>(c, v, ok);
+                } else {
+                    atomicAdd(&acc[o], wr[0][k]);
+                    atomicAdd(&acc[o + IM], wi[0][k]);
+                    if (xm < 7) {
+                        atomicAdd(&acc[o + 8], wr[1][k]);
+                        atomicAdd(&acc[o + IM + 8], wi[1][k]);
+                    }
+                }
+            }
+            wr[0][k] = wi[0][k] = wr[1][k] = wi[1][k] = R(0);
+        };
+
+        // planes in groups of 2m (slot k of plane p + k, p a multiple of 2m);
+        // a phase is one group
+        int p = -M2;
+        const int nph = (zs + kRingZp - 1) / kRingZp;
+        for (int ph = 0; ph < nph; ++ph) {
+            const int pe = min((ph + 1) * kRingZp, zs);  // planes below pe retire in this phase
+            if (mine) {
+                for (; p < pe; p += M2) {
+#pragma unroll
+                    for (int k = 0; k < M2; ++k) plane_step(k, p + k, pe);
+                }
+            }
+            __syncthreads();
+            // add this phase's planes to the grid and clear them
+            const int zb = ph * kRingZp, nzp = pe - zb;
+            const int ry0 = W.lb, ry1 = min(W.le, n1 - Y0) + M2 - 1;  // rows any block reached
+            const size_t pstride = (size_t)n1 * n2;
+            const gptr<R> grid = as_global(reinterpret_cast<R *>(X->grid));
+            for (int i = tid; i < nzp * kRingPlane; i += blockDim.x) {
+                const int zz = i / kRingPlane, c = i - zz * kRingPlane;
+                const int y = c / kRingPitch, x = c % kRingPitch;
+                if (y < ry0 || y >= ry1 || x >= kRingP) continue;
+                const int o = ((zb + zz) & (NRP - 1)) * kRingPlane + c;
+                R vr, vi;
+                if constexpr (COMP) {
+                    const unsigned long long a0 = pairs[o], a1 = pairs[o + IM];
+                    vr = (R)(__uint_as_float((unsigned int)a0) + __uint_as_float((unsigned int)(a0 >> 32)));
+                    vi = (R)(__uint_as_float((unsigned int)a1) + __uint_as_float((unsigned int)(a1 >> 32)));
+                } else {
+                    vr = acc[o];
+                    vi = acc[o + IM];
+                }
+                pairs[o] = 0ull;
+                pairs[o + IM] = 0ull;
+                int gy = Y0 + y - (m - 1), gx = X0 + x - (m - 1);
+                gy += gy < 0 ? n1 : 0;
+                gy -= gy >= n1 ? n1 : 0;
+                gy -= gy >= n1 ? n1 : 0;
+                gx += gx < 0 ? n2 : 0;
+                gx -= gx >= n2 ? n2 : 0;
+                gx -= gx >= n2 ? n2 : 0;
+                const size_t gi = ((size_t)(z0 + zb + zz) * pstride + (size_t)gy * n2 + gx) * 2;
+                if (vr != R(0)) __hip_atomic_fetch_add(&grid[gi], vr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (vi != R(0)) __hip_atomic_fetch_add(&grid[gi + 1], vi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            // the next phase retires into the same planes
+            if (ph + 1 < nph) __syncthreads();
+        }
+    }
+    release_queue(queue);
+}
+
+template <typename R>
+static hipError_t spread_ring(const Xform *dxf, const SItem *items, int nitems, int *queue, Tiling t,
+                              const unsigned char *rec, size_t rec_bytes, const R *fs, const int *cs, hipStream_t s)
+{
+    constexpr bool COMP = sizeof(R) == 4;
+    auto kern = k_spread_ring<R, COMP>;
+    hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kRingLds);
+    if (e != hipSuccess) return e;
+    const int per_cu = std::max(1, (int)((160 * 1024) / (kRingLds + 1024)));
+    const int grid = std::min(cu_count() * per_cu, nitems);
+    if (grid < 1) return hipSuccess;
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(kRingThreads), kRingLds, s, dxf, items, nitems, queue, t.Zs, rec,
+                       (int)rec_bytes, fs, cs);
+    return hipGetLastError();
+}
+
+}  // namespace hpnfft

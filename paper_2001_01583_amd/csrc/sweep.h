@@ -478,8 +478,6 @@ __global__ __launch_bounds__(spread_max_threads(sizeof(R), M2)) void k_spread(co
                     row_ok[1] = xm < BW - 1;  // column lx + 15 is outside every footprint
                 }
                 const int qshift = U - g.z0 - M2;  // slab-relative plane = q + qshift
-                // byte offsets of the dim-2 weights of columns lx + xm, lx + xm + BW
-                const int xb0 = (2 * M2 + xm) * (int)sizeof(R), xb1 = xb0 + BW * (int)sizeof(R);
 
                 R wr[NW][M2], wi[NW][M2];
 #pragma unroll
@@ -539,13 +537,10 @@ __global__ __launch_bounds__(spread_max_threads(sizeof(R), M2)) void k_spread(co
                             const int2 hx = head_of(stage, min(sl + 1, b - 1), ST16, OFF_PZ);
                             R sr[NW], si[NW];
                             if constexpr (NW > 1) {
-                                const int j = jn;
-                                const bool hi = xm < j;
-                                // tap dx = column - j, addressed as (ps - j)[column]
-                                // so that the per-point part stays scalar
-                                const int pj = uni(sl * ST16 * 16 - j * (int)sizeof(R));
-                                const R w12 = ps[M2 + dy] * *reinterpret_cast<const R *>(
-                                    reinterpret_cast<const unsigned char *>(stage) + pj + (hi ? xb1 : xb0));
+                                // the record holds dim 2 in lane order (slot xm =
+                                // tap (xm - j) mod 2m), so the lane reads slot xm
+                                const bool hi = xm < jn;
+                                const R w12 = ps[M2 + dy] * ps[2 * M2 + xm];
                                 const R fr = ps[OFF_F] * w12, fi = ps[OFF_F + 1] * w12;
                                 sr[0] = hi ? R(0) : fr;
                                 si[0] = hi ? R(0) : fi;
@@ -804,17 +799,9 @@ __global__ __launch_bounds__(interp_max_threads(sizeof(R), M2, GRAD)) void k_int
                                     // the lane's row for this point: single
                                     // lines use row 0; in a block, row 1 when
                                     // the point's line lies right of column xm
-                                    // dim-2 tap of the lane: byte offset of ps[2m + dx]
-                                    // as (ps - j)[2m + column] (j scalar)
-                                    int xb = (2 * M2 + xm) * (int)sizeof(R);
-                                    int js = 0;
-                                    bool hi = false;
-                                    if constexpr (NW > 1) {
-                                        const int j = jn;
-                                        hi = xm < j;
-                                        xb = hi ? xb + BW * (int)sizeof(R) : xb;
-                                        js = j * (int)sizeof(R);
-                                    }
+                                    // (dim 2 is stored in lane order: the
+                                    // lane's tap is slot xm)
+                                    const bool hi = NW > 1 && xm < jn;
                                     R sr, si;
                                     {
                                         R ar[NW], ai[NW];
@@ -831,9 +818,7 @@ __global__ __launch_bounds__(interp_max_threads(sizeof(R), M2, GRAD)) void k_int
                                         si = (NW > 1 && hi) ? ai[NW - 1] : ai[0];
                                     }
                                     const R w1 = active ? ps[M2 + dy] : R(0);
-                                    const R w2 = active ? *reinterpret_cast<const R *>(
-                                                              reinterpret_cast<const unsigned char *>(ps) - js + xb)
-                                                        : R(0);
+                                    const R w2 = active ? ps[2 * M2 + xm] : R(0);
                                     const R w12 = w1 * w2;
                                     R v[2 * NO];
                                     v[0] = sr * w12;
@@ -856,9 +841,7 @@ __global__ __launch_bounds__(interp_max_threads(sizeof(R), M2, GRAD)) void k_int
                                             di = (NW > 1 && hi) ? ai[NW - 1] : ai[0];
                                         }
                                         const R d1 = active ? dp[M2 + dy] * w2 : R(0);
-                                        const R d2 = active ? w1 * *reinterpret_cast<const R *>(
-                                                                   reinterpret_cast<const unsigned char *>(dp) - js + xb)
-                                                            : R(0);
+                                        const R d2 = active ? w1 * dp[2 * M2 + xm] : R(0);
                                         v[2] = dr * w12;
                                         v[3] = di * w12;
                                         v[4] = sr * d1;

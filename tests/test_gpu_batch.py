@@ -203,7 +203,7 @@ def test_autotune_cache(H, oracle_mod, tmp_path, monkeypatch):
     tiles = plan.autotune()
     t_first = time.perf_counter() - t0
     txt = path.read_text()
-    assert '"hpnfft_tune_cache": 2' in txt and "[%d, %d, %d]" % tiles in txt
+    assert '"hpnfft_tune_cache": 3' in txt and "[%d, %d, %d]" % tiles in txt
     plan2 = H.Plan(N, M, m=4, precision="f32")
     plan2.set_points(torch.from_numpy(x).cuda())
     t0 = time.perf_counter()
