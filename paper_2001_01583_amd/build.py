@@ -22,7 +22,7 @@ LIB = os.path.join(HERE, "libhpnfft.so")
 OBJDIR = os.path.join(HERE, "_build")
 
 SOURCES = ["plan.hip", "k_bin.hip", "k_items.hip", "k_spread.hip", "k_spread_wide.hip", "k_fft.hip", "k_misc.hip", "k_ewald.hip", "k_boxes.hip", "k_det.hip"]
-HEADERS = ["internal.h", "window.h", "sweep.h", "wave_reduce.h"]
+HEADERS = ["internal.h", "window.h", "sweep.h", "ring.h", "wave_reduce.h"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -41,6 +41,8 @@ hipError_t launch_interp(int m, bool grad, const Xform *dxf, const SItem *items,
                          Tiling t, const unsigned char *rec, size_t rec_bytes, const int *cs, R *outs,
                          hipStream_t s)
 {
+    if (m == 4 && !grad && t.ring && ring_tiling(8, t.T, t.Zs))
+        return interp_ring<R>(dxf, items, nitems, queue, t, rec, rec_bytes, cs, outs, s);
 #define HPNFFT_INTERP_CASE(MM)                                                                        \
     case MM:                                                                                          \
         return grad ? interp_m<R, 2 * MM, true>(dxf, items, nitems, queue, t, rec, rec_bytes, cs, outs, s) \

@@ -460,12 +460,12 @@ Tiling default_tiling(const hpnfft_plan_s *p)
         for (int Tb : {16, 12, 8})
             if (tiling_fits(p, Tiling{Tb, Tb, 512})) return Tiling{Tb, Tb, 512};
     }
-    // 2m = 8: the ring spread (tiles of 8 x 8 lines) with the slab depth
+    // 2m = 8: the ring sweeps (tiles of 8 x 8 lines) with the slab depth
     // that measured fastest for spread plus interpolation at 0.5 points
-    // per cell (float32: 16 planes, 0.229 + 0.221 ms at N = 64^3, M = 2^20;
-    // float64: 32 planes)
+    // per cell (32 planes; float32 0.215 + 0.152 ms, float64 0.303 + 0.259
+    // ms at N = 64^3, M = 2^20)
     if (block_w(M2) > 1) {
-        const Tiling r{kRingT, p->prec == HPNFFT_F32 ? 16 : 32, 512};
+        const Tiling r{kRingT, 32, 512};
         if (use_ring(p, r) && tiling_fits(p, r)) return r;
     }
     // blocked 2m = 8 sweeps: tiles of one block of lines per row fit best
@@ -975,7 +975,9 @@ template <typename R> int run_forward(hpnfft_plan_s *p, const void *fhat, void *
     const Layout &L = p->L;
     hipStream_t s = p->stream;
     const Xform *dxf = p->at<Xform>(L.xf);
-    {
+    // the ring interpolation stores every point's value once; the other
+    // sweeps add partial sums into a cleared output
+    if (p->any_box || p->det() || !use_ring(p, p->til)) {
         PhaseTimer t(p, HPNFFT_PH_ZERO);
         HCHECK(launch_zero(p->ws + L.outs, (size_t)p->Mtot * 2 * sizeof(R), s));
     }
@@ -990,10 +992,13 @@ template <typename R> int run_forward(hpnfft_plan_s *p, const void *fhat, void *
             HCHECK(launch_interp_box<R>(p->m, false, dxf, p->at<SItem>(L.bitems), p->nbitems,
                                         p->at<int>(L.counters) + 1, p->max_cells, p->at<unsigned char>(L.rec),
                                         L.rec_bytes, p->at<int>(L.cell_start), p->at<R>(L.outs), s));
-        if (p->any_lines)
+        if (p->any_lines) {
+            Tiling t = p->til;
+            t.ring = use_ring(p, t);
             HCHECK(launch_interp<R>(p->m, false, dxf, p->at<SItem>(L.items), p->nitems,
-                                    p->at<int>(L.counters) + 1, p->til, p->at<unsigned char>(L.rec), L.rec_bytes,
+                                    p->at<int>(L.counters) + 1, t, p->at<unsigned char>(L.rec), L.rec_bytes,
                                     p->at<int>(L.cell_start), p->at<R>(L.outs), s));
+        }
     }
     {
         PhaseTimer t(p, HPNFFT_PH_SCATTER);

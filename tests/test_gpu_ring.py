@@ -1,10 +1,12 @@
-"""The ring sweep of the spread for 2m = 8 (the Spreading step of Algorithm 2,
-Section 3): tiles of 8 x 8 lines, slabs of whole 8-plane phases, one
-wavefront per block of 8 lines sweeping its points through the slab while
-the retired planes meet in a two-phase LDS ring.  Checked against the direct
-FP64 oracle (Eq. (5)) and against the staged sweep, on slabs that divide the
-grid and ragged ones, grids as small as the window (n = 2m), clustered point
-sets (heavy tiles cut into line ranges), batches and gradient plans."""
+"""The ring sweeps for 2m = 8 (the Spreading step of Algorithm 2 and the
+Interpolating step of Algorithm 5, Section 3): tiles of 8 x 8 lines, slabs of
+whole 8-plane phases, one wavefront per block of 8 lines sweeping its points
+through the slab while the planes pass through an LDS ring.  Checked against
+the direct FP64 oracle (Eqs. (5) and (6)) and against the staged sweeps, on
+slabs that divide the grid and ragged ones, grids as small as the window
+(n = 2m), clustered point sets (heavy tiles cut into line ranges), batches
+and gradient plans; grids whose n0 is no multiple of 2m fall back to the
+staged sweeps."""
 import numpy as np
 import pytest
 import torch
@@ -21,11 +23,15 @@ def H():
     return hpnfft
 
 
-def _adjoint(H, N, x, f, prec, tiles, with_grad=False):
+def _adjoint(H, N, x, f, prec, tiles, with_grad=False, fh=None):
     cd = torch.complex128 if prec == "f64" else torch.complex64
     plan = H.Plan(N, x.shape[0], m=4, precision=prec, method="lines", tiles=tiles, with_grad=with_grad)
     plan.set_points(torch.from_numpy(x).cuda())
-    return plan.adjoint(torch.from_numpy(f).cuda().to(cd)).cpu().numpy().astype(np.complex128)
+    a = plan.adjoint(torch.from_numpy(f).cuda().to(cd)).cpu().numpy().astype(np.complex128)
+    if fh is None:
+        return a
+    b = plan.forward(torch.from_numpy(fh).cuda().to(cd)).cpu().numpy().astype(np.complex128)
+    return a, b
 
 
 def _data(seed, N, M, prec, clustered=False):
@@ -56,10 +62,14 @@ CASES = [
 @pytest.mark.parametrize("N,M,Zs", CASES)
 def test_ring_against_oracle(H, oracle_mod, N, M, Zs, prec):
     x, f = _data(900 + M + Zs, N, M, prec)
-    a = _adjoint(H, N, x, f, prec, (8, Zs, 512))
+    fh = W.complex_normal(int(np.prod(N)), W.rng(M + Zs)).reshape(N)
+    if prec == "f32":
+        fh = fh.astype(np.complex64).astype(np.complex128)
+    a, b = _adjoint(H, N, x, f, prec, (8, Zs, 512), fh=fh)
     err = oracle_mod.rel_l2(a, oracle_mod.ndft_adjoint(N, x, f))
-    print("ring N=%s M=%d Zs=%d %s: adjoint rel-l2 %.3e" % (N, M, Zs, prec, err))
-    assert err <= 1e-5
+    errb = oracle_mod.rel_l2(b, oracle_mod.ndft_forward(N, x, fh))
+    print("ring N=%s M=%d Zs=%d %s: adjoint rel-l2 %.3e forward %.3e" % (N, M, Zs, prec, err, errb))
+    assert err <= 1e-5 and errb <= 1e-5
 
 
 @pytest.mark.parametrize("prec,tol", [("f64", 1e-13), ("f32", 2e-6)])
@@ -68,11 +78,13 @@ def test_ring_matches_staged(H, prec, tol):
     sweep (Zs = 12): equal up to the order of the additions."""
     N, M = (20, 16, 24), 20000
     x, f = _data(77, N, M, prec)
-    ring = _adjoint(H, N, x, f, prec, (8, 16, 512))
-    staged = _adjoint(H, N, x, f, prec, (8, 12, 512))
+    fh = W.complex_normal(int(np.prod(N)), W.rng(78)).reshape(N)
+    ring, ringb = _adjoint(H, N, x, f, prec, (8, 16, 512), fh=fh)
+    staged, stagedb = _adjoint(H, N, x, f, prec, (8, 12, 512), fh=fh)
     d = np.linalg.norm(ring - staged) / np.linalg.norm(staged)
-    print("ring vs staged %s: %.3e" % (prec, d))
-    assert d <= tol
+    db = np.linalg.norm(ringb - stagedb) / np.linalg.norm(stagedb)
+    print("ring vs staged %s: adjoint %.3e forward %.3e" % (prec, d, db))
+    assert d <= tol and db <= tol
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
@@ -81,10 +93,14 @@ def test_ring_clustered(H, oracle_mod, prec):
     pairs are cut into ranges of blocks, so items start at blocks > 0."""
     N = (16, 16, 16)
     x, f = _data(31, N, 8000, prec, clustered=True)
-    a = _adjoint(H, N, x, f, prec, (8, 16, 512))
+    fh = W.complex_normal(int(np.prod(N)), W.rng(32)).reshape(N)
+    if prec == "f32":
+        fh = fh.astype(np.complex64).astype(np.complex128)
+    a, b = _adjoint(H, N, x, f, prec, (8, 16, 512), fh=fh)
     err = oracle_mod.rel_l2(a, oracle_mod.ndft_adjoint(N, x, f))
-    print("ring clustered %s: %.3e" % (prec, err))
-    assert err <= 1e-5
+    errb = oracle_mod.rel_l2(b, oracle_mod.ndft_forward(N, x, fh))
+    print("ring clustered %s: adjoint %.3e forward %.3e" % (prec, err, errb))
+    assert err <= 1e-5 and errb <= 1e-5
 
 
 def test_ring_edges_of_the_torus(H, oracle_mod):
@@ -95,9 +111,11 @@ def test_ring_edges_of_the_torus(H, oracle_mod):
     x = np.stack(np.meshgrid(grid[::3], grid[::5], grid[::2], indexing="ij"), -1).reshape(-1, 3)
     x = np.concatenate([x, np.array([[-0.5, -0.5, -0.5], [0.5 - 1e-13, 0.5 - 1e-13, -0.5]])])
     f = W.complex_normal(x.shape[0], g)
-    a = _adjoint(H, N, x, f, "f64", (8, 8, 512))
+    fh = W.complex_normal(int(np.prod(N)), g).reshape(N)
+    a, b = _adjoint(H, N, x, f, "f64", (8, 8, 512), fh=fh)
     err = oracle_mod.rel_l2(a, oracle_mod.ndft_adjoint(N, x, f))
-    assert err <= 1e-5
+    errb = oracle_mod.rel_l2(b, oracle_mod.ndft_forward(N, x, fh))
+    assert err <= 1e-5 and errb <= 1e-5
 
 
 def test_ring_batch_and_grad_plan(H, oracle_mod):
@@ -117,5 +135,11 @@ def test_ring_batch_and_grad_plan(H, oracle_mod):
         err = oracle_mod.rel_l2(out[fo:fo + nb], oracle_mod.ndft_adjoint(Ns[b], xs[b], fs[b]).reshape(-1))
         print("ring batch b=%d: %.3e" % (b, err))
         assert err <= 1e-5
+    fhs = [W.complex_normal(int(np.prod(Nb)), g) for Nb in Ns]
+    back = plan.forward(torch.from_numpy(np.concatenate(fhs)).cuda()).cpu().numpy()
+    for b in range(3):
+        po, _ = plan.offsets(b)
+        ref = oracle_mod.ndft_forward(Ns[b], xs[b], fhs[b].reshape(Ns[b]))
+        assert oracle_mod.rel_l2(back[po:po + Ms[b]], ref) <= 1e-5
     a = _adjoint(H, Ns[0], xs[0], fs[0], "f64", (8, 16, 512), with_grad=True)
     assert oracle_mod.rel_l2(a, oracle_mod.ndft_adjoint(Ns[0], xs[0], fs[0])) <= 1e-5
