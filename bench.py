@@ -99,7 +99,7 @@ def src_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel: str, prec: str):
+def measured_traffic(kernel: str, prec: str, m: int):
     """Bytes per launch from the committed rocprofv3 counter summary, if it was
     taken on the current kernel sources; else None."""
     path = os.path.join(ROOT, "profiles", "traffic_c2.json")
@@ -110,7 +110,7 @@ def measured_traffic(kernel: str, prec: str):
         return None
     if d.get("src_hash") != src_hash():
         return None
-    return d.get("kernels", {}).get("%s_%s" % (kernel, prec))
+    return d.get("kernels", {}).get("%s_%s_m%d" % (kernel, prec, m))
 
 
 COPY_BYTES = 1 << 30
@@ -158,20 +158,18 @@ def summarize_counters(fetch_dir: str, write_dir: str, out_json: str, command: s
     f_scale = known_kib / cf if cf else None
     w_scale = known_kib / cw if cw else None
     kern = {}
-    names = {"k_spread": "spread", "k_interp": "interp", "k_fft": "fft"}
+    import re
     for full in set(fetch) | set(write):
-        short = None
-        for key, label in names.items():
-            if key in full:
-                short = label
-        if short is None:
+        # the sweep kernels of the default line: the ring sweeps (2m = 8,
+        # m = 4) and the staged sweeps, whose second template argument is 2m
+        mt = re.match(r"(?:void )?hpnfft::k_(spread|interp)(_ring)?<(float|double)(?:, (\d+))?", full)
+        if not mt:
             continue
-        prec = "f32" if "<float" in full else "f64"
-        if short == "fft":
-            continue
+        m = 4 if mt.group(2) else int(mt.group(4)) // 2
+        prec = "f32" if mt.group(3) == "float" else "f64"
         fb = fetch.get(full, 0.0) * 1024.0 * (f_scale or 1.0)
         wb = write.get(full, 0.0) * 1024.0 * (w_scale or 1.0)
-        kern["%s_%s" % (short, prec)] = round(fb + wb)
+        kern["%s_%s_m%d" % (mt.group(1), prec, m)] = round(fb + wb)
     out = {"src_hash": src_hash(), "command": command, "copy_kernel_fetch": ck, "copy_kernel_write": wk,
            "fetch_scale": f_scale, "write_scale": w_scale, "kernels": kern,
            "raw_kib": {"fetch": fetch, "write": write}}
@@ -248,7 +246,7 @@ def summarize(res, prec, m, copy_gbs=None):
         ach, peak, unit = amount / per_s / 1e12, PEAK_TFLOPS[prec], "TFLOP/s"
     else:
         ach, peak, unit = amount / per_s / 1e9, PEAK_HBM_GBS, "GB/s"
-    traffic = measured_traffic(dom, prec)
+    traffic = measured_traffic(dom, prec, m)
     roof = {"bound": kind, "kernel": dom, "achieved": round(ach, 3), "peak": peak, "unit": unit,
             "frac": round(ach / peak, 4), "traffic": traffic}
     if kind == "alu":
