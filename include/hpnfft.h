@@ -23,6 +23,12 @@
  *   fhat   prod(N) complex, C order (last dimension fastest), frequency k_t
  *          stored at index k_t + N_t/2
  * Streams: all transform calls are asynchronous on the plan's HIP stream.
+ * A plan serves one call at a time: its workspace (the grid, the sorted
+ * values, the outputs) and the work-queue counters of its sweep kernels
+ * (which reset themselves at the end of each launch) assume that its
+ * launches run in stream order.  Calls on one plan from two streams, or the
+ * replay of its captured graph overlapping an eager call on another stream,
+ * race; use one plan per concurrent stream.
  * The library never allocates device memory: the caller provides one
  * workspace buffer of hpnfft_workspace_size() bytes.  The only allocation
  * is 64 bytes of pinned host memory per plan (at its first set_points), the
@@ -168,8 +174,9 @@ int hpnfft_set_workspace(hpnfft_plan plan, void *dev_ptr, size_t bytes);
  * and tabulates the window values (the paper's CUNFFT evaluates the window on
  * the fly, Section 1; here it is tabulated once per point set because the
  * same points serve adjoint, forward and gradient).  The caller may free x
- * afterwards.  Waits once for the plan's stream (polling the readback of
- * its status words), to check the domain: returns EDOMAIN if any coordinate
+ * afterwards.  Waits once for the plan's stream (the calling thread polls
+ * the readback of the status words, keeping one host core busy until the
+ * binning kernels are done), to check the domain: returns EDOMAIN if any coordinate
  * is outside [-1/2,1/2) or not finite, and the plan then has no points.
  * ESTATE if no workspace is attached. */
 int hpnfft_set_points(hpnfft_plan plan, const double *x);

@@ -367,10 +367,10 @@ long long box_max_cells(const hpnfft_plan_s *p, Tiling t)
 // faster; at 0.01 (the 24^3-cell Ewald lattice on a 256^3 grid) the boxes
 // are 2.2x (float64) and 1.3x (float32) faster.  The 256-transform float32
 // batch (0.0001 - 4 points per cell per transform) runs fastest with the
-// float32 switch at 0.05 (29.0 ms; 31.3 at 0.005, 32.6 at 0.1, 38.9 all
-// lines).
+// float32 switch at 0.02 now that its dense transforms take the 2m = 8 ring
+// sweeps (25.05 ms; 25.8 at 0.05, 26.0 at 0.01, 27.2 at 0.005).
 constexpr double kBoxDensityF64 = 0.1;
-constexpr double kBoxDensityF32 = 0.05;
+constexpr double kBoxDensityF32 = 0.02;
 // The method of every transform (a batch may mix them: sparse transforms
 // take boxes, dense ones the line sweeps).
 void choose_methods(hpnfft_plan_s *p)
