@@ -511,6 +511,59 @@ def bench_c5(H, torch, W, args, summary=False):
     }
 
 
+def bench_c5sweep(H, torch, W, args, summary=False):
+    """The differentiation workload over its lattice and grid sizes: fluorite
+    L^3 cells (L = 4, 8, 12, 16, 24: 768 to 165,888 ions, displacements std
+    0.01 r0) on N^3 grids (N = 64, 128, 256), float64 m=8 and float32 m=4,
+    default tilings; step = set_points + adjoint + Eq. (12) energy + backward
+    (forces)."""
+    import numpy as np
+    from paper_2001_01583_amd import ewald as E
+    dev = torch.device("cuda", 0)
+    steps = max(3, min(args.steps, 10))
+    rows = []
+    for cells in (4, 8, 12, 16, 24):
+        r_np, q_np, L_box = W.fluorite(cells, 0.01, seed=5)
+        r = torch.from_numpy(r_np).to(dev)
+        q = torch.from_numpy(q_np).to(dev)
+        for Nn in (64, 128, 256):
+            lo, hi = E.alpha_window(L_box, Nn)
+            alpha = 0.5 * (lo + hi)
+            row = {"cells": cells, "ions": int(r.shape[0]), "N": Nn, "alpha": round(alpha, 6)}
+            forces = {}
+            for prec, m in (("f64", 8), ("f32", 4)):
+                ew = E.Ewald(r.shape[0], L_box, alpha, N=(Nn, Nn, Nn), m=m, precision=prec, device=dev,
+                             method=args.method)
+                t = _time(torch, lambda: ew.reciprocal(r, q, forces=True), steps, 1)
+                U, F = ew.reciprocal(r, q, forces=True)
+                torch.cuda.synchronize()
+                row["%s_m%d_ms" % (prec, m)] = round(t * 1e3, 4)
+                row["%s_energy" % prec] = float(U)
+                row["%s_method" % prec] = ew.plan.method
+                forces[prec] = F.cpu().numpy()
+                del ew
+                torch.cuda.empty_cache()
+            row["energy_f32_vs_f64_rel"] = float("%.3e" % abs((row["f32_energy"] - row["f64_energy"]) /
+                                                              row["f64_energy"]))
+            row["forces_f32_vs_f64_max_rel"] = float("%.3e" % (np.abs(forces["f32"] - forces["f64"]).max() /
+                                                              np.abs(forces["f64"]).max()))
+            log("c5 sweep %d^3 cells N=%d: f64 %.3f ms, f32 %.3f ms" % (cells, Nn, row["f64_m8_ms"],
+                                                                        row["f32_m4_ms"]))
+            rows.append(row)
+    if summary:
+        return {"workload": "Ewald reciprocal energy + forces over L = 4..24 cells and N = 64..256", "rows": rows}
+    last = [rw for rw in rows if rw["cells"] == 24 and rw["N"] == 128][0]
+    return {
+        "metric": METRIC, "value": round(last["ions"] / (last["f64_m8_ms"] * 1e-3), 1), "unit": "ions/s",
+        "n_gpus": 1, "steps": steps, "warmup": 1, "ms_per_step": last["f64_m8_ms"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "Ewald reciprocal energy + forces, fluorite L^3 cells (L = 4, 8, 12, 16, 24, "
+                               "displacement std 0.01 r0) on N^3 grids (N = 64, 128, 256), float64 m=8 and "
+                               "float32 m=4, default tilings; value: L = 24, N = 128, float64"},
+        "rows": rows,
+    }
+
+
 def bench_enuf(H, torch, W, args, summary=False):
     """Full Ewald (HP-ENUF) step on fluorite lattices of the paper's timing
     sweep, 12 * c^3 ions for c = 32, 45, 56, 64 (393,216 .. 3,145,728 ions):
@@ -588,9 +641,10 @@ def main():
                     help="sweep method of the spread and interpolation (default: the library's choice)")
     ap.add_argument("--enuf-cells", default="32,45,56,64",
                     help="lattice sizes (cells per edge) of the enuf workload")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5", "enuf"],
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5", "c5sweep", "enuf"],
                     help="c2 (default): N=64^3, M=2^20, set_points+adjoint+forward; c3: precision N=128^3, "
-                         "M=2^23; c4: 256-transform batch; c5: Ewald forces, 165,888 ions")
+                         "M=2^23; c4: 256-transform batch; c5: Ewald forces, 165,888 ions; c5sweep: Ewald "
+                         "forces over L = 4..24 cells and N = 64..256; enuf: full Ewald ion sweep")
     args = ap.parse_args()
     if args.summarize_counters:
         summarize_counters(args.summarize_counters[0], args.summarize_counters[1],
@@ -618,7 +672,8 @@ def main():
         import tempfile
         os.environ["HPNFFT_TUNE_CACHE"] = os.path.join(tempfile.mkdtemp(prefix="hpnfft_"), "tune.json")
     if args.workload != "c2":
-        fn = {"c3": bench_c3, "c4": bench_c4, "c5": bench_c5, "enuf": bench_enuf}[args.workload]
+        fn = {"c3": bench_c3, "c4": bench_c4, "c5": bench_c5, "c5sweep": bench_c5sweep,
+              "enuf": bench_enuf}[args.workload]
         print(json.dumps(fn(H, torch, W, args)), flush=True)
         return
     data = W.c2()
