@@ -46,8 +46,9 @@ struct SItem {
 // bins covers cells [box_lo(i), box_lo(i + 1)); box_of inverts it.  Every
 // bin is at least m cells wide, so a window reaches only the bins next to its
 // own; an output box is a block of gbox consecutive bins per dim.
-__host__ __device__ inline int box_lo(int i, int n, int nb) { return (int)(((long long)i * n) / nb); }
-__host__ __device__ inline int box_of(int c, int n, int nb) { return (int)(((long long)(c + 1) * nb - 1) / n); }
+// (products below 1024 * 1024: grid edges and bin counts are at most kMaxN)
+__host__ __device__ inline int box_lo(int i, int n, int nb) { return (int)((unsigned)(i * n) / (unsigned)nb); }
+__host__ __device__ inline int box_of(int c, int n, int nb) { return (int)((unsigned)((c + 1) * nb - 1) / (unsigned)n); }
 __host__ __device__ inline int box_key(const int c[3], const int n[3], const int nb[3])
 {
     return (box_of(c[0], n[0], nb[0]) * nb[1] + box_of(c[1], n[1], nb[1])) * nb[2] + box_of(c[2], n[2], nb[2]);

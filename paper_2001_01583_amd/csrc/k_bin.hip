@@ -19,11 +19,9 @@
 
 namespace hpnfft {
 
-__device__ inline int wrap_cell(int c, int n)
-{
-    c %= n;
-    return c < 0 ? c + n : c;
-}
+// floor(x n) for x in [-1/2, 1/2) lies in [-n/2, n/2]: one conditional add
+// brings it to its storage index in [0, n)
+__device__ inline int wrap_cell(int c, int n) { return c < 0 ? c + n : c; }
 
 // Cell (storage index in [0, n)) and offset u in [0, 1) of one coordinate;
 // sets *bad for a coordinate outside [-1/2, 1/2) or not finite.
@@ -39,12 +37,30 @@ __device__ inline int cell_of(double xv, int n, double *u, bool *bad)
     return wrap_cell((int)fl, n);
 }
 
+// c / T and c % T for the tile edge T: a shift and a mask when T is a power
+// of two (T is the same for every thread, so the branch is uniform)
+__device__ inline void tile_split(int c, int T, int *q, int *r)
+{
+    if ((T & (T - 1)) == 0) {
+        const int sh = __ffs(T) - 1;
+        *q = c >> sh;
+        *r = c & (T - 1);
+    } else {
+        *q = c / T;
+        *r = c - *q * T;
+    }
+}
+
+// BW is 1 or 8 (block_w) and divides T
 __device__ inline int sort_key(const int c[3], int T, int ntx, int n0, int BW)
 {
-    const int tile = (c[1] / T) * ntx + (c[2] / T);
-    const int lx = c[2] % T;
-    const int block = tile * (T * T / BW) + (c[1] % T) * (T / BW) + lx / BW;
-    return (block * n0 + c[0]) * BW + lx % BW;
+    int q1, r1, q2, r2;
+    tile_split(c[1], T, &q1, &r1);
+    tile_split(c[2], T, &q2, &r2);
+    const int bsh = BW == 8 ? 3 : 0;
+    const int tile = q1 * ntx + q2;
+    const int block = tile * ((T * T) >> bsh) + r1 * (T >> bsh) + (r2 >> bsh);
+    return (block * n0 + c[0]) * BW + (r2 & (BW - 1));
 }
 
 // Count pass: cell and sort key of every point, its rank among the points of
@@ -211,7 +227,7 @@ __global__ __launch_bounds__(256) void k_bin_scatter(const double *__restrict__ 
     // j) mod 2m for the point's line j in its block, so that the lane of
     // block column x (which receives tap (x - j) mod 2m) reads a fixed slot
     if (block_w(M2) > 1 && !nb0) {
-        const int jl = (c[2] % T) % block_w(M2);
+        const int jl = c[2] & (block_w(M2) - 1);  // (c2 mod T) mod BW, BW dividing T
 #pragma unroll
         for (int k = 1; k < M2; k <<= 1) {
             if (jl & k) {
@@ -231,7 +247,7 @@ __global__ __launch_bounds__(256) void k_bin_scatter(const double *__restrict__ 
     }
     store_block<NW * sizeof(R)>(rp, w);
     *reinterpret_cast<int2 *>(rp + rec_off_pz(M2, sizeof(R))) =
-        nb0 ? make_int2(c[0], (c[1] << kBoxCellBits) | c[2]) : make_int2(c[0], (c[2] % T) % block_w(M2));
+        nb0 ? make_int2(c[0], (c[1] << kBoxCellBits) | c[2]) : make_int2(c[0], c[2] & (block_w(M2) - 1));
     if constexpr (GRAD) store_block<NW * sizeof(R)>(rp + rec_prefix(M2, sizeof(R)), dw);
 }
 
