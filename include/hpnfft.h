@@ -157,7 +157,13 @@ int hpnfft_get_method(hpnfft_plan plan, int *method);
  * dims 1, 2 and in dim 0; threads is not used (512).
  * Must be called before hpnfft_set_workspace.  EINVAL if the tile does not
  * fit the 160 KiB local data share, or if 2m = 8 and the tile edge is not a
- * multiple of 8 (those plans sort points in blocks of 8 lines). */
+ * multiple of 8 (those plans sort points in blocks of 8 lines).
+ * With 2m = 8, a tile edge of 8 and a slab depth that is a multiple of 8
+ * (the default: 8, 32), and every line-method grid's n0 a multiple of 8, the
+ * spread and the interpolation run as ring sweeps (one wavefront per block
+ * of 8 lines through the whole slab; environment variable HPNFFT_RING=0
+ * selects the staged sweeps instead); threads is then 512 whatever is
+ * passed. */
 int hpnfft_set_tiles(hpnfft_plan plan, int tile, int slab, int threads);
 int hpnfft_get_tiles(hpnfft_plan plan, int *tile, int *slab, int *threads);
 
