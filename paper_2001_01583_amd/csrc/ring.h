@@ -1,5 +1,6 @@
-// Ring sweep of the spread (the Spreading step of Algorithm 2, Section 3)
-// for windows of 2m = 8 cells, the blocked-line layout of sweep.h.
+// Ring sweeps for windows of 2m = 8 cells, on the blocked-line layout of
+// sweep.h: the spread (the Spreading step of Algorithm 2, Section 3) here,
+// the interpolation (the Interpolating step of Algorithm 5) below.
 //
 // A work item is a tile of 8 x 8 z-lines (eight blocks of 8 lines, one per
 // tile row) restricted to a slab of Zs planes along dim 0.  Each wavefront
