@@ -1,6 +1,7 @@
 // Spread and interpolation launchers for windows of 2m <= 16 cells (m <= 8);
 // wider windows (m = 9 .. 15) are instantiated in k_spread_wide.hip.  The
 // kernels themselves are in sweep.h.
+#include "lines.h"
 #include "ring.h"
 
 namespace hpnfft {
@@ -61,6 +62,23 @@ hipError_t launch_interp(int m, bool grad, const Xform *dxf, const SItem *items,
 #undef HPNFFT_INTERP_CASE
 }
 
+template <typename R>
+hipError_t launch_interp_lines(int m, const Xform *xf, const int n[3], int *queue, int T, const unsigned char *rec,
+                               size_t rec_bytes, const int *cs, R *outs, hipStream_t s)
+{
+    switch (m) {
+    case 5: return interp_lines_m<R, 10>(xf, n, queue, T, rec, rec_bytes, cs, outs, s);
+    case 6: return interp_lines_m<R, 12>(xf, n, queue, T, rec, rec_bytes, cs, outs, s);
+    case 7: return interp_lines_m<R, 14>(xf, n, queue, T, rec, rec_bytes, cs, outs, s);
+    case 8: return interp_lines_m<R, 16>(xf, n, queue, T, rec, rec_bytes, cs, outs, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template hipError_t launch_interp_lines<double>(int, const Xform *, const int *, int *, int, const unsigned char *,
+                                                size_t, const int *, double *, hipStream_t);
+template hipError_t launch_interp_lines<float>(int, const Xform *, const int *, int *, int, const unsigned char *,
+                                               size_t, const int *, float *, hipStream_t);
 template hipError_t launch_spread<double>(int, const Xform *, const SItem *, int, int *, Tiling,
                                           const unsigned char *, size_t, const double *, const int *, hipStream_t);
 template hipError_t launch_spread<float>(int, const Xform *, const SItem *, int, int *, Tiling,

@@ -1,0 +1,290 @@
+// Interpolation by groups of single z-lines (the Interpolating step of
+// Algorithm 5, Section 3) for windows of 2m = 10 .. 16 cells.
+//
+// A work item is a group of 2 x 2 neighbouring z-lines and a slab of Zi
+// planes along dim 0 (a multiple of 2m).  Each point is evaluated once, by
+// the slab that holds its first tap plane.  A line's (2m)^2 tap rows are
+// spread over NRG wavefronts of 64 lanes (lane <-> one (dy, dx) row), and
+// each wavefront owns one (line, row group) for the whole slab: its register
+// window of 2m complex values along dim 0 carries from plane to plane.  The
+// planes reach the window through an LDS ring that holds one phase of 2m
+// planes of the group's (2m + 1)^2-cell footprint: per phase all threads
+// store the phase's planes (read from the grid into registers while the
+// previous phase was swept), and after a barrier each wavefront takes one
+// step per plane q: plane q enters slot q mod 2m, then the points whose
+// window starts at q - 2m + 1 are evaluated.  The per-lane partials of
+// consecutive points go through the halving steps of wave_reduce.h, and
+// every 64 points each lane adds one point's row-group sum to the output
+// (NRG adds per point, so the output is cleared first).
+//
+// Against the staged sweep this drops the z-halo (a point is evaluated once
+// instead of by both slabs its window reaches), the record staging and its
+// barriers, and the LDS tile of the slab: the per-point values the lanes
+// share come through scalar loads straight from the records.
+#pragma once
+
+#include "sweep.h"
+
+namespace hpnfft {
+
+constexpr int kLineGroup = 2;  // lines per group along dims 1 and 2
+constexpr int kLinesZ = 64;    // slab depth target (planes), rounded down to a multiple of 2m
+
+template <int M2> constexpr int lines_nrg() { return (M2 * M2 + 63) / 64; }
+template <int M2> constexpr int lines_threads() { return kLineGroup * kLineGroup * lines_nrg<M2>() * 64; }
+template <int M2> constexpr int lines_pp() { return M2 + kLineGroup - 1; }
+template <int M2, typename R> constexpr size_t lines_lds()
+{
+    return (size_t)M2 * lines_pp<M2>() * lines_pp<M2>() * 2 * sizeof(R);
+}
+__host__ __device__ constexpr int lines_slab(int M2) { return (kLinesZ / M2) * M2; }
+
+template <typename R, int M2>
+__global__ __launch_bounds__(lines_threads<M2>()) void k_interp_lines(
+    const Xform *__restrict__ xf, int nitems, int *__restrict__ queue, int T, const unsigned char *__restrict__ rec,
+    int rbytes, const int *__restrict__ cell_start, R *__restrict__ outs)
+{
+    constexpr int m = M2 / 2;
+    constexpr int NRG = lines_nrg<M2>();
+    constexpr int PP = lines_pp<M2>();
+    constexpr int PLANE = PP * PP;
+    constexpr int NTH = lines_threads<M2>();
+    constexpr int NPF = (M2 * PLANE + NTH - 1) / NTH;  // ring cells per thread and phase
+    constexpr int OFF_PZ = (int)rec_off_pz(M2, sizeof(R));
+    constexpr int Zi = lines_slab(M2);
+    // the next phase's ring cells load into registers during the sweep,
+    // except where the float64 window leaves no registers for them
+    constexpr bool PREF = sizeof(R) == 4 || M2 <= 12;
+    // likewise the next point's record loads while the current one is
+    // evaluated, except for the widest float64 windows
+    constexpr bool PFP = sizeof(R) == 4 || M2 <= 12;
+    extern __shared__ uint4 smem16[];
+    R *ring = reinterpret_cast<R *>(smem16);  // [slot][footprint row][column] complex
+    __shared__ int s_item;
+    const int tid = threadIdx.x, lane = tid & 63, wave = uni(tid >> 6);
+    const int line = wave / NRG, rg = wave - line * NRG;
+    const int ly = line / kLineGroup, lx = line % kLineGroup;
+    const int row = rg * 64 + lane;
+    const bool active = row < M2 * M2;
+    const int dy = active ? row / M2 : 0, dx = active ? row % M2 : 0;
+    const int cell = (ly + dy) * PP + lx + dx;  // lane's cell in a ring plane
+    // batch position whose sum this lane receives (see halve8_sum)
+    const int j8 = lane >> 3;
+    const int own = (lane & 7) * 8 + (((j8 & 1) << 2) | (j8 & 2) | (j8 >> 2));
+
+    const int n0 = xf->n[0], n1 = xf->n[1], n2 = xf->n[2];
+    const int ntx = xf->ntx;
+    const int ngx = (n2 + kLineGroup - 1) / kLineGroup, ngy = (n1 + kLineGroup - 1) / kLineGroup;
+    const long long poff = xf->poff;
+    const int Mx = (int)xf->M;
+    const unsigned char *recb = rec + (size_t)poff * rbytes;
+    const gptr<const R> grid = as_global(reinterpret_cast<const R *>(xf->grid));
+    const size_t pstride = (size_t)n1 * n2;
+
+    struct PointData {
+        R wz[M2];
+        R wy, wx;
+    };
+    auto fetch = [&](const unsigned char *rp, PointData &d) __attribute__((always_inline)) {
+        const cptr<R> pc = as_const(reinterpret_cast<const R *>(rp));
+#pragma unroll
+        for (int s = 0; s < M2; ++s) d.wz[s] = pc[s];
+        const R *ps = reinterpret_cast<const R *>(rp);
+        d.wy = ps[M2 + dy];
+        d.wx = ps[2 * M2 + dx];
+    };
+
+    for (int it = next_item(queue, &s_item); it < nitems; it = next_item(queue, &s_item)) {
+        const int gx = it % ngx, r0 = it / ngx;
+        const int gy = r0 % ngy, sl = r0 / ngy;
+        const int z0 = sl * Zi, zs = min(Zi, n0 - z0);
+        const int Y0 = gy * kLineGroup, X0 = gx * kLineGroup;
+        const int y = Y0 + ly, x = X0 + lx;
+        const bool mine = y < n1 && x < n2;
+        // the line's points by plane: key (tile, row and column in the
+        // tile, plane) of the counting sort, whose tiles have edge T
+        const int q1 = y / T, q2 = x / T;
+        const int key_line = ((q1 * ntx + q2) * T + (y - q1 * T)) * T + (x - q2 * T);
+        const int *cs = cell_start + xf->key_off + (long long)key_line * n0;
+        auto plane_c = [&](int b) __attribute__((always_inline)) {
+            int c = b + (m - 1) + z0;  // within [m - 1, 2 n0)
+            c -= c >= n0 ? n0 : 0;
+            return c;
+        };
+
+        PointData cur{};
+        int cidx = -1;
+        const unsigned char *rcur = recb;
+        R gr[M2], gi[M2];
+
+        // halving-step state: partials of the open pair, quad and octet
+        R s0r = 0, s0i = 0, s1r = 0, s1i = 0, s2r = 0, s2i = 0, orr = 0, ori = 0;
+        int t = 0;    // position of the next point in the batch of 64
+        int bsp = 0;  // lane t: sorted index of batch point t
+        auto feed = [&](R vr, R vi) __attribute__((always_inline)) {
+            if (!(t & 1)) {
+                s0r = vr;
+                s0i = vi;
+            } else {
+                vr = halve32(s0r, vr);
+                vi = halve32(s0i, vi);
+                if (!(t & 2)) {
+                    s1r = vr;
+                    s1i = vi;
+                } else {
+                    vr = halve16(s1r, vr);
+                    vi = halve16(s1i, vi);
+                    if (!(t & 4)) {
+                        s2r = vr;
+                        s2i = vi;
+                    } else {
+                        const R tr = halve8_sum(s2r, vr), ti = halve8_sum(s2i, vi);
+                        if ((lane & 7) == (t >> 3)) {
+                            orr += tr;
+                            ori += ti;
+                        }
+                    }
+                }
+            }
+            ++t;
+        };
+        // every lane that holds the row-group sum of a point adds it to the
+        // point's output (positions padded with zeros hold no point)
+        auto drain = [&]() __attribute__((always_inline)) {
+            const int count = t;
+            while (t & 7) feed(R(0), R(0));
+            const int sp_own = __builtin_amdgcn_ds_bpermute(own << 2, bsp);
+            if (own < count) {
+                __hip_atomic_fetch_add(&outs[(size_t)sp_own * 2], orr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_fetch_add(&outs[(size_t)sp_own * 2 + 1], ori, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+            }
+            orr = ori = R(0);
+            t = 0;
+        };
+
+        int na = 0, nb = 0;  // sorted range of the next base plane, one step ahead
+        if (mine) {
+            const int c = plane_c(0);
+            na = cs[c];
+            nb = cs[c + 1];
+        }
+        const int zr = zs + M2 - 1;  // window planes of the slab's points
+        // step q: plane q (slot k = q mod 2m) enters from the ring (planes
+        // past the windows hold zeros); then the points whose window starts
+        // at q - 2m + 1
+        auto step = [&](const int k, const int q) __attribute__((always_inline)) {
+            {
+                const int o = (k * PLANE + cell) * 2;
+                gr[k] = ring[o];
+                gi[k] = ring[o + 1];
+            }
+            const int b = q - (M2 - 1);
+            if (b >= 0 && b < zs) {
+                const int pa = uni(na), pb = uni(nb);
+                const int c = plane_c(b + 1);
+                na = cs[c];
+                nb = cs[c + 1];
+                for (int sp = pa; sp < pb; ++sp) {
+                    if (!PFP || sp != cidx) {
+                        rcur = recb + (size_t)sp * rbytes;
+                        fetch(rcur, cur);
+                    }
+                    const bool adv = sp + 1 < Mx;
+                    const unsigned char *rnx = adv ? rcur + rbytes : rcur;
+                    PointData nxt;
+                    if constexpr (PFP) fetch(rnx, nxt);
+                    R ar = 0, ai = 0;
+#pragma unroll
+                    for (int s = 0; s < M2; ++s) {
+                        ar = fma(gr[s], cur.wz[s], ar);
+                        ai = fma(gi[s], cur.wz[s], ai);
+                    }
+                    const R w12 = active ? cur.wy * cur.wx : R(0);
+                    bsp = lane == t ? (int)(poff + sp) : bsp;
+                    feed(ar * w12, ai * w12);
+                    if (t == 64) drain();
+                    if constexpr (PFP) {
+                        cur = nxt;
+                        cidx = adv ? sp + 1 : sp;
+                        rcur = rnx;
+                    }
+                }
+            }
+        };
+
+        // ring cells of a phase, read from the grid (one phase ahead with PREF)
+        R pr[NPF], pim[NPF];
+        auto ring_fetch = [&](int ph) __attribute__((always_inline)) {
+#pragma unroll
+            for (int u = 0; u < NPF; ++u) {
+                const int e = tid + u * NTH;
+                const int zz = e / PLANE, c = e - zz * PLANE;
+                const int q = ph * M2 + zz;
+                pr[u] = pim[u] = R(0);
+                if (e < M2 * PLANE && q < zr) {
+                    const int fy = c / PP, fx = c - fy * PP;
+                    int gz = z0 + q;  // below 2 n0
+                    gz -= gz >= n0 ? n0 : 0;
+                    int gyy = Y0 + fy - (m - 1), gxx = X0 + fx - (m - 1);
+                    gyy += gyy < 0 ? n1 : 0;
+                    gyy -= gyy >= n1 ? n1 : 0;
+                    gyy -= gyy >= n1 ? n1 : 0;
+                    gxx += gxx < 0 ? n2 : 0;
+                    gxx -= gxx >= n2 ? n2 : 0;
+                    gxx -= gxx >= n2 ? n2 : 0;
+                    const size_t gidx = ((size_t)gz * pstride + (size_t)gyy * n2 + gxx) * 2;
+                    pr[u] = grid[gidx];
+                    pim[u] = grid[gidx + 1];
+                }
+            }
+        };
+
+        const int nph = (zr + M2 - 1) / M2;
+        if constexpr (PREF) ring_fetch(0);
+        for (int ph = 0; ph < nph; ++ph) {
+            if (ph > 0) __syncthreads();  // the previous phase's steps have read the ring
+            if constexpr (!PREF) ring_fetch(ph);
+#pragma unroll
+            for (int u = 0; u < NPF; ++u) {
+                const int e = tid + u * NTH;
+                if (e < M2 * PLANE) {
+                    ring[2 * e] = pr[u];
+                    ring[2 * e + 1] = pim[u];
+                }
+            }
+            __syncthreads();
+            if constexpr (PREF) {
+                if (ph + 1 < nph) ring_fetch(ph + 1);
+            }
+            if (mine) {
+#pragma unroll
+                for (int k = 0; k < M2; ++k) step(k, ph * M2 + k);
+            }
+        }
+        if (mine && t > 0) drain();
+    }
+    release_queue(queue);
+}
+
+// One launch per transform (the items of a transform are its line groups
+// times its slabs).  xf: the transform's device descriptor; n: its grid
+// edges on the host.
+template <typename R, int M2>
+static hipError_t interp_lines_m(const Xform *xf, const int n[3], int *queue, int T, const unsigned char *rec,
+                                 size_t rec_bytes, const int *cs, R *outs, hipStream_t s)
+{
+    const int nsl = (n[0] + lines_slab(M2) - 1) / lines_slab(M2);
+    const int nitems = nsl * ((n[1] + kLineGroup - 1) / kLineGroup) * ((n[2] + kLineGroup - 1) / kLineGroup);
+    constexpr size_t lds = lines_lds<M2, R>();
+    auto kern = k_interp_lines<R, M2>;
+    hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    const int grid = std::min(cu_count(), nitems);
+    if (grid < 1) return hipSuccess;
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(lines_threads<M2>()), lds, s, xf, nitems, queue, T, rec,
+                       (int)rec_bytes, cs, outs);
+    return hipGetLastError();
+}
+
+}  // namespace hpnfft

@@ -418,6 +418,23 @@ bool use_ring(const hpnfft_plan_s *p, const Tiling &t)
     return true;
 }
 
+// Whether the forward's interpolation runs by groups of single lines
+// (lines.h): windows of 2m = 10 .. 16 cells, every line-method transform with
+// n0 a multiple of 2m (HPNFFT_LINES=0 turns it off).
+bool use_lines(const hpnfft_plan_s *p)
+{
+    static int on = -1;
+    if (on < 0) {
+        const char *e = getenv("HPNFFT_LINES");
+        on = (e && e[0] == '0') ? 0 : 1;
+    }
+    const int M2 = p->M2();
+    if (!on || p->det() || M2 < 10 || M2 > 16) return false;
+    for (size_t b = 0; b < p->hx.size(); ++b)
+        if (!p->tbox[b] && p->hx[b].n[0] % M2) return false;
+    return true;
+}
+
 bool tiling_fits(const hpnfft_plan_s *p, Tiling t)
 {
     if (t.T < 4 || t.T > 32 || t.Zs < 2 || t.Zs > 64) return false;
@@ -992,7 +1009,13 @@ template <typename R> int run_forward(hpnfft_plan_s *p, const void *fhat, void *
             HCHECK(launch_interp_box<R>(p->m, false, dxf, p->at<SItem>(L.bitems), p->nbitems,
                                         p->at<int>(L.counters) + 1, p->max_cells, p->at<unsigned char>(L.rec),
                                         L.rec_bytes, p->at<int>(L.cell_start), p->at<R>(L.outs), s));
-        if (p->any_lines) {
+        if (p->any_lines && use_lines(p)) {
+            for (size_t b = 0; b < p->hx.size(); ++b)
+                if (!p->tbox[b])
+                    HCHECK(launch_interp_lines<R>(p->m, dxf + b, p->hx[b].n, p->at<int>(L.counters) + 1, p->til.T,
+                                                  p->at<unsigned char>(L.rec), L.rec_bytes,
+                                                  p->at<int>(L.cell_start), p->at<R>(L.outs), s));
+        } else if (p->any_lines) {
             Tiling t = p->til;
             t.ring = use_ring(p, t);
             HCHECK(launch_interp<R>(p->m, false, dxf, p->at<SItem>(L.items), p->nitems,
