@@ -163,11 +163,13 @@ __global__ __launch_bounds__(lines_threads<M2>()) void k_interp_lines(
             t = 0;
         };
 
-        int na = 0, nb = 0;  // sorted range of the next base plane, one step ahead
-        if (mine) {
-            const int c = plane_c(0);
-            na = cs[c];
-            nb = cs[c + 1];
+        // sorted point range of base plane b (b < zs <= 64) in lane b: read
+        // with lane reads at the steps, so that the steps wait on no load
+        int rlo = 0, rhi = 0;
+        if (mine && lane < zs) {
+            const int c = plane_c(lane);
+            rlo = cs[c];
+            rhi = cs[c + 1];
         }
         const int zr = zs + M2 - 1;  // window planes of the slab's points
         // step q: plane q (slot k = q mod 2m) enters from the ring (planes
@@ -181,10 +183,7 @@ __global__ __launch_bounds__(lines_threads<M2>()) void k_interp_lines(
             }
             const int b = q - (M2 - 1);
             if (b >= 0 && b < zs) {
-                const int pa = uni(na), pb = uni(nb);
-                const int c = plane_c(b + 1);
-                na = cs[c];
-                nb = cs[c + 1];
+                const int pa = __builtin_amdgcn_readlane(rlo, b), pb = __builtin_amdgcn_readlane(rhi, b);
                 for (int sp = pa; sp < pb; ++sp) {
                     if (!PFP || sp != cidx) {
                         rcur = recb + (size_t)sp * rbytes;

@@ -420,7 +420,7 @@ bool use_ring(const hpnfft_plan_s *p, const Tiling &t)
 
 // Whether the forward's interpolation runs by groups of single lines
 // (lines.h): windows of 2m = 10 .. 16 cells, every line-method transform with
-// n0 a multiple of 2m (HPNFFT_LINES=0 turns it off).
+// n0 a multiple of 2m (HPNFFT_LINES=0 selects the staged sweep).
 bool use_lines(const hpnfft_plan_s *p)
 {
     static int on = -1;

@@ -62,11 +62,17 @@ CASES = [
 def test_lines_against_oracle(H, oracle_mod, N, M, m, prec):
     g = W.rng(1300 + M + m)
     x = W.uniform_points(M, 3, g)
+    f = W.complex_normal(M, g)
+    if prec == "f32":
+        f = f.astype(np.complex64).astype(np.complex128)
     fh = _fh(1400 + m, N, prec)
-    _, out = _forward(H, N, x, fh, m, prec)
+    plan, out = _forward(H, N, x, fh, m, prec)
     err = oracle_mod.rel_l2(out, oracle_mod.ndft_forward(N, x, fh))
-    print("lines N=%s M=%d m=%d %s: forward rel-l2 %.3e" % (N, M, m, prec, err))
-    assert err <= (TOL64[m] if prec == "f64" else TOL32)
+    a = plan.adjoint(torch.from_numpy(f).cuda().to(plan.cdtype)).cpu().numpy().astype(np.complex128)
+    erra = oracle_mod.rel_l2(a, oracle_mod.ndft_adjoint(N, x, f))
+    print("lines N=%s M=%d m=%d %s: forward rel-l2 %.3e adjoint %.3e" % (N, M, m, prec, err, erra))
+    tol = TOL64[m] if prec == "f64" else TOL32
+    assert err <= tol and erra <= tol
 
 
 def test_lines_sigma(H, oracle_mod):
