@@ -1,14 +1,15 @@
 // Interpolation by groups of single z-lines (the Interpolating step of
 // Algorithm 5, Section 3) for windows of 2m = 10 .. 16 cells.
 //
-// A work item is a group of 2 x 2 neighbouring z-lines and a slab of Zi
-// planes along dim 0 (a multiple of 2m).  Each point is evaluated once, by
+// A work item is a group of neighbouring z-lines (2 x 2, or a row of three
+// for the widest float64 windows) and a slab of Zi planes along dim 0 (a
+// multiple of 2m).  Each point is evaluated once, by
 // the slab that holds its first tap plane.  A line's (2m)^2 tap rows are
 // spread over NRG wavefronts of 64 lanes (lane <-> one (dy, dx) row), and
 // each wavefront owns one (line, row group) for the whole slab: its register
 // window of 2m complex values along dim 0 carries from plane to plane.  The
 // planes reach the window through an LDS ring that holds one phase of 2m
-// planes of the group's (2m + 1)^2-cell footprint: per phase all threads
+// planes of the group's footprint ((2m + 1)^2 or 2m (2m + 2) cells): per phase all threads
 // store the phase's planes (read from the grid into registers while the
 // previous phase was swept), and after a barrier each wavefront takes one
 // step per plane q: plane q enters slot q mod 2m, then the points whose
@@ -27,54 +28,54 @@
 
 namespace hpnfft {
 
-constexpr int kLineGroup = 2;  // lines per group along dims 1 and 2
-constexpr int kLinesZ = 64;    // slab depth target (planes), rounded down to a multiple of 2m
+constexpr int kLinesZ = 64;  // slab depth target (planes), rounded down to a multiple of 2m
 
 template <int M2> constexpr int lines_nrg() { return (M2 * M2 + 63) / 64; }
-template <int M2> constexpr int lines_threads() { return kLineGroup * kLineGroup * lines_nrg<M2>() * 64; }
-template <int M2> constexpr int lines_pp() { return M2 + kLineGroup - 1; }
-template <int M2, typename R> constexpr size_t lines_lds()
-{
-    return (size_t)M2 * lines_pp<M2>() * lines_pp<M2>() * 2 * sizeof(R);
-}
+// Lines per group along dims 1 (GY) and 2 (GX).  2 x 2 in general; a row of
+// three lines for float64 windows of 2m >= 14, whose 2m-slot float64 window
+// takes 4 * 2m registers per lane: twelve wavefronts per workgroup leave 168
+// registers per lane, enough to keep the next point's and the next phase's
+// loads in flight.
+template <typename R, int M2> struct LineGroup {
+    static constexpr bool wide = sizeof(R) == 8 && M2 >= 14;
+    static constexpr int GY = wide ? 1 : 2, GX = wide ? 3 : 2;
+    static constexpr int PY = M2 + GY - 1, PX = M2 + GX - 1;  // footprint rows and columns
+    static constexpr int threads = GY * GX * lines_nrg<M2>() * 64;
+    static constexpr size_t lds = (size_t)M2 * PY * PX * 2 * sizeof(R);
+};
 __host__ __device__ constexpr int lines_slab(int M2) { return (kLinesZ / M2) * M2; }
 
 template <typename R, int M2>
-__global__ __launch_bounds__(lines_threads<M2>()) void k_interp_lines(
+__global__ __launch_bounds__((LineGroup<R, M2>::threads)) void k_interp_lines(
     const Xform *__restrict__ xf, int nitems, int *__restrict__ queue, int T, const unsigned char *__restrict__ rec,
     int rbytes, const int *__restrict__ cell_start, R *__restrict__ outs)
 {
     constexpr int m = M2 / 2;
     constexpr int NRG = lines_nrg<M2>();
-    constexpr int PP = lines_pp<M2>();
-    constexpr int PLANE = PP * PP;
-    constexpr int NTH = lines_threads<M2>();
+    using G = LineGroup<R, M2>;
+    constexpr int GY = G::GY, GX = G::GX, PX = G::PX;
+    constexpr int PLANE = G::PY * PX;
+    constexpr int NTH = G::threads;
     constexpr int NPF = (M2 * PLANE + NTH - 1) / NTH;  // ring cells per thread and phase
     constexpr int OFF_PZ = (int)rec_off_pz(M2, sizeof(R));
     constexpr int Zi = lines_slab(M2);
-    // the next phase's ring cells load into registers during the sweep,
-    // except where the float64 window leaves no registers for them
-    constexpr bool PREF = sizeof(R) == 4 || M2 <= 12;
-    // likewise the next point's record loads while the current one is
-    // evaluated, except for the widest float64 windows
-    constexpr bool PFP = sizeof(R) == 4 || M2 <= 12;
     extern __shared__ uint4 smem16[];
     R *ring = reinterpret_cast<R *>(smem16);  // [slot][footprint row][column] complex
     __shared__ int s_item;
     const int tid = threadIdx.x, lane = tid & 63, wave = uni(tid >> 6);
     const int line = wave / NRG, rg = wave - line * NRG;
-    const int ly = line / kLineGroup, lx = line % kLineGroup;
+    const int ly = line / GX, lx = line % GX;
     const int row = rg * 64 + lane;
     const bool active = row < M2 * M2;
     const int dy = active ? row / M2 : 0, dx = active ? row % M2 : 0;
-    const int cell = (ly + dy) * PP + lx + dx;  // lane's cell in a ring plane
+    const int cell = (ly + dy) * PX + lx + dx;  // lane's cell in a ring plane
     // batch position whose sum this lane receives (see halve8_sum)
     const int j8 = lane >> 3;
     const int own = (lane & 7) * 8 + (((j8 & 1) << 2) | (j8 & 2) | (j8 >> 2));
 
     const int n0 = xf->n[0], n1 = xf->n[1], n2 = xf->n[2];
     const int ntx = xf->ntx;
-    const int ngx = (n2 + kLineGroup - 1) / kLineGroup, ngy = (n1 + kLineGroup - 1) / kLineGroup;
+    const int ngx = (n2 + GX - 1) / GX, ngy = (n1 + GY - 1) / GY;
     const long long poff = xf->poff;
     const int Mx = (int)xf->M;
     const unsigned char *recb = rec + (size_t)poff * rbytes;
@@ -98,7 +99,7 @@ __global__ __launch_bounds__(lines_threads<M2>()) void k_interp_lines(
         const int gx = it % ngx, r0 = it / ngx;
         const int gy = r0 % ngy, sl = r0 / ngy;
         const int z0 = sl * Zi, zs = min(Zi, n0 - z0);
-        const int Y0 = gy * kLineGroup, X0 = gx * kLineGroup;
+        const int Y0 = gy * GY, X0 = gx * GX;
         const int y = Y0 + ly, x = X0 + lx;
         const bool mine = y < n1 && x < n2;
         // the line's points by plane: key (tile, row and column in the
@@ -185,14 +186,14 @@ __global__ __launch_bounds__(lines_threads<M2>()) void k_interp_lines(
             if (b >= 0 && b < zs) {
                 const int pa = __builtin_amdgcn_readlane(rlo, b), pb = __builtin_amdgcn_readlane(rhi, b);
                 for (int sp = pa; sp < pb; ++sp) {
-                    if (!PFP || sp != cidx) {
+                    if (sp != cidx) {
                         rcur = recb + (size_t)sp * rbytes;
                         fetch(rcur, cur);
                     }
                     const bool adv = sp + 1 < Mx;
                     const unsigned char *rnx = adv ? rcur + rbytes : rcur;
                     PointData nxt;
-                    if constexpr (PFP) fetch(rnx, nxt);
+                    fetch(rnx, nxt);
                     R ar = 0, ai = 0;
 #pragma unroll
                     for (int s = 0; s < M2; ++s) {
@@ -203,16 +204,14 @@ __global__ __launch_bounds__(lines_threads<M2>()) void k_interp_lines(
                     bsp = lane == t ? (int)(poff + sp) : bsp;
                     feed(ar * w12, ai * w12);
                     if (t == 64) drain();
-                    if constexpr (PFP) {
-                        cur = nxt;
-                        cidx = adv ? sp + 1 : sp;
-                        rcur = rnx;
-                    }
+                    cur = nxt;
+                    cidx = adv ? sp + 1 : sp;
+                    rcur = rnx;
                 }
             }
         };
 
-        // ring cells of a phase, read from the grid (one phase ahead with PREF)
+        // ring cells of a phase, read from the grid one phase ahead
         R pr[NPF], pim[NPF];
         auto ring_fetch = [&](int ph) __attribute__((always_inline)) {
 #pragma unroll
@@ -222,7 +221,7 @@ __global__ __launch_bounds__(lines_threads<M2>()) void k_interp_lines(
                 const int q = ph * M2 + zz;
                 pr[u] = pim[u] = R(0);
                 if (e < M2 * PLANE && q < zr) {
-                    const int fy = c / PP, fx = c - fy * PP;
+                    const int fy = c / PX, fx = c - fy * PX;
                     int gz = z0 + q;  // below 2 n0
                     gz -= gz >= n0 ? n0 : 0;
                     int gyy = Y0 + fy - (m - 1), gxx = X0 + fx - (m - 1);
@@ -240,10 +239,9 @@ __global__ __launch_bounds__(lines_threads<M2>()) void k_interp_lines(
         };
 
         const int nph = (zr + M2 - 1) / M2;
-        if constexpr (PREF) ring_fetch(0);
+        ring_fetch(0);
         for (int ph = 0; ph < nph; ++ph) {
             if (ph > 0) __syncthreads();  // the previous phase's steps have read the ring
-            if constexpr (!PREF) ring_fetch(ph);
 #pragma unroll
             for (int u = 0; u < NPF; ++u) {
                 const int e = tid + u * NTH;
@@ -253,9 +251,7 @@ __global__ __launch_bounds__(lines_threads<M2>()) void k_interp_lines(
                 }
             }
             __syncthreads();
-            if constexpr (PREF) {
-                if (ph + 1 < nph) ring_fetch(ph + 1);
-            }
+            if (ph + 1 < nph) ring_fetch(ph + 1);
             if (mine) {
 #pragma unroll
                 for (int k = 0; k < M2; ++k) step(k, ph * M2 + k);
@@ -274,14 +270,15 @@ static hipError_t interp_lines_m(const Xform *xf, const int n[3], int *queue, in
                                  size_t rec_bytes, const int *cs, R *outs, hipStream_t s)
 {
     const int nsl = (n[0] + lines_slab(M2) - 1) / lines_slab(M2);
-    const int nitems = nsl * ((n[1] + kLineGroup - 1) / kLineGroup) * ((n[2] + kLineGroup - 1) / kLineGroup);
-    constexpr size_t lds = lines_lds<M2, R>();
+    using G = LineGroup<R, M2>;
+    const int nitems = nsl * ((n[1] + G::GY - 1) / G::GY) * ((n[2] + G::GX - 1) / G::GX);
+    constexpr size_t lds = G::lds;
     auto kern = k_interp_lines<R, M2>;
     hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     const int grid = std::min(cu_count(), nitems);
     if (grid < 1) return hipSuccess;
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(lines_threads<M2>()), lds, s, xf, nitems, queue, T, rec,
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(G::threads), lds, s, xf, nitems, queue, T, rec,
                        (int)rec_bytes, cs, outs);
     return hipGetLastError();
 }
