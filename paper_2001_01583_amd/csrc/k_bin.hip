@@ -144,22 +144,19 @@ __device__ inline double horner(const double *__restrict__ c, double v)
     return r;
 }
 
+// Point j's sorted position (written to perm and ipos unless the positions
+// are fixed), window tables in record slot order and record header.
 template <typename R, int M2, bool GRAD>
-__global__ __launch_bounds__(256) void k_bin_scatter(const double *__restrict__ xd, const float *__restrict__ xf,
-                                                     long long M, long long poff, int n0, int n1, int n2, int T,
-                                                     int ntx, const int *__restrict__ cell_start,
-                                                     const int *__restrict__ rank, int *__restrict__ perm,
-                                                     int *__restrict__ ipos, unsigned char *__restrict__ rec,
-                                                     size_t rec_bytes, WindowParams wp,
-                                                     const double *__restrict__ poly, int flat, int nb0, int nb1,
-                                                     int nb2, const int *__restrict__ fixed_pos)
+__device__ inline long long scatter_point(long long j, const double *__restrict__ xd, const float *__restrict__ xf,
+                                          long long poff, int n0, int n1, int n2, int T, int ntx,
+                                          const int *__restrict__ cell_start, const int *__restrict__ rank,
+                                          int *__restrict__ perm, int *__restrict__ ipos, const WindowParams &wp,
+                                          const double *__restrict__ poly, int flat, int nb0, int nb1, int nb2,
+                                          const int *__restrict__ fixed_pos, R (&w)[3 * M2],
+                                          R (&dw)[GRAD ? 3 * M2 : 1], int2 &head)
 {
     constexpr int m = M2 / 2;
-    constexpr int NW = 3 * M2;
     constexpr int NC = sizeof(R) == 4 ? kPolyF32 : kPolyF64;
-    static_assert((NW * sizeof(R)) % 8 == 0, "window block is a whole number of 8-byte units");
-    const long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= M) return;
     const int n[3] = {n0, n1, n2};
     bool bad = false;
     int c[3];
@@ -178,12 +175,9 @@ __global__ __launch_bounds__(256) void k_bin_scatter(const double *__restrict__ 
         perm[pos] = (int)(poff + j);
         ipos[poff + j] = (int)pos;
     }
-    unsigned char *rp = rec + pos * rec_bytes;
 
     int rot = (c[0] - m + 1) % M2;
     if (rot < 0) rot += M2;
-    R w[NW];
-    R dw[GRAD ? NW : 1];
     // values in tap order (the tap index, hence the polynomial, is the same
     // for every thread)
 #pragma unroll
@@ -245,10 +239,97 @@ __global__ __launch_bounds__(256) void k_bin_scatter(const double *__restrict__ 
             }
         }
     }
+    head = nb0 ? make_int2(c[0], (c[1] << kBoxCellBits) | c[2]) : make_int2(c[0], c[2] & (block_w(M2) - 1));
+    return pos;
+}
+
+// One thread per point, each storing its own record (gradient plans, whose
+// records carry the derivative tables too).
+template <typename R, int M2, bool GRAD>
+__global__ __launch_bounds__(256) void k_bin_scatter(const double *__restrict__ xd, const float *__restrict__ xf,
+                                                     long long M, long long poff, int n0, int n1, int n2, int T,
+                                                     int ntx, const int *__restrict__ cell_start,
+                                                     const int *__restrict__ rank, int *__restrict__ perm,
+                                                     int *__restrict__ ipos, unsigned char *__restrict__ rec,
+                                                     size_t rec_bytes, WindowParams wp,
+                                                     const double *__restrict__ poly, int flat, int nb0, int nb1,
+                                                     int nb2, const int *__restrict__ fixed_pos)
+{
+    constexpr int NW = 3 * M2;
+    static_assert((NW * sizeof(R)) % 8 == 0, "window block is a whole number of 8-byte units");
+    const long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= M) return;
+    R w[NW];
+    R dw[GRAD ? NW : 1];
+    int2 head;
+    const long long pos = scatter_point<R, M2, GRAD>(j, xd, xf, poff, n0, n1, n2, T, ntx, cell_start, rank, perm,
+                                                     ipos, wp, poly, flat, nb0, nb1, nb2, fixed_pos, w, dw, head);
+    unsigned char *rp = rec + pos * rec_bytes;
     store_block<NW * sizeof(R)>(rp, w);
-    *reinterpret_cast<int2 *>(rp + rec_off_pz(M2, sizeof(R))) =
-        nb0 ? make_int2(c[0], (c[1] << kBoxCellBits) | c[2]) : make_int2(c[0], c[2] & (block_w(M2) - 1));
+    *reinterpret_cast<int2 *>(rp + rec_off_pz(M2, sizeof(R))) = head;
     if constexpr (GRAD) store_block<NW * sizeof(R)>(rp + rec_prefix(M2, sizeof(R)), dw);
+}
+
+// Records without derivative tables: each wavefront assembles its 64
+// records in LDS, then stores them unit by unit, consecutive lanes on
+// consecutive 16-byte units, so that a store instruction writes a few whole
+// records instead of one 16-byte piece of 64 records.  The value slot is
+// left zero (the sweeps that stage records fill it per call).
+template <typename R, int M2>
+__global__ __launch_bounds__(64) void k_bin_scatter_lds(const double *__restrict__ xd, const float *__restrict__ xf,
+                                                        long long M, long long poff, int n0, int n1, int n2, int T,
+                                                        int ntx, const int *__restrict__ cell_start,
+                                                        const int *__restrict__ rank, int *__restrict__ perm,
+                                                        int *__restrict__ ipos, unsigned char *__restrict__ rec,
+                                                        size_t rec_bytes, WindowParams wp,
+                                                        const double *__restrict__ poly, int flat, int nb0, int nb1,
+                                                        int nb2, const int *__restrict__ fixed_pos)
+{
+    constexpr int NW = 3 * M2;
+    constexpr int RB = (int)rec_prefix(M2, sizeof(R));  // record bytes staged
+    constexpr int U = RB / 16;
+    static_assert(RB % 16 == 0 && (NW * sizeof(R)) % 8 == 0, "records of whole 16-byte units");
+    extern __shared__ uint4 sm[];  // 64 records, then 64 positions
+    int *spos = reinterpret_cast<int *>(sm + 64 * U);
+    const int lane = threadIdx.x;
+    const long long j0 = (long long)blockIdx.x * 64;
+    const long long j = j0 + lane;
+    if (j < M) {
+        R w[NW];
+        R dw[1];
+        int2 head;
+        const long long pos = scatter_point<R, M2, false>(j, xd, xf, poff, n0, n1, n2, T, ntx, cell_start, rank,
+                                                          perm, ipos, wp, poly, flat, nb0, nb1, nb2, fixed_pos, w,
+                                                          dw, head);
+        uint4 *lp = sm + lane * U;
+        constexpr int NU32 = NW * (int)sizeof(R) / 4;  // words of the window tables
+        unsigned wv[NU32];
+        __builtin_memcpy(wv, w, sizeof(wv));  // (a copy: no access through a pointer of another type)
+        // words NU32 .. : value slot (zero), header, padding (zero)
+        unsigned tail[4 * U - NU32];
+#pragma unroll
+        for (int i = 0; i < 4 * U - NU32; ++i) tail[i] = 0u;
+        constexpr int HW = (int)rec_off_pz(M2, sizeof(R)) / 4 - NU32;  // header word in tail
+        tail[HW] = (unsigned)head.x;
+        tail[HW + 1] = (unsigned)head.y;
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            unsigned v[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int wi = 4 * k + i;
+                v[i] = wi < NU32 ? wv[wi] : tail[wi - NU32];
+            }
+            lp[k] = make_uint4(v[0], v[1], v[2], v[3]);
+        }
+        spos[lane] = (int)pos;
+    }
+    __syncthreads();
+    const int nvalid = (int)(M - j0 < 64 ? M - j0 : 64);
+    for (int u = lane; u < nvalid * U; u += 64) {
+        const int r = u / U, k = u - r * U;
+        *reinterpret_cast<uint4 *>(rec + (size_t)spos[r] * rec_bytes + 16 * k) = sm[r * U + k];
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -405,11 +486,20 @@ static void scatter_m(const double *x, const float *xf32, long long M, const Xfo
                       size_t rec_bytes, const WindowParams &wp, const double *poly, bool grad, const int *fixed_pos,
                       hipStream_t s)
 {
+    if (!grad) {
+        constexpr size_t lds = 64 * rec_prefix(M2, sizeof(R)) + 64 * 4;
+        const unsigned nb = (unsigned)((M + 63) / 64);
+        auto kl = k_bin_scatter_lds<R, M2>;
+        hipLaunchKernelGGL(kl, dim3(nb), dim3(64), lds, s, x, xf32, M, X.poff, X.n[0],
+                           X.n[1], X.n[2], T, X.ntx, cell_start, rank, perm, ipos, rec, rec_bytes, wp, poly, X.flat,
+                           X.nbox[0], X.nbox[1], X.nbox[2], fixed_pos);
+        return;
+    }
     const unsigned nb = (unsigned)((M + 255) / 256);
-    auto k = grad ? k_bin_scatter<R, M2, true> : k_bin_scatter<R, M2, false>;
-    hipLaunchKernelGGL(k, dim3(nb), dim3(256), 0, s, x, xf32, M, X.poff, X.n[0], X.n[1], X.n[2], T, X.ntx,
-                       cell_start, rank, perm, ipos, rec, rec_bytes, wp, poly, X.flat, X.nbox[0], X.nbox[1],
-                       X.nbox[2], fixed_pos);
+    auto kg = k_bin_scatter<R, M2, true>;
+    hipLaunchKernelGGL(kg, dim3(nb), dim3(256), 0, s, x, xf32, M, X.poff, X.n[0], X.n[1],
+                       X.n[2], T, X.ntx, cell_start, rank, perm, ipos, rec, rec_bytes, wp, poly, X.flat, X.nbox[0],
+                       X.nbox[1], X.nbox[2], fixed_pos);
 }
 
 template <typename R>
