@@ -226,8 +226,7 @@ hipError_t launch_interp(int m, bool grad, const Xform *dxf, const SItem *items,
                          Tiling t, const unsigned char *rec, size_t rec_bytes, const int *cell_start,
                          R *outs, hipStream_t s);
 // Interpolation by groups of single lines (lines.h), one transform per
-// launch: windows of 2m = 10 .. 16 cells on grids whose n0 is a multiple of
-// 2m.  xf: the transform's device descriptor; n: its grid edges; T: the
+// launch: windows of 2m = 16 cells on grids whose n0 is a multiple of 2m.  xf: the transform's device descriptor; n: its grid edges; T: the
 // tile edge of the counting sort; outs: cleared, receives sums.
 template <typename R>
 hipError_t launch_interp_lines(int m, const Xform *xf, const int n[3], int *queue, int T, const unsigned char *rec,

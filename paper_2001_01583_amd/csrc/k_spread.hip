@@ -66,13 +66,8 @@ template <typename R>
 hipError_t launch_interp_lines(int m, const Xform *xf, const int n[3], int *queue, int T, const unsigned char *rec,
                                size_t rec_bytes, const int *cs, R *outs, hipStream_t s)
 {
-    switch (m) {
-    case 5: return interp_lines_m<R, 10>(xf, n, queue, T, rec, rec_bytes, cs, outs, s);
-    case 6: return interp_lines_m<R, 12>(xf, n, queue, T, rec, rec_bytes, cs, outs, s);
-    case 7: return interp_lines_m<R, 14>(xf, n, queue, T, rec, rec_bytes, cs, outs, s);
-    case 8: return interp_lines_m<R, 16>(xf, n, queue, T, rec, rec_bytes, cs, outs, s);
-    default: return hipErrorInvalidValue;
-    }
+    if (m != 8) return hipErrorInvalidValue;
+    return interp_lines_m<R, 16>(xf, n, queue, T, rec, rec_bytes, cs, outs, s);
 }
 
 template hipError_t launch_interp_lines<double>(int, const Xform *, const int *, int *, int, const unsigned char *,

@@ -1,5 +1,6 @@
 // Interpolation by groups of single z-lines (the Interpolating step of
-// Algorithm 5, Section 3) for windows of 2m = 10 .. 16 cells.
+// Algorithm 5, Section 3).  Written for windows of 2m = 10 .. 16 cells; the
+// plan selects it for 2m = 16, where it beats the staged sweep.
 //
 // A work item is a group of neighbouring z-lines (2 x 2, or a row of three
 // for the widest float64 windows) and a slab of Zi planes along dim 0 (a

@@ -419,8 +419,12 @@ bool use_ring(const hpnfft_plan_s *p, const Tiling &t)
 }
 
 // Whether the forward's interpolation runs by groups of single lines
-// (lines.h): windows of 2m = 10 .. 16 cells, every line-method transform with
-// n0 a multiple of 2m (HPNFFT_LINES=0 selects the staged sweep).
+// (lines.h): windows of 2m = 16 cells, every line-method transform with n0 a
+// multiple of 2m (HPNFFT_LINES=0 selects the staged sweep).  Measured at N =
+// 64^3, M = 2^20: float64 2.94 -> 1.34 ms, float32 1.58 -> 0.91 ms for 2m =
+// 16; for 2m = 10, 12 and 14 the staged sweep stays faster (float64 0.94,
+// 1.35, 2.26 ms against 1.24, 1.47, 2.33 ms): with fewer taps per point the
+// per-point and per-plane costs of the line groups dominate.
 bool use_lines(const hpnfft_plan_s *p)
 {
     static int on = -1;
@@ -429,7 +433,7 @@ bool use_lines(const hpnfft_plan_s *p)
         on = (e && e[0] == '0') ? 0 : 1;
     }
     const int M2 = p->M2();
-    if (!on || p->det() || M2 < 10 || M2 > 16) return false;
+    if (!on || p->det() || M2 != 16) return false;
     for (size_t b = 0; b < p->hx.size(); ++b)
         if (!p->tbox[b] && p->hx[b].n[0] % M2) return false;
     return true;

@@ -1,11 +1,12 @@
 """The interpolation by groups of single lines (the Interpolating step of
-Algorithm 5, Section 3) for windows of 2m = 10 .. 16 cells on grids whose n0
-is a multiple of 2m: groups of 2 x 2 lines, slabs of up to 64 planes, each
-point evaluated once by the slab of its first tap plane, the planes passing
-through an LDS ring of 2m planes.  Checked against the direct FP64 oracle
-(Eq. (6)) on one slab and several (the last one short), sigma = 1.5, every
-m the path serves, clustered points, a single point, batches, gradient plans
-and repeated calls."""
+Algorithm 5, Section 3) for windows of 2m = 16 cells on grids whose n0 is a
+multiple of 2m: groups of 2 x 2 lines (a row of three in float64), slabs of
+64 planes, each point evaluated once by the slab of its first tap plane, the
+planes passing through an LDS ring of 2m planes.  Checked against the
+direct FP64 oracle (Eqs. (5) and (6)) on one slab and several (the last one
+short), sigma = 1.5, clustered points, a single point, batches, gradient
+plans and repeated calls; m = 5, 6, 7 (which keep the staged sweep) and
+grids whose n0 is no multiple of 2m run the same checks through it."""
 import numpy as np
 import pytest
 import torch
@@ -44,8 +45,8 @@ def _fh(seed, N, prec):
 
 
 # N, M, m: one slab (n0 = 32), two (n0 = 128), a short last slab (n0 = 80:
-# 64 + 16 planes; m = 6, n0 = 72: 60 + 12), 2m = 10 (two row groups, 36 rows
-# of the second idle), 2m = 14 (four row groups, the last with 4 rows)
+# 64 + 16 planes), a single point, n0 = 24 (no multiple of 16: staged);
+# m = 5, 6, 7 run the staged sweep
 CASES = [
     ((16, 16, 16), 4096, 8),
     ((64, 16, 16), 20000, 8),
@@ -54,6 +55,7 @@ CASES = [
     ((36, 12, 12), 3000, 6),
     ((28, 16, 16), 3000, 7),
     ((16, 16, 16), 1, 8),
+    ((12, 16, 16), 4000, 8),
 ]
 
 
