@@ -161,11 +161,12 @@ def summarize_counters(fetch_dir: str, write_dir: str, out_json: str, command: s
     import re
     for full in set(fetch) | set(write):
         # the sweep kernels of the default line: the ring sweeps (2m = 8,
-        # m = 4) and the staged sweeps, whose second template argument is 2m
-        mt = re.match(r"(?:void )?hpnfft::k_(spread|interp)(_ring)?<(float|double)(?:, (\d+))?", full)
+        # m = 4), the line interpolation and the staged sweeps (whose second
+        # template argument is 2m)
+        mt = re.match(r"(?:void )?hpnfft::k_(spread|interp)(_ring|_lines)?<(float|double)(?:, (\d+))?", full)
         if not mt:
             continue
-        m = 4 if mt.group(2) else int(mt.group(4)) // 2
+        m = 4 if mt.group(2) == "_ring" else int(mt.group(4)) // 2
         prec = "f32" if mt.group(3) == "float" else "f64"
         fb = fetch.get(full, 0.0) * 1024.0 * (f_scale or 1.0)
         wb = write.get(full, 0.0) * 1024.0 * (w_scale or 1.0)

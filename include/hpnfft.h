@@ -163,7 +163,10 @@ int hpnfft_get_method(hpnfft_plan plan, int *method);
  * spread and the interpolation run as ring sweeps (one wavefront per block
  * of 8 lines through the whole slab; environment variable HPNFFT_RING=0
  * selects the staged sweeps instead); threads is then 512 whatever is
- * passed. */
+ * passed.  With 2m = 16 and every line-method grid's n0 a multiple of 16,
+ * the forward's interpolation runs by groups of lines over 64-plane slabs
+ * whatever the tiling (environment variable HPNFFT_LINES=0 selects the
+ * staged sweep); the spread keeps the tiling. */
 int hpnfft_set_tiles(hpnfft_plan plan, int tile, int slab, int threads);
 int hpnfft_get_tiles(hpnfft_plan plan, int *tile, int *slab, int *threads);
 
