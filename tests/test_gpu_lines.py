@@ -145,3 +145,23 @@ def test_lines_batch(H, oracle_mod, prec, tol):
         err = oracle_mod.rel_l2(out[po:po + M], oracle_mod.ndft_forward(n, xs[b], fhs[b]))
         print("lines batch %s b=%d N=%s M=%d: forward rel-l2 %.3e" % (prec, b, n, M, err))
         assert err <= tol
+
+
+def test_lines_in_mixed_batch(H, oracle_mod):
+    """A batch whose dense transforms take the line sweeps (their forward: the
+    line interpolation) and whose sparse ones take boxes: each forward output
+    against the oracle."""
+    Ns = [(16, 16, 16), (32, 32, 32), (16, 16, 16)]
+    Ms = [20000, 200, 3]
+    g = W.rng(1901)
+    xs = [W.uniform_points(M, 3, g) for M in Ms]
+    plan = H.Plan(Ns, Ms, m=8, precision="f64")
+    assert plan.method == "mixed"
+    plan.set_points(torch.from_numpy(np.concatenate(xs)).cuda())
+    fhs = [_fh(1910 + b, n, "f64") for b, n in enumerate(Ns)]
+    out = plan.forward(torch.from_numpy(np.concatenate([v.reshape(-1) for v in fhs])).cuda()).cpu().numpy()
+    for b, (n, M) in enumerate(zip(Ns, Ms)):
+        po, _ = plan.offsets(b)
+        err = oracle_mod.rel_l2(out[po:po + M], oracle_mod.ndft_forward(n, xs[b], fhs[b]))
+        print("lines mixed batch b=%d N=%s M=%d: forward rel-l2 %.3e" % (b, n, M, err))
+        assert err <= 1e-12
