@@ -116,6 +116,9 @@ __global__ __launch_bounds__((LineGroup<R, M2>::threads)) void k_interp_lines(
 
         PointData cur{};
         int cidx = -1;
+        // partial sums of the last point evaluated, not yet reduced
+        R pvr = 0, pvi = 0;
+        int pend = -1;  // its sorted index (-1: none)
         const unsigned char *rcur = recb;
         R gr[M2], gi[M2];
 
@@ -164,6 +167,12 @@ __global__ __launch_bounds__((LineGroup<R, M2>::threads)) void k_interp_lines(
             orr = ori = R(0);
             t = 0;
         };
+        auto reduce_pending = [&]() __attribute__((always_inline)) {
+            bsp = lane == t ? (int)(poff + pend) : bsp;
+            feed(pvr, pvi);
+            if (t == 64) drain();
+            pend = -1;
+        };
 
         // sorted point range of base plane b (b < zs <= 64) in lane b: read
         // with lane reads at the steps, so that the steps wait on no load
@@ -187,14 +196,16 @@ __global__ __launch_bounds__((LineGroup<R, M2>::threads)) void k_interp_lines(
             if (b >= 0 && b < zs) {
                 const int pa = __builtin_amdgcn_readlane(rlo, b), pb = __builtin_amdgcn_readlane(rhi, b);
                 for (int sp = pa; sp < pb; ++sp) {
+                    // the previous point's reduction runs first, so that the
+                    // loads of this point (issued after the previous point's
+                    // sums, into the same registers: two sets of the shared
+                    // weights do not fit the scalar registers of the widest
+                    // windows) are in flight meanwhile
+                    if (pend >= 0) reduce_pending();
                     if (sp != cidx) {
                         rcur = recb + (size_t)sp * rbytes;
                         fetch(rcur, cur);
                     }
-                    const bool adv = sp + 1 < Mx;
-                    const unsigned char *rnx = adv ? rcur + rbytes : rcur;
-                    PointData nxt;
-                    fetch(rnx, nxt);
                     R ar = 0, ai = 0;
 #pragma unroll
                     for (int s = 0; s < M2; ++s) {
@@ -202,12 +213,13 @@ __global__ __launch_bounds__((LineGroup<R, M2>::threads)) void k_interp_lines(
                         ai = fma(gi[s], cur.wz[s], ai);
                     }
                     const R w12 = active ? cur.wy * cur.wx : R(0);
-                    bsp = lane == t ? (int)(poff + sp) : bsp;
-                    feed(ar * w12, ai * w12);
-                    if (t == 64) drain();
-                    cur = nxt;
+                    pvr = ar * w12;
+                    pvi = ai * w12;
+                    pend = sp;
+                    const bool adv = sp + 1 < Mx;
+                    rcur = adv ? rcur + rbytes : rcur;
+                    fetch(rcur, cur);
                     cidx = adv ? sp + 1 : sp;
-                    rcur = rnx;
                 }
             }
         };
@@ -258,6 +270,7 @@ __global__ __launch_bounds__((LineGroup<R, M2>::threads)) void k_interp_lines(
                 for (int k = 0; k < M2; ++k) step(k, ph * M2 + k);
             }
         }
+        if (mine && pend >= 0) reduce_pending();
         if (mine && t > 0) drain();
     }
     release_queue(queue);

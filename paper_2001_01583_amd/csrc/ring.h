@@ -314,6 +314,9 @@ __global__ __launch_bounds__(kRingThreads, ring_waves_per_simd<R>()) void k_inte
         };
         PointData cur{};
         int cidx = -1;
+        // partial sums of the last point evaluated, not yet reduced
+        R pvr = 0, pvi = 0;
+        int pend = -1;  // its sorted index (-1: none)
         const unsigned char *rcur = recb;
 
         R gr[2][M2], gi[2][M2];
@@ -366,12 +369,20 @@ __global__ __launch_bounds__(kRingThreads, ring_waves_per_simd<R>()) void k_inte
             orr = ori = R(0);
             t = 0;
         };
+        auto reduce_pending = [&]() __attribute__((always_inline)) {
+            bsp = lane == t ? (int)(poff + pend) : bsp;
+            feed(pvr, pvi);
+            if (t == 64) drain();
+            pend = -1;
+        };
 
-        int na = 0, nb = 0;  // sorted range of the next base plane, one step ahead
-        if (mine) {
-            const int c = plane_c(0);
-            na = cs[c * BW];
-            nb = cs[(c + 1) * BW];
+        // sorted point range of base plane b (b < zs <= 64) in lane b: read
+        // with lane reads at the steps, so that the steps wait on no load
+        int rlo = 0, rhi = 0;
+        if (mine && lane < zs) {
+            const int c = plane_c(lane);
+            rlo = cs[c * BW];
+            rhi = cs[(c + 1) * BW];
         }
         const int zr = zs + M2 - 1;  // planes the ring carries: the slab and the windows past it
         const int rowc = (li + dy) * kRingPitch + xm;
@@ -389,19 +400,16 @@ __global__ __launch_bounds__(kRingThreads, ring_waves_per_simd<R>()) void k_inte
             }
             const int b = q - (M2 - 1);
             if (b >= 0 && b < zs) {
-                const int pa = uni(na), pb = uni(nb);
-                const int c = plane_c(b + 1);
-                na = cs[c * BW];
-                nb = cs[(c + 1) * BW];
+                const int pa = __builtin_amdgcn_readlane(rlo, b), pb = __builtin_amdgcn_readlane(rhi, b);
                 for (int sp = pa; sp < pb; ++sp) {
+                    // the previous point's reduction runs first, so that this
+                    // point's loads (issued right after the previous point's
+                    // sums, into the same registers) are in flight meanwhile
+                    if (pend >= 0) reduce_pending();
                     if (sp != cidx) {
                         rcur = recb + (size_t)sp * rbytes;
                         fetch(rcur, cur);
                     }
-                    const bool adv = sp + 1 < Mx;
-                    const unsigned char *rnx = adv ? rcur + rbytes : rcur;
-                    PointData nxt;
-                    fetch(rnx, nxt);
                     R a0r = 0, a0i = 0, a1r = 0, a1i = 0;
 #pragma unroll
                     for (int s = 0; s < M2; ++s) {
@@ -415,12 +423,13 @@ __global__ __launch_bounds__(kRingThreads, ring_waves_per_simd<R>()) void k_inte
                     // else xm + 8
                     const bool hi = xm < uni(cur.j);
                     const R w12 = cur.wy * cur.wx;
-                    bsp = lane == t ? (int)(poff + sp) : bsp;
-                    feed((hi ? a1r : a0r) * w12, (hi ? a1i : a0i) * w12);
-                    if (t == 64) drain();
-                    cur = nxt;
+                    pvr = (hi ? a1r : a0r) * w12;
+                    pvi = (hi ? a1i : a0i) * w12;
+                    pend = sp;
+                    const bool adv = sp + 1 < Mx;
+                    rcur = adv ? rcur + rbytes : rcur;
+                    fetch(rcur, cur);
                     cidx = adv ? sp + 1 : sp;
-                    rcur = rnx;
                 }
             }
         };
@@ -459,6 +468,7 @@ __global__ __launch_bounds__(kRingThreads, ring_waves_per_simd<R>()) void k_inte
             }
             if (ph + 1 < nph) __syncthreads();
         }
+        if (mine && pend >= 0) reduce_pending();
         if (mine && t > 0) drain();
     }
     release_queue(queue);
