@@ -132,6 +132,18 @@ __device__ inline long long box_point(int k, int nruns, const int *run_p0, const
     return (long long)uni(run_p0[r]) + (k - uni(run_soff[r]));
 }
 
+// Value of v in lane l (l wave-uniform), as a lane read: the dim-0 weights of
+// a point sit one per lane, so the tap loop reads them without a memory
+// access.
+template <typename R> __device__ inline R lane_value(R v, int l)
+{
+    unsigned w[Words<R>::n];
+    Words<R>::split(v, w);
+#pragma unroll
+    for (int i = 0; i < Words<R>::n; ++i) w[i] = (unsigned)__builtin_amdgcn_readlane((int)w[i], l);
+    return Words<R>::join(w);
+}
+
 // ---------------------------------------------------------------------------
 template <typename R>
 __global__ __launch_bounds__(kBoxThreads) void k_spread_box(const Xform *__restrict__ xfs,
@@ -168,6 +180,7 @@ __global__ __launch_bounds__(kBoxThreads) void k_spread_box(const Xform *__restr
             if (!clip_window(make_int2(uni(hd.x), uni(hd.y)), sh, g, m, c)) continue;
             const R *ps = reinterpret_cast<const R *>(rp);
             const R fr = fs[2 * pos], fi = fs[2 * pos + 1];
+            const R w0l = lane < M2 ? ps[lane] : R(0);  // dim-0 weight of tap `lane`
             const int n2 = c.b[2] - c.a[2], rows = (c.b[1] - c.a[1]) * n2;
             for (int i = lane; i < rows; i += 64) {
                 const int t1 = c.a[1] + i / n2, t2 = c.a[2] + i % n2;
@@ -175,7 +188,7 @@ __global__ __launch_bounds__(kBoxThreads) void k_spread_box(const Xform *__restr
                 const R vr = fr * w12, vi = fi * w12;
                 const int yx = (c.f[1] + t1 - g.lo[1]) * g.w[2] + (c.f[2] + t2 - g.lo[2]);
                 for (int t0 = c.a[0]; t0 < c.b[0]; ++t0) {
-                    const R w = ps[t0];
+                    const R w = lane_value(w0l, t0);
                     const int o = (c.f[0] + t0 - g.lo[0]) * g.w[1] * g.w[2] + yx;
                     if constexpr (COMP) {
                         unsigned long long *cc[2] = {&pairs[o], &pairs[o + cells]};
@@ -262,6 +275,9 @@ __global__ __launch_bounds__(kBoxThreads) void k_interp_box(const Xform *__restr
             if (!clip_window(make_int2(uni(hd.x), uni(hd.y)), sh, g, m, c)) continue;
             const R *ps = reinterpret_cast<const R *>(rp);
             const R *dp = ps + off_d;
+            // dim-0 weight (and derivative) of tap `lane`
+            const R w0l = lane < M2 ? ps[lane] : R(0);
+            const R d0l = GRAD && lane < M2 ? dp[lane] : R(0);
             R v[2 * NO];
 #pragma unroll
             for (int q = 0; q < 2 * NO; ++q) v[q] = R(0);
@@ -273,11 +289,11 @@ __global__ __launch_bounds__(kBoxThreads) void k_interp_box(const Xform *__restr
                 for (int t0 = c.a[0]; t0 < c.b[0]; ++t0) {
                     const int o = ((c.f[0] + t0 - g.lo[0]) * g.w[1] * g.w[2] + yx) * 2;
                     const R gr = tile[o], gim = tile[o + 1];
-                    const R w = ps[t0];
+                    const R w = lane_value(w0l, t0);
                     sr = fma(w, gr, sr);
                     si = fma(w, gim, si);
                     if constexpr (GRAD) {
-                        const R dw = dp[t0];
+                        const R dw = lane_value(d0l, t0);
                         dr = fma(dw, gr, dr);
                         di = fma(dw, gim, di);
                     }
