@@ -186,7 +186,10 @@ def test_fp32_ewald_energy_and_forces(E):
     eu = abs(U32.item() - U64.item()) / abs(U64.item())
     ef = (F32 - F64).abs().max().item() / F64.abs().max().item()
     print("FP32 Ewald: energy rel %.3e, forces rel %.3e" % (eu, ef))
-    assert eu <= 1e-5 and ef <= 1e-3
+    # forces: sums of many reciprocal terms of alternating sign, each with the
+    # float32 rounding of the grid and the FFT, lose about three of float32's
+    # seven digits on a lattice this small (measured 1.9e-4)
+    assert eu <= 1e-5 and ef <= 5e-4
 
 
 def test_autograd_forces_equal_backward_kernel(E):
@@ -203,7 +206,7 @@ def test_autograd_forces_equal_backward_kernel(E):
     assert (Fa - F).abs().max().item() <= 1e-10 * F.abs().max().item()
 
 
-@pytest.mark.parametrize("prec,m,tol_u,tol_f", [("f64", 8, 1e-12, 1e-10), ("f32", 4, 1e-5, 1e-3)])
+@pytest.mark.parametrize("prec,m,tol_u,tol_f", [("f64", 8, 1e-12, 1e-10), ("f32", 4, 1e-5, 2e-4)])
 def test_autotuned_ewald_keeps_energy_and_forces(E, oracle_mod, prec, m, tol_u, tol_f):
     """Ewald.autotune re-tiles a gradient plan (timing the backward too); the
     reciprocal energy and forces then still match the direct oracle."""
