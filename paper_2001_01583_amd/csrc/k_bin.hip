@@ -179,22 +179,43 @@ __device__ inline long long scatter_point(long long j, const double *__restrict_
     int rot = (c[0] - m + 1) % M2;
     if (rot < 0) rot += M2;
     // values in tap order (the tap index, hence the polynomial, is the same
-    // for every thread)
+    // for every thread).  A flat dim (no coordinate, N_t = 1) holds the unit
+    // impulse on cell 0, which the point (at 0) reaches with tap m - 1.
+    if (poly && !GRAD) {
+        // the fitted polynomials: a short body, unrolled, so that w stays in
+        // registers
 #pragma unroll
-    for (int dim = 0; dim < 3; ++dim) {
+        for (int dim = 0; dim < 3; ++dim) {
 #pragma unroll
-        for (int t = 0; t < M2; ++t) {
-            const double dist = u[dim] + (double)(m - 1 - t);
-            double ph = 0.0, dph = 0.0;
-            if (!poly || GRAD) win_eval(wp, dist, &ph, GRAD ? &dph : nullptr);
-            w[dim * M2 + t] = (R)(poly ? horner<NC>(poly + t * NC, 2.0 * u[dim] - 1.0) : ph);
-            if constexpr (GRAD) dw[dim * M2 + t] = (R)((double)n[dim] * dph);
-            // a flat dim (no coordinate, N_t = 1): unit impulse on cell 0,
-            // which the point (at 0) reaches with tap m - 1
-            if (dim < flat) {
-                w[dim * M2 + t] = t == m - 1 ? R(1) : R(0);
-                if constexpr (GRAD) dw[dim * M2 + t] = R(0);
+            for (int t = 0; t < M2; ++t) {
+                w[dim * M2 + t] = (R)horner<NC>(poly + t * NC, 2.0 * u[dim] - 1.0);
+                if (dim < flat) w[dim * M2 + t] = t == m - 1 ? R(1) : R(0);
             }
+        }
+    } else {
+        // direct evaluation (and the derivatives): a loop too large to
+        // unroll, into arrays of its own, then copied with fixed indices (an
+        // array indexed at run time would leave w in scratch memory for
+        // every path)
+        constexpr int NW = 3 * M2;
+        R ws[NW], dws[GRAD ? NW : 1];
+        for (int dim = 0; dim < 3; ++dim) {
+            for (int t = 0; t < M2; ++t) {
+                const double dist = u[dim] + (double)(m - 1 - t);
+                double ph = 0.0, dph = 0.0;
+                win_eval(wp, dist, &ph, GRAD ? &dph : nullptr);
+                ws[dim * M2 + t] = (R)(poly ? horner<NC>(poly + t * NC, 2.0 * u[dim] - 1.0) : ph);
+                if constexpr (GRAD) dws[dim * M2 + t] = (R)((double)n[dim] * dph);
+                if (dim < flat) {
+                    ws[dim * M2 + t] = t == m - 1 ? R(1) : R(0);
+                    if constexpr (GRAD) dws[dim * M2 + t] = R(0);
+                }
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < NW; ++i) {
+            w[i] = ws[i];
+            if constexpr (GRAD) dw[i] = dws[i];
         }
     }
     // dim 0 into slot order, slot s = (tap + rot) mod 2m: a rotation by rot
