@@ -183,13 +183,25 @@ __device__ inline long long scatter_point(long long j, const double *__restrict_
     // impulse on cell 0, which the point (at 0) reaches with tap m - 1.
     if (poly && !GRAD) {
         // the fitted polynomials: a short body, unrolled, so that w stays in
-        // registers
+        // registers.  The window is even, so tap 2m - 1 - t at v is tap t at
+        // -v: both come from the even and odd parts of tap t's polynomial.
 #pragma unroll
         for (int dim = 0; dim < 3; ++dim) {
+            const double v = 2.0 * u[dim] - 1.0, v2 = v * v;
 #pragma unroll
-            for (int t = 0; t < M2; ++t) {
-                w[dim * M2 + t] = (R)horner<NC>(poly + t * NC, 2.0 * u[dim] - 1.0);
-                if (dim < flat) w[dim * M2 + t] = t == m - 1 ? R(1) : R(0);
+            for (int t = 0; t < m; ++t) {
+                const double *c = poly + t * NC;
+                double ev = c[(NC - 1) & ~1], od = c[(NC - 2) | 1];
+#pragma unroll
+                for (int k = ((NC - 1) & ~1) - 2; k >= 0; k -= 2) ev = fma(ev, v2, c[k]);
+#pragma unroll
+                for (int k = ((NC - 2) | 1) - 2; k >= 1; k -= 2) od = fma(od, v2, c[k]);
+                w[dim * M2 + t] = (R)fma(v, od, ev);
+                w[dim * M2 + M2 - 1 - t] = (R)fma(-v, od, ev);
+            }
+            if (dim < flat) {
+#pragma unroll
+                for (int t = 0; t < M2; ++t) w[dim * M2 + t] = t == m - 1 ? R(1) : R(0);
             }
         }
     } else {
