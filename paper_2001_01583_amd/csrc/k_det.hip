@@ -48,8 +48,9 @@ __global__ void k_perm_ipos(const int *__restrict__ perm_local, long long n, lon
 size_t det_sort_bytes(long long n)
 {
     size_t bytes = 0;
-    hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, (const int *)nullptr, (int *)nullptr, (const int *)nullptr,
-                                       (int *)nullptr, (int)n, 0, 31);
+    // (a size query: it launches nothing; on failure the sort itself reports)
+    (void)hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, (const int *)nullptr, (int *)nullptr,
+                                             (const int *)nullptr, (int *)nullptr, (int)n, 0, 31);
     return bytes;
 }
 

@@ -399,8 +399,8 @@ hipError_t launch_fft(int pass, const Xform *dxf, const FItem *items, int nitems
     static int cus = 0;
     if (!cus) {
         int dev = 0;
-        hipGetDevice(&dev);
-        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
             cus = 256;
     }
     // one workgroup per item up to a few rounds of the chip (LDS, 8 x 256

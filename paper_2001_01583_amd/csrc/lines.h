@@ -58,7 +58,6 @@ __global__ __launch_bounds__((LineGroup<R, M2>::threads)) void k_interp_lines(
     constexpr int PLANE = G::PY * PX;
     constexpr int NTH = G::threads;
     constexpr int NPF = (M2 * PLANE + NTH - 1) / NTH;  // ring cells per thread and phase
-    constexpr int OFF_PZ = (int)rec_off_pz(M2, sizeof(R));
     constexpr int Zi = lines_slab(M2);
     extern __shared__ uint4 smem16[];
     R *ring = reinterpret_cast<R *>(smem16);  // [slot][footprint row][column] complex

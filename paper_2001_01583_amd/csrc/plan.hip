@@ -313,9 +313,10 @@ void tune_cache_put(const std::string &key, const Tiling &t)
 void drop_graph(hpnfft_plan_s *p)
 {
     if (!p->gexec && !p->graph) return;
-    hipStreamSynchronize(p->stream);
-    if (p->gexec) hipGraphExecDestroy(p->gexec);
-    if (p->graph) hipGraphDestroy(p->graph);
+    // (teardown: a failure leaves nothing to undo)
+    (void)hipStreamSynchronize(p->stream);
+    if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
     p->gexec = nullptr;
     p->graph = nullptr;
 }
@@ -835,15 +836,14 @@ struct PhaseTimer {
     {
         if (!((p->prof >> phase) & 1u)) return;
         a = take_event(p);
-        if (a) hipEventRecord(a, p->stream);
+        if (a && hipEventRecord(a, p->stream) != hipSuccess) a = nullptr;
     }
     ~PhaseTimer()
     {
         if (!a) return;
         hipEvent_t b = take_event(p);
         if (!b) return;
-        hipEventRecord(b, p->stream);
-        p->recs.push_back({phase, a, b});
+        if (hipEventRecord(b, p->stream) == hipSuccess) p->recs.push_back({phase, a, b});
     }
 };
 
@@ -1197,15 +1197,16 @@ int hpnfft_batch_create(hpnfft_batch *out, int B, const int64_t *N, const int64_
 int hpnfft_plan_destroy(hpnfft_plan p)
 {
     if (!p) return HPNFFT_OK;
-    if (!p->recs.empty()) hipStreamSynchronize(p->stream);
+    // (teardown: a failure leaves nothing to undo)
+    if (!p->recs.empty()) (void)hipStreamSynchronize(p->stream);
     drop_records(p);
-    for (hipEvent_t e : p->pool) hipEventDestroy(e);
+    for (hipEvent_t e : p->pool) (void)hipEventDestroy(e);
     drop_graph(p);
     if (p->res_ev) {
-        hipEventSynchronize(p->res_ev);
-        hipEventDestroy(p->res_ev);
+        (void)hipEventSynchronize(p->res_ev);
+        (void)hipEventDestroy(p->res_ev);
     }
-    if (p->hres) hipHostFree(p->hres);
+    if (p->hres) (void)hipHostFree(p->hres);
     delete p;
     return HPNFFT_OK;
 }
@@ -1431,8 +1432,9 @@ int hpnfft_copy(void *dst, const void *src, size_t bytes, void *stream)
     if ((!dst || !src) && bytes) return HPNFFT_EINVAL;
     if (((uintptr_t)dst | (uintptr_t)src) % 16) return HPNFFT_EINVAL;
     int dev = 0, cus = 256;
-    if (hipGetDevice(&dev) == hipSuccess)
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+        cus = 256;
     return hip_status(launch_copy(dst, src, bytes, cus, (hipStream_t)stream));
 }
 
@@ -1475,7 +1477,7 @@ int hpnfft_batch_capture(hpnfft_batch p, const void *f, void *fhat)
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(p->stream, &g);
     if (rc) {
-        if (g) hipGraphDestroy(g);
+        if (g) (void)hipGraphDestroy(g);
         return rc;
     }
     if (e != hipSuccess) return HPNFFT_EHIP;
@@ -1565,20 +1567,19 @@ int hpnfft_autotune(hpnfft_plan p, void *scratch_f, void *scratch_fhat, int *til
         bool ok = true;
         for (int w = 0; w < 2 && ok; ++w) ok = round();
         if (!ok) continue;
-        hipEventRecord(e0, p->stream);
+        ok = hipEventRecord(e0, p->stream) == hipSuccess;
         for (int r = 0; r < 3 && ok; ++r) ok = round();
-        hipEventRecord(e1, p->stream);
-        hipEventSynchronize(e1);
         float ms = 0;
-        hipEventElapsedTime(&ms, e0, e1);
+        ok = ok && hipEventRecord(e1, p->stream) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+             hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
         hlog("autotune: T=%d Zs=%d threads=%d %.4f ms per round", t.T, t.Zs, t.threads, ok ? ms / 3 : -1.0);
         if (ok && ms < best_t) {
             best_t = ms;
             best = t;
         }
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     int rc = install(best);
     if (rc == HPNFFT_OK) tune_cache_put(key, best);
     if (tile) *tile = best.T;
