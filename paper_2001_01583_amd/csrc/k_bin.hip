@@ -181,7 +181,11 @@ __device__ inline long long scatter_point(long long j, const double *__restrict_
     // values in tap order (the tap index, hence the polynomial, is the same
     // for every thread).  A flat dim (no coordinate, N_t = 1) holds the unit
     // impulse on cell 0, which the point (at 0) reaches with tap m - 1.
-    if (poly && !GRAD) {
+    // Derivative tables from the polynomials too in float32 (the fit's
+    // derivative error, about the degree squared times the fit tolerance of
+    // 1e-9, stays far below float32 rounding); float64 evaluates them.
+    constexpr bool POLY_D = sizeof(R) == 4;
+    if (poly && (!GRAD || POLY_D)) {
         // the fitted polynomials: a short body, unrolled, so that w stays in
         // registers.  The window is even, so tap 2m - 1 - t at v is tap t at
         // -v: both come from the even and odd parts of tap t's polynomial.
@@ -198,10 +202,29 @@ __device__ inline long long scatter_point(long long j, const double *__restrict_
                 for (int k = ((NC - 2) | 1) - 2; k >= 1; k -= 2) od = fma(od, v2, c[k]);
                 w[dim * M2 + t] = (R)fma(v, od, ev);
                 w[dim * M2 + M2 - 1 - t] = (R)fma(-v, od, ev);
+                if constexpr (GRAD) {
+                    // P(v) approximates phi(u + m - 1 - t) with v = 2u - 1, so
+                    // phi' there is 2 P'(v).  P'(v) = A(v^2) + v B(v^2): A
+                    // sums k c_k v^(k-1) over odd k, B over even k >= 2.  Tap
+                    // 2m - 1 - t is P(-v), whose phi' is -2 P'(-v).
+                    constexpr int KA = ((NC - 1) & 1) ? NC - 1 : NC - 2;  // top odd k
+                    constexpr int KB = ((NC - 1) & 1) ? NC - 2 : NC - 1;  // top even k
+                    double a = KA * c[KA], b = KB * c[KB];
+#pragma unroll
+                    for (int k = KA - 2; k >= 1; k -= 2) a = fma(a, v2, k * c[k]);
+#pragma unroll
+                    for (int k = KB - 2; k >= 2; k -= 2) b = fma(b, v2, k * c[k]);
+                    const double s = 2.0 * (double)n[dim];
+                    dw[dim * M2 + t] = (R)(s * fma(v, b, a));
+                    dw[dim * M2 + M2 - 1 - t] = (R)(-s * fma(-v, b, a));
+                }
             }
             if (dim < flat) {
 #pragma unroll
-                for (int t = 0; t < M2; ++t) w[dim * M2 + t] = t == m - 1 ? R(1) : R(0);
+                for (int t = 0; t < M2; ++t) {
+                    w[dim * M2 + t] = t == m - 1 ? R(1) : R(0);
+                    if constexpr (GRAD) dw[dim * M2 + t] = R(0);
+                }
             }
         }
     } else {
