@@ -312,13 +312,28 @@ __global__ __launch_bounds__(kBoxThreads) void k_interp_box(const Xform *__restr
                     v[7] = fma(si, d2, v[7]);
                 }
             }
+            if constexpr (GRAD) {
+                // the eight sums through the halving steps of wave_reduce.h
+                // (about 10 lane exchanges per word instead of 48): the
+                // 8-lane group j ends with the sum of value bitrev3(j), which
+                // its first lane adds to the output
+                const R a0 = halve32(v[0], v[1]), a1 = halve32(v[2], v[3]);
+                const R a2 = halve32(v[4], v[5]), a3 = halve32(v[6], v[7]);
+                const R r = halve8_sum(halve16(a0, a1), halve16(a2, a3));
+                if ((lane & 7) == 0) {
+                    const int j = lane >> 3;
+                    const int q = ((j & 1) << 2) | (j & 2) | (j >> 2);
+                    atomicAdd(&outs[pos * (2 * NO) + q], r);
+                }
+            } else {
 #pragma unroll
-            for (int q = 0; q < 2 * NO; ++q) v[q] = wave_sum(v[q]);
-            if (lane < 2 * NO) {
-                R mine = v[0];
+                for (int q = 0; q < 2 * NO; ++q) v[q] = wave_sum(v[q]);
+                if (lane < 2 * NO) {
+                    R mine = v[0];
 #pragma unroll
-                for (int q = 1; q < 2 * NO; ++q) mine = lane == q ? v[q] : mine;
-                atomicAdd(&outs[pos * (2 * NO) + lane], mine);
+                    for (int q = 1; q < 2 * NO; ++q) mine = lane == q ? v[q] : mine;
+                    atomicAdd(&outs[pos * (2 * NO) + lane], mine);
+                }
             }
         }
         __syncthreads();  // the next box overwrites the tile
