@@ -226,13 +226,6 @@ __global__ __launch_bounds__(kBoxThreads) void k_spread_box(const Xform *__restr
 }
 
 // ---------------------------------------------------------------------------
-// Sum over the 64 lanes (butterfly of lane swaps; every lane ends with the sum).
-template <typename R> __device__ inline R wave_sum(R v)
-{
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
 
 template <typename R, bool GRAD>
 __global__ __launch_bounds__(kBoxThreads) void k_interp_box(const Xform *__restrict__ xfs,
@@ -326,14 +319,13 @@ __global__ __launch_bounds__(kBoxThreads) void k_interp_box(const Xform *__restr
                     atomicAdd(&outs[pos * (2 * NO) + q], r);
                 }
             } else {
-#pragma unroll
-                for (int q = 0; q < 2 * NO; ++q) v[q] = wave_sum(v[q]);
-                if (lane < 2 * NO) {
-                    R mine = v[0];
-#pragma unroll
-                    for (int q = 1; q < 2 * NO; ++q) mine = lane == q ? v[q] : mine;
-                    atomicAdd(&outs[pos * (2 * NO) + lane], mine);
-                }
+                // the two sums through the same steps, each value fed in four
+                // times: 8-lane groups 0-3 end with the sum of v[0], groups
+                // 4-7 with that of v[1]
+                const R a = halve32(v[0], v[1]);
+                const R b = halve16(a, a);
+                const R r = halve8_sum(b, b);
+                if ((lane & 31) == 0) atomicAdd(&outs[pos * 2 + (lane >> 5)], r);
             }
         }
         __syncthreads();  // the next box overwrites the tile
